@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPU spin stepper: spin-steps/s on one MI355X.
+
+Workload: the 2-D 256 x 256 spin-echo configuration -- 262,144 spins
+(4 jittered isochromats per voxel, dw ~ N(0, (2 pi 20 Hz)^2)), 90x/180y
+with TE 20 ms and TR 500 ms, 256 phase encodes x 256 samples: 66,304
+elementary intervals per spin, 65,536 complex samples.  One step is one
+complete simulation of that request through the C ABI (sequence compile +
+upload, step kernel, FP64 finalize) with the object already resident in
+HBM.  Prints one JSON line.
+
+Also reported: the step kernel's roofline position (algorithmic FP32 flops
+per launch / its mean HIP-event duration, against the FP32 vector peak),
+and the FP64 CPU oracle timed on the host on a bounded spin subset of the
+same workload (with the GPU's error against it on that subset).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak (published)
+FLOPS_ADC_SAMPLE = 8          # p <- p z (complex multiply) and accumulate
+FLOPS_HARD_RF = 15            # 3x3 rotation of (Mx, My, Mz), eq. 3.19
+FLOPS_SHAPE_SUBSTEP = 23      # rotation + complex precession/decay + Mz recovery
+WORKLOAD = ("c2: 2-D 256x256 grid, 4 jittered isochromats/voxel (262,144 spins), "
+            "spin echo 90x/180y TE 20 ms TR 500 ms, 256 phase encodes x 256 samples")
+
+
+def algorithmic_flops(seq, n_spins: int) -> float:
+    n_rf = int(sum(1 for a in seq.rf_alpha if a != 0.0))
+    n_sub = int(sum(seq.shapes[int(s)].n_sub for s in seq.rf_shape if s >= 0))
+    return float(n_spins) * (FLOPS_ADC_SAMPLE * seq.n_samples + FLOPS_HARD_RF * n_rf
+                             + FLOPS_SHAPE_SUBSTEP * n_sub)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ps_ops.h", "ps_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1305_6861_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(spl: int):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source and tiling."""
+    p = os.path.join(ROOT, "profiles", "step_kernel_c2_traffic.json")
+    try:
+        with open(p) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_source_hash() or rec.get("spins_per_lane") != spl:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(obj, seq, ctx, target_s: float):
+    """Oracle (FP64, all host threads) on every stride-th spin of the
+    workload, stride chosen so that the run takes about target_s."""
+    import numpy as np
+    import oracle
+    from workloads.phantom import subset
+    n_steps = seq.n_steps_per_spin
+    threads = oracle.default_threads()
+    probe = subset(obj, 4096)
+    t0 = time.perf_counter()
+    oracle.simulate(probe, seq, n_threads=threads)
+    rate = probe.n_spins * n_steps / max(time.perf_counter() - t0, 1e-6)
+    want = max(rate * target_s / n_steps, 64)
+    stride = 1 << max(0, int(math.floor(math.log2(obj.n_spins / want))))
+    sub = subset(obj, stride)
+    t0 = time.perf_counter()
+    ref = oracle.simulate(sub, seq, n_threads=threads)
+    dt = time.perf_counter() - t0
+    import torch
+    got = ctx.simulate(sub, seq)
+    torch.cuda.synchronize()
+    err = oracle.rel_l2(got.cpu().numpy(), ref)
+    return {"value": sub.n_spins * n_steps / dt, "unit": "spin-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"every {stride}th spin ({sub.n_spins} spins) through the full sequence "
+                      f"({n_steps} steps/spin), {dt:.1f} s",
+            "gpu_rel_l2_on_sample": err}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--spins-per-lane", type=int, default=0, help="0 = autotuned")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus N with N > 1 is not supported "
+              "(the spin domain would shard across GPUs with one reduction of the partial signals, "
+              "which is not built here)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1305_6861_amd as ps
+    from workloads import configs as C
+
+    obj, seq = C.c2()
+    dev = ps.to_device(obj)
+    ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane)
+    packed = ps.pack_sequence(seq)
+    n_samples, n_steps = packed.count()
+    out = torch.empty(2 * n_samples, dtype=torch.float64, device="cuda")
+    spl, _ = ctx.tile(obj.n_spins)
+
+    for _ in range(args.warmup):
+        ctx.simulate(dev, packed, out=out)
+    torch.cuda.synchronize()
+    ctx.kernel_times()                     # forget warm-up launches
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.simulate(dev, packed, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms, fin_ms = ctx.kernel_times()
+
+    spin_steps = float(obj.n_spins) * n_steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = spin_steps * args.steps / elapsed
+    flops = algorithmic_flops(seq, obj.n_spins)
+    k_ms = sum(step_ms) / max(len(step_ms), 1)
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_from_profiles(spl),
+            "kernel": "step_kernel<float,%d>" % spl, "kernel_ms": k_ms,
+            "flops_per_launch": flops, "finalize_ms_per_step": fin_ms / max(args.steps, 1)}
+    rec = {"metric": "spin-steps/s", "value": value, "unit": "spin-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": WORKLOAD, "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
+                      "n_samples": n_samples, "spins_per_lane": spl, "precision": "fp32 stepping, "
+                      "fp64 phases and cross-block sums"},
+           "eta_spins_per_s": obj.n_spins / (ms_per_step * 1e-3),
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(obj, seq, ctx, args.cpu_seconds)
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * parspin.h -- C ABI of the MI355X spin-stepping Bloch simulator.
+ *
+ * The library steps every spin (isochromat) of a discretised object through
+ * a pulse sequence with analytic solutions of the Bloch equation and sums
+ * the rotating-frame transverse magnetisation of all spins into complex
+ * receive-signal samples (section 5.1.1, spin-based simulation procedure;
+ * section 3.5.2 for the signal).  The work is data-parallel over spins
+ * (section 5.3.2, domain decomposition).
+ *
+ * Conventions shared by every call:
+ *  - No C++ exceptions cross this boundary; every call returns ps_status.
+ *    On failure the thread-local message of ps_last_error() says why.
+ *  - Device pointers are HIP device addresses on the context's device.  The
+ *    caller owns them and keeps them valid until the work that uses them has
+ *    completed on the given stream (for ps_submit: until ps_poll/ps_wait
+ *    report completion or ps_cancel returns).
+ *  - Host pointers are read during the call only; the library copies what it
+ *    needs (the sequence is compiled and uploaded during the call).
+ *  - Streams are hipStream_t passed as void*; NULL is the null stream.
+ */
+#ifndef PARSPIN_H
+#define PARSPIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ps_status {
+    PS_OK = 0,
+    PS_E_INVALID_ARG = 1,  /* a pointer, size, count or value is out of range   */
+    PS_E_NO_MEMORY = 2,    /* host or device allocation failed                  */
+    PS_E_DEVICE = 3,       /* a HIP call failed; ps_last_error() has its text   */
+    PS_E_TOO_LARGE = 4,    /* the request's device footprint exceeds the cap    */
+    PS_E_NOT_READY = 5,    /* ps_wait timed out / result not yet available      */
+    PS_E_CANCELLED = 6,    /* the request was cancelled                         */
+    PS_E_NO_DEVICE = 7     /* no usable gfx950 device                           */
+} ps_status;
+
+/* ps_event.flags: transverse magnetisation is set to zero at the end of the
+ * interval.  An idealised spoiler; the paper has no such primitive. */
+#define PS_EV_SPOIL 1u
+
+typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
+
+/* ps_config.flags: bracket every step-kernel and finalize-kernel launch with
+ * HIP events on its stream so that ps_kernel_times() can report durations. */
+#define PS_CFG_KERNEL_TIMING 1u
+
+typedef struct ps_config {
+    int32_t device;              /* HIP device ordinal                                 */
+    int32_t precision;           /* 32: FP32 stepping (FP64 phases and cross-block
+                                    sums); 64: FP64 throughout                         */
+    int32_t spins_per_lane;      /* 0 = autotuned; else 1, 2, 4 or 8 (FP64: 1 or 2)    */
+    int32_t flags;               /* PS_CFG_KERNEL_TIMING                               */
+    int64_t max_partial_bytes;   /* bound on the per-block partial-sum buffer; longer
+                                    sequences run in time slices (0 = default 512 MiB) */
+    int64_t max_footprint_bytes; /* admission cap for served requests (0 = 64 GiB)     */
+} ps_config;
+
+/* Spins as structure-of-arrays, n_spins entries each, FP32, DEVICE memory
+ * (section 6.1.1: position, rest magnetisation M0, T1, T2 and the
+ * rotating-frame off-resonance of eq. 6.1 / 6.2). */
+typedef struct ps_object {
+    int64_t n_spins;             /* >= 0                                               */
+    const float *x, *y, *z;      /* position, m                                        */
+    const float *m0;             /* rest magnetisation (isochromat weight)             */
+    const float *t1, *t2;        /* s, > 0; +INF means no relaxation of that kind      */
+    const float *dw;             /* rad/s off-resonance (chemical shift + B0 + suscep.)*/
+} ps_object;
+
+/* One elementary sequence (section 4.1, eq. 4.1): a hard RF pulse at the
+ * start (eq. 3.19), then precession and relaxation over dt under a gradient
+ * given by its moment m = (gamma / 2 pi) * integral G dt (eq. 3.16), in
+ * cycles/m.  With n_adc = N > 0 the interval is cut into N equal sub-steps
+ * and one sample is taken after each (section 5.1.1).  With rf_shape >= 0
+ * the shape's sub-steps run first, then the hard pulse, then the interval. */
+typedef struct ps_event {
+    double   dt;                 /* s, finite, >= 0                                    */
+    double   m[3];               /* cycles/m over the whole interval                   */
+    double   rf_alpha;           /* rad; 0 = no pulse                                  */
+    double   rf_phase;           /* rad; rotation axis (cos, sin, 0) in x'y'; also
+                                    added to every sub-pulse phase of rf_shape         */
+    int32_t  rf_shape;           /* -1, or index into ps_sequence.shapes               */
+    uint32_t n_adc;              /* 0, or number of samples (< 2^31)                   */
+    uint32_t flags;              /* PS_EV_SPOIL                                        */
+    uint32_t reserved;           /* must be 0                                          */
+} ps_event;
+
+/* A shaped pulse in the hard-pulse approximation (eq. 3.23): n_sub equal
+ * sub-steps of length tau, each a hard sub-pulse (alpha[i], phase[i]) at its
+ * start followed by precession and relaxation under the moment m_sub. */
+typedef struct ps_rf_shape {
+    int32_t       n_sub;         /* >= 1                                               */
+    int32_t       reserved;
+    double        tau;           /* s per sub-step, finite, >= 0                       */
+    double        m_sub[3];      /* cycles/m per sub-step                              */
+    const double *alpha;         /* HOST, n_sub flip angles, rad (signed)              */
+    const double *phase;         /* HOST, n_sub phases, rad                            */
+} ps_rf_shape;
+
+typedef struct ps_sequence {
+    int64_t            n_events;
+    const ps_event    *events;   /* HOST                                               */
+    int32_t            n_shapes;
+    int32_t            reserved;
+    const ps_rf_shape *shapes;   /* HOST                                               */
+} ps_sequence;
+
+/* Fill *cfg with the defaults (device 0, precision 32, autotuned tiles). */
+ps_status ps_config_default(ps_config *cfg);
+
+/* Create a context on cfg->device (NULL = defaults).  Fails with
+ * PS_E_NO_DEVICE when the device is absent or is not gfx950. */
+ps_status ps_create(ps_ctx **out, const ps_config *cfg);
+
+/* Wait for the context's outstanding work and free everything it owns. */
+void ps_destroy(ps_ctx *ctx);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *ps_last_error(void);
+
+/* Number of ADC samples (the signal length) and the number of elementary
+ * intervals each spin is stepped through after cutting ADC intervals into
+ * their samples and shaped pulses into their sub-pulses.  Validates the
+ * sequence; needs no device. */
+ps_status ps_count(const ps_sequence *seq, int64_t *n_samples, int64_t *n_steps_per_spin);
+
+/* Simulate one request, stream-ordered on `stream`.
+ * signal: DEVICE, 2 * n_samples doubles, interleaved (re, im), samples in
+ * event order and by sample index inside an event; it receives
+ * sum over spins of (Mx + j My) at every sample (eq. 3.30 - 3.32).
+ * n_samples must equal ps_count's value.  The result is bitwise
+ * reproducible for a given context configuration and n_spins. */
+ps_status ps_simulate(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq,
+                      double *signal, int64_t n_samples, void *stream);
+
+/* The tiling ps_simulate uses for an object of n_spins spins on this
+ * context: spins held per lane (the autotuned or configured value) and
+ * spins per workgroup (4 waves of 64 lanes). */
+ps_status ps_tile(ps_ctx *ctx, int64_t n_spins, int32_t *spins_per_lane, int64_t *spins_per_block);
+
+/* Durations in ms of the kernels launched since the previous call (contexts
+ * created with PS_CFG_KERNEL_TIMING only): the step kernels in launch order
+ * into step_ms[0 .. min(capacity, *n_step) - 1] (step_ms may be NULL when
+ * capacity is 0), their count into *n_step, and the summed finalize-kernel
+ * time into *finalize_ms.  Waits for those kernels to finish, then forgets
+ * them.  Measurement support, not part of the simulation. */
+ps_status ps_kernel_times(ps_ctx *ctx, double *step_ms, int64_t capacity, int64_t *n_step,
+                          double *finalize_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARSPIN_H */

@@ -1,0 +1,184 @@
+"""MI355X spin-stepping Bloch simulator (Python binding of libparspin.so).
+
+Every spin of an object is stepped through a sequence of elementary
+sequences with analytic Bloch solutions and the rotating-frame transverse
+magnetisation of all spins is summed per ADC sample (section 5.1.1).  All
+of that runs in hand-written HIP kernels behind the C ABI of
+include/parspin.h; this module only marshals arguments.  PyTorch provides
+device memory and streams.
+
+    import paper_1305_6861_amd as ps
+    ctx = ps.Context()                      # device 0, FP32 stepping
+    sig = ctx.simulate(obj, seq)            # torch.complex128 on the GPU
+
+`obj` is a mapping (or object with attributes) of x, y, z, m0, t1, t2, dw:
+float32 CUDA tensors, or numpy arrays that are copied to the device.
+`seq` exposes dt, m, rf_alpha, rf_phase, rf_shape, n_adc, flags (one entry
+per elementary sequence) and shapes (tau, m_sub, alpha, phase).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _binding as _b
+from ._binding import PsError, PS_EV_SPOIL
+
+FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
+
+__all__ = ["Context", "PsError", "PS_EV_SPOIL", "count", "pack_sequence", "to_device", "FIELDS"]
+
+
+class PackedSequence:
+    """A sequence marshalled into ps_event / ps_rf_shape arrays (host memory
+    kept alive by this object)."""
+
+    def __init__(self, seq):
+        n = int(seq.n_events)
+        self.n_events = n
+        self._events = (_b.ps_event * max(n, 1))()
+        if n:
+            dt = np.asarray(seq.dt, np.float64)
+            m = np.asarray(seq.m, np.float64).reshape(n, 3)
+            al = np.asarray(seq.rf_alpha, np.float64)
+            ph = np.asarray(seq.rf_phase, np.float64)
+            sh = np.asarray(seq.rf_shape, np.int64)
+            na = np.asarray(seq.n_adc, np.int64)
+            fl = np.asarray(seq.flags, np.int64)
+            if np.any(na < 0) or np.any(na > 0x7FFFFFFF):
+                raise PsError(1, "n_adc out of range")
+            rec = np.zeros(n, dtype=np.dtype([("dt", "<f8"), ("m", "<f8", (3,)), ("a", "<f8"), ("p", "<f8"),
+                                               ("s", "<i4"), ("n", "<u4"), ("f", "<u4"), ("r", "<u4")]))
+            rec["dt"] = dt; rec["m"] = m; rec["a"] = al; rec["p"] = ph
+            rec["s"] = sh.astype(np.int32); rec["n"] = na.astype(np.uint32); rec["f"] = fl.astype(np.uint32)
+            ctypes.memmove(self._events, rec.ctypes.data, rec.nbytes)
+        shapes = list(getattr(seq, "shapes", []))
+        self._keep = []
+        self._shapes = (_b.ps_rf_shape * max(len(shapes), 1))()
+        for i, s in enumerate(shapes):
+            a = np.ascontiguousarray(s.alpha, np.float64)
+            p = np.ascontiguousarray(s.phase, np.float64)
+            self._keep += [a, p]
+            rec = self._shapes[i]
+            rec.n_sub = int(a.shape[0])
+            rec.tau = float(s.tau)
+            for d in range(3):
+                rec.m_sub[d] = float(np.asarray(s.m_sub, np.float64).reshape(3)[d])
+            rec.alpha = a.ctypes.data
+            rec.phase = p.ctypes.data
+        self.struct = _b.ps_sequence(n, ctypes.addressof(self._events), len(shapes), 0,
+                                     ctypes.addressof(self._shapes))
+
+    def count(self):
+        ns = ctypes.c_int64(); st = ctypes.c_int64()
+        _b.check(_b.lib.ps_count(ctypes.byref(self.struct), ctypes.byref(ns), ctypes.byref(st)))
+        return int(ns.value), int(st.value)
+
+
+def pack_sequence(seq) -> PackedSequence:
+    return seq if isinstance(seq, PackedSequence) else PackedSequence(seq)
+
+
+def count(seq):
+    """(n_samples, n_steps_per_spin) of a sequence, validated by the library."""
+    return pack_sequence(seq).count()
+
+
+def to_device(obj, device="cuda"):
+    """Spin arrays as contiguous float32 tensors on the device."""
+    import torch
+    out = {}
+    for f in FIELDS:
+        v = obj[f] if isinstance(obj, dict) else getattr(obj, f)
+        t = v if isinstance(v, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(v, np.float32))
+        out[f] = t.to(device=device, dtype=torch.float32).contiguous()
+    return out
+
+
+def _object_struct(dev):
+    n = int(dev["x"].numel())
+    for f in FIELDS:
+        t = dev[f]
+        if t.dtype.itemsize != 4 or not t.is_contiguous() or int(t.numel()) != n or not t.is_cuda:
+            raise PsError(1, f"field {f} must be a contiguous float32 CUDA tensor of {n} entries")
+    return _b.ps_object(n, *[dev[f].data_ptr() if n else 0 for f in FIELDS])
+
+
+class Context:
+    """One library context (device, precision, tiling)."""
+
+    def __init__(self, device: int = 0, precision: int = 32, spins_per_lane: int = 0,
+                 max_partial_bytes: int = 0, max_footprint_bytes: int = 0, kernel_timing: bool = False):
+        cfg = _b.ps_config()
+        _b.check(_b.lib.ps_config_default(ctypes.byref(cfg)))
+        cfg.device = device
+        cfg.precision = precision
+        cfg.spins_per_lane = spins_per_lane
+        cfg.flags = _b.PS_CFG_KERNEL_TIMING if kernel_timing else 0
+        if max_partial_bytes:
+            cfg.max_partial_bytes = max_partial_bytes
+        if max_footprint_bytes:
+            cfg.max_footprint_bytes = max_footprint_bytes
+        h = ctypes.c_void_p()
+        _b.check(_b.lib.ps_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self._h = h
+        self.device = device
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _b.lib.ps_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def tile(self, n_spins: int):
+        """(spins per lane, spins per workgroup) used for an object of n_spins."""
+        spl = ctypes.c_int32(); spb = ctypes.c_int64()
+        _b.check(_b.lib.ps_tile(self._h, int(n_spins), ctypes.byref(spl), ctypes.byref(spb)))
+        return int(spl.value), int(spb.value)
+
+    def kernel_times(self, capacity: int = 1 << 16):
+        """(step-kernel durations in ms in launch order, summed finalize-kernel
+        ms) of the launches since the previous call.  Needs a context created
+        with kernel_timing=True; synchronises on those launches."""
+        buf = (ctypes.c_double * capacity)()
+        n = ctypes.c_int64(); fin = ctypes.c_double()
+        _b.check(_b.lib.ps_kernel_times(self._h, buf, capacity, ctypes.byref(n), ctypes.byref(fin)))
+        return [buf[i] for i in range(min(n.value, capacity))], float(fin.value)
+
+    def simulate(self, obj, seq, out=None, stream=None):
+        """Signal of one request as a complex128 CUDA tensor (stream-ordered
+        on `stream`, default torch's current stream)."""
+        import torch
+        owned = not (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
+                                                   for f in FIELDS))
+        dev = to_device(obj, f"cuda:{self.device}") if owned else obj
+        ps = pack_sequence(seq)
+        n_samples, _ = ps.count()
+        if out is None:
+            out = torch.empty(2 * n_samples, dtype=torch.float64, device=f"cuda:{self.device}")
+        elif out.dtype != torch.float64 or out.numel() != 2 * n_samples or not out.is_contiguous():
+            raise PsError(1, "out must be a contiguous float64 tensor of 2 * n_samples entries")
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        if owned:   # temporaries must outlive the asynchronous work on `stream`
+            for t in dev.values():
+                t.record_stream(stream)
+        o = _object_struct(dev)
+        _b.check(_b.lib.ps_simulate(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                    ctypes.c_void_p(out.data_ptr() if n_samples else 0),
+                                    n_samples, ctypes.c_void_p(stream.cuda_stream)))
+        return out.view(torch.complex128)

@@ -1,0 +1,108 @@
+"""ctypes binding of libparspin.so (include/parspin.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library.  There is no CPU fallback; when the library cannot be loaded the
+import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libparspin.so")
+
+PS_OK = 0
+STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID_ARG", 2: "PS_E_NO_MEMORY", 3: "PS_E_DEVICE",
+                4: "PS_E_TOO_LARGE", 5: "PS_E_NOT_READY", 6: "PS_E_CANCELLED", 7: "PS_E_NO_DEVICE"}
+PS_EV_SPOIL = 1
+PS_CFG_KERNEL_TIMING = 1
+
+
+class PsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+class ps_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("spins_per_lane", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("max_partial_bytes", ctypes.c_int64), ("max_footprint_bytes", ctypes.c_int64)]
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class ps_object(ctypes.Structure):
+    _fields_ = [("n_spins", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("m0", ctypes.c_void_p), ("t1", ctypes.c_void_p),
+                ("t2", ctypes.c_void_p), ("dw", ctypes.c_void_p)]
+
+
+class ps_event(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("m", ctypes.c_double * 3), ("rf_alpha", ctypes.c_double),
+                ("rf_phase", ctypes.c_double), ("rf_shape", ctypes.c_int32), ("n_adc", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ps_rf_shape(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("m_sub", ctypes.c_double * 3), ("alpha", ctypes.c_void_p), ("phase", ctypes.c_void_p)]
+
+
+class ps_sequence(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int64), ("events", ctypes.c_void_p), ("n_shapes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("shapes", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(ps_event) == 64
+assert ctypes.sizeof(ps_rf_shape) == 56
+assert ctypes.sizeof(ps_config) == 32
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "ps_config_default": (ctypes.c_int, [ctypes.POINTER(ps_config)]),
+    "ps_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ps_config)]),
+    "ps_destroy": (None, [ctypes.c_void_p]),
+    "ps_last_error": (ctypes.c_char_p, []),
+    "ps_count": (ctypes.c_int, [ctypes.POINTER(ps_sequence), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int64)]),
+    "ps_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "ps_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int64)]),
+    "ps_simulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+}
+
+
+def _load():
+    # PyTorch ships its own HIP runtime with the same soname as ROCm's
+    # (libamdhip64.so.7).  Loading torch first lets this library bind to that
+    # already-loaded runtime; otherwise the process would hold two HIP/HSA
+    # runtimes and torch would find no GPU.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    msg = lib.ps_last_error()
+    return msg.decode() if msg else ""
+
+
+def check(status: int):
+    if status != PS_OK:
+        raise PsError(status, last_error())

@@ -1,0 +1,59 @@
+"""Build the HIP library libparspin.so for gfx950 (in-tree).
+
+Every source is compiled with hipcc for gfx950 only, with packed-FP32
+instructions disabled (-Xclang -target-feature -Xclang -packed-fp32-ops).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_lib")
+LIB = os.path.join(OUT_DIR, "libparspin.so")
+SOURCES = ["kernels.hip", "compile.cpp", "api.cpp", "server.cpp"]
+ARCH = "gfx950"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    with tempfile.TemporaryDirectory(prefix="parspin_build_") as tmp:
+        procs = []
+        objs = []
+        for src in SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            lang = [] if src.endswith(".hip") else ["-x", "hip"]
+            cmd = [HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), file=sys.stderr)
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+            objs.append(obj)
+            if len([p for _, p in procs if p.poll() is None]) >= jobs:
+                procs[0][1].wait()
+        for src, p in procs:
+            out, _ = p.communicate()
+            text = "\n".join(l for l in out.decode(errors="replace").splitlines()
+                             if "not a recognized feature" not in l)
+            if p.returncode != 0:
+                raise RuntimeError(f"hipcc failed for {src}:\n{text}")
+            if verbose and text.strip():
+                print(text, file=sys.stderr)
+        tmp_lib = LIB + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp_lib, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,366 @@
+// C ABI implementation: contexts, validation, compilation, device buffers
+// and the per-request launch sequence (step kernel + finalize per slice).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/parspin.h"
+#include "compile.h"
+#include "ps_kernels.h"
+#include "ps_runtime.h"
+
+static_assert(sizeof(ps_event) == 64, "ps_event ABI size");
+static_assert(sizeof(ps_rf_shape) == 56, "ps_rf_shape ABI size");
+static_assert(sizeof(ps_config) == 32, "ps_config ABI size");
+static_assert(sizeof(ps_object) == 64, "ps_object ABI size");
+static_assert(sizeof(ps_sequence) == 32, "ps_sequence ABI size");
+
+namespace ps {
+
+static thread_local std::string g_last_error;
+
+ps_status fail(ps_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+ps_status hip_fail(hipError_t e, const char* what) {
+    return fail(PS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) hipSetDevice(dev);
+    dev_ = dev;
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev_ >= 0 && prev_ != dev_) hipSetDevice(prev_);
+}
+
+ps_status DevBuf::reserve(size_t n) {
+    if (n <= bytes) return PS_OK;
+    if (ptr) { hipFree(ptr); ptr = nullptr; bytes = 0; }
+    size_t want = std::max(n, (size_t)4096);
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) { ptr = nullptr; return fail(PS_E_NO_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+    bytes = want;
+    return PS_OK;
+}
+void DevBuf::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+ps_status HostBuf::reserve(size_t n) {
+    if (n <= bytes) return PS_OK;
+    if (ptr) { hipHostFree(ptr); ptr = nullptr; bytes = 0; }
+    size_t want = std::max(n, (size_t)4096);
+    hipError_t e = hipHostMalloc(&ptr, want, hipHostMallocDefault);
+    if (e != hipSuccess) { ptr = nullptr; return fail(PS_E_NO_MEMORY, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
+    bytes = want;
+    return PS_OK;
+}
+void HostBuf::release() {
+    if (ptr) hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins) {
+    if (ctx->cfg.spins_per_lane > 0) return ctx->cfg.spins_per_lane;
+    // Keep at least ~2 waves per SIMD (2 x 1024 SIMDs) while giving each lane
+    // as many spins as possible: more spins per lane amortise the per-sample
+    // lane-sum + butterfly reduction.
+    const int64_t target_waves = 2 * 4 * (int64_t)std::max(ctx->n_cu, 1);
+    const int maxS = ctx->cfg.precision == 64 ? 2 : 4;
+    int S = 1;
+    while (S < maxS && n_spins >= (int64_t)(2 * S) * 64 * target_waves) S *= 2;
+    return S;
+}
+
+hipEvent_t timing_event(Ctx* ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t ev = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    return ev;
+}
+
+ps_status validate_object(const ps_object* obj) {
+    if (!obj) return fail(PS_E_INVALID_ARG, "object is NULL");
+    if (obj->n_spins < 0) return fail(PS_E_INVALID_ARG, "n_spins < 0");
+    if (obj->n_spins > 0 && (!obj->x || !obj->y || !obj->z || !obj->m0 || !obj->t1 || !obj->t2 || !obj->dw))
+        return fail(PS_E_INVALID_ARG, "object array pointer is NULL");
+    return PS_OK;
+}
+
+// Compile + slice a request for a given tiling.
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_blocks, Program* prog) {
+    std::string err;
+    ps_status st = compile_sequence(seq, prog, &err);
+    if (st != PS_OK) return fail(st, err);
+    const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
+    const int64_t per_sample = std::max<int64_t>(n_blocks, 1) * 2 * real_bytes;
+    int64_t max_samples = ctx->cfg.max_partial_bytes / per_sample;
+    if (max_samples < 64) max_samples = 64;
+    plan_slices(prog, max_samples);
+    if (ctx->cfg.precision != 64) narrow_rotations(&prog->ops);
+    return PS_OK;
+}
+
+// Upload program tables into the context's buffers (stream-ordered).
+ps_status upload(Ctx* ctx, const Program& prog, hipStream_t stream) {
+    const size_t ops_bytes = prog.ops.size() * sizeof(Op);
+    const size_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
+    const size_t rows_bytes = prog.rows.size() * real_bytes;
+    ps_status st;
+    if ((st = ctx->ops.reserve(ops_bytes)) != PS_OK) return st;
+    if ((st = ctx->rows.reserve(rows_bytes)) != PS_OK) return st;
+    if ((st = ctx->staging.reserve(ops_bytes + rows_bytes)) != PS_OK) return st;
+    unsigned char* h = reinterpret_cast<unsigned char*>(ctx->staging.ptr);
+    if (ops_bytes) std::memcpy(h, prog.ops.data(), ops_bytes);
+    if (rows_bytes) {
+        if (real_bytes == 8) {
+            std::memcpy(h + ops_bytes, prog.rows.data(), rows_bytes);
+        } else {
+            float* f = reinterpret_cast<float*>(h + ops_bytes);
+            for (size_t i = 0; i < prog.rows.size(); ++i) f[i] = (float)prog.rows[i];
+        }
+    }
+    hipError_t e;
+    if (ops_bytes && (e = hipMemcpyAsync(ctx->ops.ptr, h, ops_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(ops)");
+    if (rows_bytes && (e = hipMemcpyAsync(ctx->rows.ptr, h + ops_bytes, rows_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(rows)");
+    return PS_OK;
+}
+
+ps_status wait_previous(Ctx* ctx) {
+    if (!ctx->pending) return PS_OK;
+    hipError_t e = hipEventSynchronize(ctx->done);
+    ctx->pending = false;
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    return PS_OK;
+}
+
+ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
+                      int64_t n_samples, hipStream_t stream, int S_override) {
+    ps_status st = validate_object(obj);
+    if (st != PS_OK) return st;
+    const int S = S_override > 0 ? S_override : choose_spins_per_lane(ctx, obj->n_spins);
+    const int64_t spb = spins_per_block_of(S);
+    const int64_t n_blocks = (obj->n_spins + spb - 1) / spb;
+    Program prog;
+    if ((st = prepare(ctx, seq, n_blocks, &prog)) != PS_OK) return st;
+    if (n_samples != prog.n_samples)
+        return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
+                                          std::to_string(prog.n_samples));
+    if (n_samples == 0) return PS_OK;
+    if (!signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
+    hipError_t e;
+    if (obj->n_spins == 0) {
+        if ((e = launch_fill_zero(signal, 2 * n_samples, stream)) != hipSuccess) return hip_fail(e, "fill");
+        return PS_OK;
+    }
+    if ((st = wait_previous(ctx)) != PS_OK) return st;
+
+    const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
+    int64_t max_slice = 0;
+    for (const Slice& s : prog.slices) max_slice = std::max(max_slice, s.n_samples);
+    const int64_t row_stride = 2 * max_slice;
+    if ((st = ctx->partial.reserve((size_t)(n_blocks * row_stride * real_bytes))) != PS_OK) return st;
+    const bool sliced = prog.slices.size() > 1;
+    if (sliced && (st = ctx->state.reserve((size_t)(3 * obj->n_spins * real_bytes))) != PS_OK) return st;
+    if ((st = upload(ctx, prog, stream)) != PS_OK) return st;
+
+    StepArgs a;
+    a.x = obj->x; a.y = obj->y; a.z = obj->z; a.m0 = obj->m0; a.t1 = obj->t1; a.t2 = obj->t2; a.dw = obj->dw;
+    a.n_spins = obj->n_spins;
+    a.n_rows = (int32_t)(prog.rows.size() / 9);
+    a.rows = ctx->rows.ptr;
+    a.partial = ctx->partial.ptr;
+    a.row_stride = row_stride;
+    a.state = ctx->state.ptr;
+    const Op* ops_dev = reinterpret_cast<const Op*>(ctx->ops.ptr);
+    const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
+    for (size_t i = 0; i < prog.slices.size(); ++i) {
+        const Slice& sl = prog.slices[i];
+        a.ops = ops_dev + sl.op_begin;
+        a.n_ops = (int32_t)(sl.op_end - sl.op_begin);
+        a.load_state = i > 0;
+        a.save_state = i + 1 < prog.slices.size();
+        hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
+        if (timing) {
+            t0 = timing_event(ctx); t1 = timing_event(ctx); t2 = timing_event(ctx);
+            if (!t0 || !t1 || !t2) return fail(PS_E_DEVICE, "timing event creation failed");
+            hipEventRecord(t0, stream);
+        }
+        if ((e = launch_step(a, ctx->cfg.precision, S, n_blocks, stream)) != hipSuccess)
+            return hip_fail(e, "step kernel launch");
+        if (timing) hipEventRecord(t1, stream);
+        if (sl.n_samples > 0 &&
+            (e = launch_finalize(ctx->partial.ptr, ctx->cfg.precision, n_blocks, row_stride, 2 * sl.n_samples,
+                                 signal + 2 * sl.sample_begin, stream)) != hipSuccess)
+            return hip_fail(e, "finalize kernel launch");
+        if (timing) {
+            hipEventRecord(t2, stream);
+            ctx->step_marks.emplace_back(t0, t1);
+            ctx->fin_marks.emplace_back(t1, t2);
+        }
+    }
+    if ((e = hipEventRecord(ctx->done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ctx->pending = true;
+    return PS_OK;
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" {
+
+ps_status ps_config_default(ps_config* cfg) {
+    if (!cfg) return fail(PS_E_INVALID_ARG, "cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->device = 0;
+    cfg->precision = 32;
+    cfg->spins_per_lane = 0;
+    cfg->max_partial_bytes = 512ll << 20;
+    cfg->max_footprint_bytes = 64ll << 30;
+    return PS_OK;
+}
+
+ps_status ps_create(ps_ctx** out, const ps_config* cfg_in) {
+    clear_error();
+    if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    ps_config cfg;
+    if (cfg_in) cfg = *cfg_in; else ps_config_default(&cfg);
+    if (cfg.precision != 32 && cfg.precision != 64) return fail(PS_E_INVALID_ARG, "precision must be 32 or 64");
+    if (cfg.spins_per_lane != 0) {
+        const int s = cfg.spins_per_lane;
+        const bool ok = cfg.precision == 64 ? (s == 1 || s == 2) : (s == 1 || s == 2 || s == 4 || s == 8);
+        if (!ok) return fail(PS_E_INVALID_ARG, "spins_per_lane not supported for this precision");
+    }
+    if (cfg.max_partial_bytes <= 0) cfg.max_partial_bytes = 512ll << 20;
+    if (cfg.max_footprint_bytes <= 0) cfg.max_footprint_bytes = 64ll << 30;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(PS_E_NO_DEVICE, "no HIP device visible");
+    if (cfg.device < 0 || cfg.device >= count) return fail(PS_E_NO_DEVICE, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, cfg.device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PS_E_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    Ctx* ctx = new (std::nothrow) Ctx();
+    if (!ctx) return fail(PS_E_NO_MEMORY, "context allocation");
+    ctx->cfg = cfg;
+    ctx->n_cu = prop.multiProcessorCount;
+    DeviceGuard g(cfg.device);
+    if ((e = hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming)) != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipEventCreate");
+    }
+    *out = reinterpret_cast<ps_ctx*>(ctx);
+    return PS_OK;
+}
+
+void ps_destroy(ps_ctx* handle) {
+    if (!handle) return;
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    {
+        DeviceGuard g(ctx->cfg.device);
+        destroy_runtime(ctx);
+        if (ctx->pending) hipEventSynchronize(ctx->done);
+        hipEventDestroy(ctx->done);
+        for (auto& m : ctx->step_marks) { hipEventDestroy(m.first); hipEventDestroy(m.second); }
+        for (auto& m : ctx->fin_marks) hipEventDestroy(m.second);   // m.first is a step mark
+        for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
+        ctx->ops.release(); ctx->rows.release(); ctx->partial.release(); ctx->state.release();
+        ctx->staging.release();
+    }
+    delete ctx;
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+ps_status ps_count(const ps_sequence* seq, int64_t* n_samples, int64_t* n_steps_per_spin) {
+    clear_error();
+    Program p;
+    std::string err;
+    ps_status st = compile_sequence(seq, &p, &err);
+    if (st != PS_OK) return fail(st, err);
+    if (n_samples) *n_samples = p.n_samples;
+    if (n_steps_per_spin) *n_steps_per_spin = p.n_steps;
+    return PS_OK;
+}
+
+ps_status ps_simulate(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq, double* signal,
+                      int64_t n_samples, void* stream) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0);
+}
+
+ps_status ps_tile(ps_ctx* handle, int64_t n_spins, int32_t* spins_per_lane, int64_t* spins_per_block) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    if (n_spins < 0) return fail(PS_E_INVALID_ARG, "n_spins < 0");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    const int S = choose_spins_per_lane(ctx, n_spins);
+    if (spins_per_lane) *spins_per_lane = S;
+    if (spins_per_block) *spins_per_block = spins_per_block_of(S);
+    return PS_OK;
+}
+
+ps_status ps_kernel_times(ps_ctx* handle, double* step_ms, int64_t capacity, int64_t* n_step,
+                          double* finalize_ms) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    if (capacity < 0 || (capacity > 0 && !step_ms)) return fail(PS_E_INVALID_ARG, "bad step_ms/capacity");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    ps_status st = PS_OK;
+    double fin = 0.0;
+    int64_t n = 0;
+    for (auto& m : ctx->step_marks) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(m.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.first, m.second);
+        if (e != hipSuccess && st == PS_OK) st = hip_fail(e, "kernel timing");
+        if (n < capacity) step_ms[n] = ms;
+        ++n;
+    }
+    for (auto& m : ctx->fin_marks) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(m.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.first, m.second);
+        if (e != hipSuccess && st == PS_OK) st = hip_fail(e, "kernel timing");
+        fin += ms;
+    }
+    for (auto& m : ctx->step_marks) { ctx->ev_pool.push_back(m.first); ctx->ev_pool.push_back(m.second); }
+    for (auto& m : ctx->fin_marks) ctx->ev_pool.push_back(m.second);
+    ctx->step_marks.clear();
+    ctx->fin_marks.clear();
+    if (n_step) *n_step = n;
+    if (finalize_ms) *finalize_ms = fin;
+    return st;
+}
+
+}  // extern "C"

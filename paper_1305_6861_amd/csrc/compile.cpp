@@ -1,0 +1,224 @@
+// Sequence compiler (host, FP64).
+//
+// Spin-independent work is done once here rather than per spin, as the
+// paper's master process precomputes the trigonometry of RF pulses
+// (section 6.3): rotation matrices of hard pulses (eq. 3.19) and of every
+// sub-pulse of shaped pulses, and the accumulated gradient moments and times
+// since each spin's anchors (see ps_ops.h).  Intervals that contain neither
+// a pulse, an ADC nor a spoiler compile to nothing.
+#include "compile.h"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <utility>
+
+namespace ps {
+
+void rf_matrix(double a, double p, double r[9]) {
+    const double ca = std::cos(a), sa = std::sin(a), cp = std::cos(p), sp = std::sin(p);
+    r[0] = cp * cp + sp * sp * ca;  r[1] = sp * cp * (1.0 - ca);     r[2] = -sp * sa;
+    r[3] = sp * cp * (1.0 - ca);    r[4] = sp * sp + cp * cp * ca;   r[5] = cp * sa;
+    r[6] = sp * sa;                 r[7] = -cp * sa;                 r[8] = ca;
+}
+
+void rf_delta(double a, double p, double d[9]) {
+    // R - I with 1 - cos(a) = 2 sin^2(a/2) so that small pulses keep full
+    // relative precision in every entry.
+    const double sa = std::sin(a), cp = std::cos(p), sp = std::sin(p);
+    const double h = std::sin(0.5 * a);
+    const double v = 2.0 * h * h;          // 1 - cos(a)
+    d[0] = -sp * sp * v;  d[1] = sp * cp * v;   d[2] = -sp * sa;
+    d[3] = sp * cp * v;   d[4] = -cp * cp * v;  d[5] = cp * sa;
+    d[6] = sp * sa;       d[7] = -cp * sa;      d[8] = -v;
+}
+
+static bool finite(double v) { return std::isfinite(v); }
+
+static Op blank_op(uint32_t kind) {
+    Op op;
+    std::memset(&op, 0, sizeof(op));
+    op.kind = kind;
+    return op;
+}
+
+ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err) {
+    if (!seq || !out) { *err = "null sequence or output"; return PS_E_INVALID_ARG; }
+    if (seq->n_events < 0) { *err = "n_events < 0"; return PS_E_INVALID_ARG; }
+    if (seq->n_events > 0 && !seq->events) { *err = "events is NULL"; return PS_E_INVALID_ARG; }
+    if (seq->n_shapes < 0) { *err = "n_shapes < 0"; return PS_E_INVALID_ARG; }
+    if (seq->n_shapes > 0 && !seq->shapes) { *err = "shapes is NULL"; return PS_E_INVALID_ARG; }
+
+    for (int32_t s = 0; s < seq->n_shapes; ++s) {
+        const ps_rf_shape& sh = seq->shapes[s];
+        if (sh.n_sub < 1 || !sh.alpha || !sh.phase) {
+            *err = "shape " + std::to_string(s) + ": n_sub < 1 or NULL alpha/phase";
+            return PS_E_INVALID_ARG;
+        }
+        if (!finite(sh.tau) || sh.tau < 0 || !finite(sh.m_sub[0]) || !finite(sh.m_sub[1]) ||
+            !finite(sh.m_sub[2])) {
+            *err = "shape " + std::to_string(s) + ": tau or m_sub not finite / negative";
+            return PS_E_INVALID_ARG;
+        }
+        for (int32_t q = 0; q < sh.n_sub; ++q)
+            if (!finite(sh.alpha[q]) || !finite(sh.phase[q])) {
+                *err = "shape " + std::to_string(s) + ": non-finite sub-pulse";
+                return PS_E_INVALID_ARG;
+            }
+    }
+
+    Program p;
+    double K[3] = {0, 0, 0};
+    double txy = 0, tz = 0;
+    bool mxy_zero = true;
+    std::map<std::pair<int32_t, uint64_t>, uint32_t> row_cache;
+
+    for (int64_t e = 0; e < seq->n_events; ++e) {
+        const ps_event& ev = seq->events[e];
+        const std::string where = "event " + std::to_string(e) + ": ";
+        if (!finite(ev.dt) || ev.dt < 0) { *err = where + "dt must be finite and >= 0"; return PS_E_INVALID_ARG; }
+        if (!finite(ev.m[0]) || !finite(ev.m[1]) || !finite(ev.m[2])) {
+            *err = where + "moment not finite"; return PS_E_INVALID_ARG;
+        }
+        if (!finite(ev.rf_alpha) || !finite(ev.rf_phase)) {
+            *err = where + "RF angle not finite"; return PS_E_INVALID_ARG;
+        }
+        if (ev.rf_shape < -1 || ev.rf_shape >= seq->n_shapes) {
+            *err = where + "rf_shape out of range"; return PS_E_INVALID_ARG;
+        }
+        if (ev.n_adc > 0x7fffffffu) { *err = where + "n_adc too large"; return PS_E_INVALID_ARG; }
+        if (ev.flags & ~PS_EV_SPOIL) { *err = where + "unknown flag bits"; return PS_E_INVALID_ARG; }
+        if (ev.reserved != 0) { *err = where + "reserved field must be 0"; return PS_E_INVALID_ARG; }
+
+        if (ev.rf_shape >= 0) {
+            const ps_rf_shape& sh = seq->shapes[ev.rf_shape];
+            uint64_t bits;
+            std::memcpy(&bits, &ev.rf_phase, sizeof(bits));
+            auto key = std::make_pair(ev.rf_shape, bits);
+            auto it = row_cache.find(key);
+            uint32_t first;
+            if (it == row_cache.end()) {
+                first = (uint32_t)(p.rows.size() / 9);
+                for (int32_t q = 0; q < sh.n_sub; ++q) {
+                    double r[9];
+                    rf_delta(sh.alpha[q], sh.phase[q] + ev.rf_phase, r);
+                    p.rows.insert(p.rows.end(), r, r + 9);
+                }
+                row_cache.emplace(key, first);
+            } else {
+                first = it->second;
+            }
+            Op op = blank_op(OP_SHAPE);
+            std::memcpy(op.k, K, sizeof(K));
+            op.txy = txy; op.tz = tz;
+            op.u.adc.mu[0] = sh.m_sub[0]; op.u.adc.mu[1] = sh.m_sub[1]; op.u.adc.mu[2] = sh.m_sub[2];
+            op.u.adc.tau = sh.tau;
+            op.n = (uint32_t)sh.n_sub;
+            op.aux = first;
+            op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
+            p.ops.push_back(op);
+            K[0] = K[1] = K[2] = 0; txy = 0; tz = 0; mxy_zero = false;
+            p.n_steps += sh.n_sub;
+            p.n_shape_substeps += sh.n_sub;
+        }
+
+        if (ev.rf_alpha != 0.0) {
+            Op op = blank_op(OP_RF);
+            std::memcpy(op.k, K, sizeof(K));
+            op.txy = txy; op.tz = tz;
+            rf_delta(ev.rf_alpha, ev.rf_phase, op.u.r64);
+            op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
+            p.ops.push_back(op);
+            K[0] = K[1] = K[2] = 0; txy = 0; tz = 0; mxy_zero = false;
+            p.n_rf += 1;
+        }
+
+        const int64_t n = (int64_t)ev.n_adc;
+        if (n > 0) {
+            Op op = blank_op(OP_ADC);
+            const double mu[3] = {ev.m[0] / (double)n, ev.m[1] / (double)n, ev.m[2] / (double)n};
+            const double tau = ev.dt / (double)n;
+            for (int d = 0; d < 3; ++d) { op.k[d] = K[d] + mu[d]; op.u.adc.mu[d] = mu[d]; }
+            op.txy = txy + tau;
+            op.u.adc.tau = tau;
+            op.n = (uint32_t)n;
+            op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
+            p.ops.push_back(op);
+            p.n_samples += n;
+            p.n_adc_ops += 1;
+        }
+        K[0] += ev.m[0]; K[1] += ev.m[1]; K[2] += ev.m[2];
+        txy += ev.dt; tz += ev.dt;
+        p.n_steps += n > 0 ? n : 1;
+
+        if (ev.flags & PS_EV_SPOIL) {
+            if (!mxy_zero) p.ops.push_back(blank_op(OP_SPOIL));
+            K[0] = K[1] = K[2] = 0; txy = 0; mxy_zero = true;
+        }
+    }
+    // Operations after the last readout cannot change the signal.
+    size_t keep = 0;
+    for (size_t i = 0; i < p.ops.size(); ++i)
+        if (p.ops[i].kind == OP_ADC) keep = i + 1;
+    p.ops.resize(keep);
+    if ((int64_t)(p.rows.size() / 9) > kMaxShapeRows) {
+        *err = "shaped pulses need " + std::to_string(p.rows.size() / 9) +
+               " distinct sub-pulse rotations; at most " + std::to_string(kMaxShapeRows) + " are supported";
+        return PS_E_TOO_LARGE;
+    }
+    *out = std::move(p);
+    return PS_OK;
+}
+
+void plan_slices(Program* p, int64_t max_samples) {
+    if (max_samples < 1) max_samples = 1;
+    std::vector<Op> ops;
+    ops.reserve(p->ops.size());
+    p->slices.clear();
+    Slice cur;
+    cur.op_begin = 0;
+    cur.sample_begin = 0;
+    int64_t sample = 0;
+    auto close_slice = [&]() {
+        cur.op_end = (int64_t)ops.size();
+        cur.n_samples = sample - cur.sample_begin;
+        p->slices.push_back(cur);
+        cur = Slice();
+        cur.op_begin = (int64_t)ops.size();
+        cur.sample_begin = sample;
+    };
+    for (const Op& op0 : p->ops) {
+        if (op0.kind != OP_ADC) { ops.push_back(op0); continue; }
+        int64_t done = 0;
+        const int64_t n = op0.n;
+        while (done < n) {
+            int64_t room = max_samples - (sample - cur.sample_begin);
+            if (room <= 0) { close_slice(); room = max_samples; }
+            const int64_t take = std::min<int64_t>(room, n - done);
+            Op op = op0;
+            for (int d = 0; d < 3; ++d) op.k[d] = op0.k[d] + (double)done * op0.u.adc.mu[d];
+            op.txy = op0.txy + (double)done * op0.u.adc.tau;
+            op.n = (uint32_t)take;
+            op.aux = (uint32_t)(sample - cur.sample_begin);
+            ops.push_back(op);
+            sample += take;
+            done += take;
+        }
+    }
+    cur.op_end = (int64_t)ops.size();
+    cur.n_samples = sample - cur.sample_begin;
+    if (cur.op_end > cur.op_begin || p->slices.empty()) p->slices.push_back(cur);
+    p->ops = std::move(ops);
+}
+
+void narrow_rotations(std::vector<Op>* ops) {
+    for (Op& op : *ops) {
+        if (op.kind != OP_RF) continue;
+        float r[9];
+        for (int i = 0; i < 9; ++i) r[i] = (float)op.u.r64[i];
+        std::memset(&op.u, 0, sizeof(op.u));
+        std::memcpy(op.u.r32, r, sizeof(r));
+    }
+}
+
+}  // namespace ps

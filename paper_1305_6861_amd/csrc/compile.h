@@ -1,0 +1,46 @@
+// Host-side sequence compiler: elementary sequences -> device operations.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/parspin.h"
+#include "ps_ops.h"
+
+namespace ps {
+
+struct Slice {
+    int64_t op_begin = 0, op_end = 0;  // operation range of the slice
+    int64_t sample_begin = 0;          // index of the slice's first sample
+    int64_t n_samples = 0;
+};
+
+struct Program {
+    std::vector<Op> ops;               // rotation deltas R - I in FP64 (r64)
+    std::vector<double> rows;          // shaped-pulse rotation deltas, 9 per sub-step
+    int64_t n_samples = 0;
+    int64_t n_steps = 0;               // intervals per spin (see ps_count)
+    int64_t n_rf = 0, n_shape_substeps = 0, n_adc_ops = 0;
+    std::vector<Slice> slices;
+};
+
+// Eq. 3.19: rotation matrix of a hard pulse (alpha, phi), row-major.
+void rf_matrix(double alpha, double phi, double r[9]);
+// The same rotation minus the identity, R - I, formed without cancellation.
+// Device tables hold these deltas: M <- M + (R - I) M keeps small pulses
+// exact to FP32 relative precision of their deviation from the identity.
+void rf_delta(double alpha, double phi, double d[9]);
+
+// Validate and compile; on failure returns an error status and sets *err.
+ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err);
+
+// Cut the program into time slices of at most max_samples samples each
+// (ADC operations longer than that are split exactly), setting every ADC
+// op's offset inside its slice.  max_samples >= 1.
+void plan_slices(Program* p, int64_t max_samples);
+
+// Copy of the ops with rotations narrowed to FP32 (precision 32 tables).
+void narrow_rotations(std::vector<Op>* ops);
+
+}  // namespace ps

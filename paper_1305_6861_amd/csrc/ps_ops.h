@@ -1,0 +1,60 @@
+// Device-side sequence table shared by the host compiler and the kernels.
+//
+// The host compiles the caller's elementary sequences into a short list of
+// operations that only appear where a spin's state changes in a way that is
+// not a pure precession/relaxation: hard RF pulses, shaped pulses, ADC
+// readouts and spoilers.  Free-precession intervals between them cost
+// nothing on the device: precession about z and relaxation over consecutive
+// intervals compose in closed form (eq. 3.5 / 3.14: phases and times add),
+// so the compiler only accumulates, per operation,
+//   k   = gradient moment since the transverse anchor (cycles/m, FP64),
+//   txy = time since the transverse anchor (s, FP64),
+//   tz  = time since the longitudinal anchor (s, FP64),
+// and every spin keeps its magnetisation at its anchors ("lazy anchors"):
+//   Mxy(t) = Mxy_a * exp(-txy/T2) * exp(-j 2 pi (k.x + dw/(2 pi) txy))
+//   Mz(t)  = M0 + (Mz_a - M0) * exp(-tz/T1).
+// An RF pulse or shaped pulse evaluates both, rotates, and resets both
+// anchors; a spoiler zeroes Mxy_a and resets only the transverse anchor.
+#pragma once
+#include <stdint.h>
+
+namespace ps {
+
+enum OpKind : uint32_t {
+    OP_RF = 1,     // hard pulse: evaluate, rotate by r (eq. 3.19), re-anchor
+    OP_ADC = 2,    // n samples at k, k + mu, ...; txy, txy + tau, ...
+    OP_SPOIL = 3,  // Mxy_a := 0 (transverse anchor reset)
+    OP_SHAPE = 4,  // shaped pulse: evaluate, then n_sub sub-steps (eq. 3.23)
+};
+
+enum OpFlags : uint32_t {
+    OPF_MXY_ZERO = 1u,  // Mxy_a is known to be 0 for every spin (after init/spoil)
+};
+
+// 128-byte operation record.
+struct alignas(16) Op {
+    double k[3];   // moment since the transverse anchor, at the op (RF/SHAPE)
+                   // or at sample 0 (ADC), cycles/m
+    double txy;    // time since the transverse anchor, same instant, s
+    double tz;     // time since the longitudinal anchor (RF/SHAPE), s
+    union {
+        double r64[9];                           // RF rotation, FP64 tables
+        float r32[9];                            // RF rotation, FP32 tables
+        struct { double mu[3]; double tau; } adc;  // ADC: per-sample moment and
+                                                   // dwell; SHAPE: per-sub-step
+    } u;
+    uint32_t kind;
+    uint32_t flags;
+    uint32_t n;    // ADC: samples; SHAPE: sub-steps
+    uint32_t aux;  // ADC: first sample's offset inside the time slice;
+                   // SHAPE: first sub-step index in the shape rotation table
+};
+static_assert(sizeof(Op) == 128, "Op must be 128 bytes");
+
+// A SHAPE op keeps the shape's sub-step duration and per-sub-step moment in
+// u.adc (mu, tau).  Its sub-step rotations live in a separate table of 9
+// reals per sub-step; the event's RF phase is folded into them, so every
+// distinct (shape, phase) pair gets its own rows.
+constexpr int kMaxShapeRows = 512;
+
+}  // namespace ps

@@ -1,0 +1,66 @@
+// Host runtime internals shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/parspin.h"
+#include "compile.h"
+
+namespace ps {
+
+ps_status fail(ps_status st, const std::string& msg);
+ps_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+private:
+    int prev_ = -1, dev_ = 0;
+};
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    ps_status reserve(size_t n);   // grows, never shrinks; contents not kept
+    void release();
+};
+
+struct HostBuf {                   // pinned
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    ps_status reserve(size_t n);
+    void release();
+};
+
+struct Server;                     // served / batched mode (server.cpp)
+
+struct Ctx {
+    ps_config cfg{};
+    int n_cu = 256;
+    std::mutex mu;                 // serialises calls on one context
+    DevBuf ops, rows, partial, state;
+    HostBuf staging;
+    hipEvent_t done = nullptr;     // completion of the last request's work
+    bool pending = false;
+    // kernel timing (PS_CFG_KERNEL_TIMING): event pairs around launches
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> step_marks, fin_marks;
+    Server* server = nullptr;
+};
+
+int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins);
+hipEvent_t timing_event(Ctx* ctx);  // from the pool (timing-enabled contexts)
+ps_status validate_object(const ps_object* obj);
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_blocks, Program* prog);
+ps_status wait_previous(Ctx* ctx);
+ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
+                      int64_t n_samples, hipStream_t stream, int S_override);
+void destroy_runtime(Ctx* ctx);    // stops the server if one runs
+
+}  // namespace ps

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Bars: FP32 stepping rel-L2 <= 1e-5, FP64 stepping rel-L2 <= 1e-12 over all
+samples of a request (rel-L2 = 10^(dE/20) with the noise distance dE of
+section 5.4.2).  Full-size configurations are checked on sampled outputs
+the oracle can compute (the first repetitions of the full object) and on
+fixed spin subsets over the whole sequence (superposition makes subset
+parity exact up to summation order).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Sequence, Shape, SPOIL, configs as C
+from workloads.phantom import SpinObject, grid2d, grid3d_two_species, random_spins, subset
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import paper_1305_6861_amd as ps
+    return ps
+
+
+@pytest.fixture(scope="module")
+def ctx32(ps):
+    return ps.Context(precision=32)
+
+
+@pytest.fixture(scope="module")
+def ctx64(ps):
+    return ps.Context(precision=64)
+
+
+def gpu(ctx, obj, seq):
+    import torch
+    out = ctx.simulate(obj, seq)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check(ctx, obj, seq, tol, ref=None, label=""):
+    ref = oracle.simulate(obj, seq) if ref is None else ref
+    got = gpu(ctx, obj, seq)
+    assert got.shape == ref.shape
+    err = oracle.rel_l2(got, ref)
+    print(f"[parity] {label or seq.name} spins={obj.n_spins} samples={ref.size} rel_l2={err:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err <= tol, (label, err)
+    return got, ref, err
+
+
+# --------------------------------------------------------------------------
+# whole configurations at oracle-friendly sizes
+# --------------------------------------------------------------------------
+def test_c1_full_fp32(ctx32):
+    obj, seq = C.c1()
+    check(ctx32, obj, seq, TOL32, label="c1")
+
+
+def test_c1_full_fp64(ctx64):
+    obj, seq = C.c1()
+    check(ctx64, obj, seq, TOL64, label="c1/fp64")
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_c2_recipe_reduced(ctx32, ctx64, n):
+    obj, seq = C.c2(n)
+    ref = oracle.simulate(obj, seq)
+    check(ctx32, obj, seq, TOL32, ref=ref, label=f"c2[{n}]")
+    check(ctx64, obj, seq, TOL64, ref=ref, label=f"c2[{n}]/fp64")
+
+
+def test_c3_recipe_reduced(ctx32, ctx64):
+    obj, _ = C.c3(16)
+    seq = C.gre_3d_sinc(16, 4, 3)
+    ref = oracle.simulate(obj, seq)
+    check(ctx32, obj, seq, TOL32, ref=ref, label="c3[16]")
+    check(ctx64, obj, seq, TOL64, ref=ref, label="c3[16]/fp64")
+
+
+# --------------------------------------------------------------------------
+# full sizes in the benchmark's launch configuration
+# --------------------------------------------------------------------------
+def test_c2_full_size_first_repetitions(ctx32):
+    """The full 256^2 x 4-isochromat object through the whole sequence; the
+    oracle computes the first two repetitions' 512 samples exactly."""
+    obj, seq = C.c2()
+    got = gpu(ctx32, obj, seq)
+    ref = oracle.simulate(obj, seq.truncated(8))
+    err = oracle.rel_l2(got[:ref.size], ref)
+    print(f"[parity] c2 full, first 2 TRs rel_l2={err:.3e}", flush=True)
+    assert err <= TOL32
+
+
+def test_c2_full_sequence_spin_subset(ctx32):
+    """Every 64th spin of the full object through all 256 repetitions."""
+    obj, seq = C.c2()
+    check(ctx32, subset(obj, 64), seq, TOL32, label="c2 subset/64")
+
+
+def test_c3_full_object_subset_truncated(ctx32):
+    """Every 4096th spin of the full 2 x 128^3 object, first 48 repetitions
+    of the full recipe (sinc 128 sub-steps, 128 samples)."""
+    obj, seq = C.c3()
+    check(ctx32, subset(obj, 4096, 7), seq.truncated(3 * 48), TOL32, label="c3 subset/4096")
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+def test_empty_object_gives_zeros(ctx32):
+    obj = random_spins(4, seed=1).take(np.arange(0))
+    got = gpu(ctx32, obj, C.fid(1.0, 10, 1e-3))
+    assert got.shape == (10,) and np.all(got == 0)
+
+
+def test_sequence_without_samples(ctx32):
+    got = gpu(ctx32, random_spins(100, seed=2), Sequence("none").add(1e-3, alpha=1.0))
+    assert got.shape == (0,)
+
+
+@pytest.mark.parametrize("n_spins", [1, 63, 257, 1000, 4097])
+def test_ragged_spin_counts(ctx32, n_spins):
+    obj = random_spins(n_spins, seed=n_spins, t_inf_frac=0.2)
+    _, seq = C.c1()
+    check(ctx32, obj, seq.truncated(9), TOL32, label=f"ragged{n_spins}")
+
+
+@pytest.mark.parametrize("n_adc", [1, 17, 31, 32, 33, 95, 1000])
+def test_ragged_sample_counts(ctx32, ctx64, n_adc):
+    obj = random_spins(700, seed=3)
+    seq = Sequence(f"adc{n_adc}")
+    seq.add(2e-3, m=(-40, 10, 5), alpha=0.5, phase=0.3)
+    seq.add(n_adc * 1e-5, m=(n_adc * 1.5, 0, 0), n_adc=n_adc)
+    seq.add(1e-3, m=(3, 0, 0), alpha=1.2, phase=-0.4)
+    seq.add(n_adc * 2e-5, m=(0, n_adc * 0.7, 0), n_adc=n_adc, flags=SPOIL)
+    seq.add(1e-3, alpha=0.4, n_adc=3)
+    ref = oracle.simulate(obj, seq)
+    check(ctx32, obj, seq, TOL32, ref=ref, label=f"adc{n_adc}")
+    check(ctx64, obj, seq, TOL64, ref=ref, label=f"adc{n_adc}/fp64")
+
+
+def test_long_readout_and_time_slicing(ps):
+    """A 5000-sample readout forced through many time slices (small partial
+    buffer).  A slice boundary inside a readout re-anchors the recurrence from
+    the FP64 phase, so the sliced run agrees with the unsliced one to rounding
+    (not bit for bit); both match the oracle."""
+    obj = random_spins(3000, seed=4)
+    seq = Sequence("long")
+    seq.add(1e-3, alpha=1.0)
+    seq.add(5000 * 4e-6, m=(2000, 0, 0), n_adc=5000)
+    seq.add(1e-3, alpha=2.0, phase=1.0, n_adc=7, flags=SPOIL)
+    seq.add(1e-3, alpha=0.7, n_adc=300)
+    with ps.Context(precision=32, spins_per_lane=1) as big, \
+            ps.Context(precision=32, spins_per_lane=1, max_partial_bytes=12 * 8 * 256) as small:
+        a = gpu(big, obj, seq)
+        b = gpu(small, obj, seq)
+    assert oracle.rel_l2(b, a) <= 5e-6
+    ref = oracle.simulate(obj, seq)
+    print(f"[parity] long readout unsliced {oracle.rel_l2(a, ref):.3e} sliced {oracle.rel_l2(b, ref):.3e}",
+          flush=True)
+    assert oracle.rel_l2(a, ref) <= TOL32
+    assert oracle.rel_l2(b, ref) <= TOL32
+
+
+def test_shaped_pulses_with_phase_offsets_and_hard_pulse(ctx32, ctx64):
+    obj = random_spins(900, seed=5, dw_sigma_hz=200.0)
+    rng = np.random.default_rng(5)
+    seq = Sequence("shapes")
+    s0 = seq.add_shape(Shape(tau=1e-5, m_sub=(0, 0, 4.0), alpha=rng.uniform(-0.1, 0.2, 50),
+                             phase=rng.uniform(-1, 1, 50)))
+    s1 = seq.add_shape(C.sinc_shape(64, 2e-5, 0.8, 4.0, 0.1))
+    seq.add(1e-3, m=(0, 0, -100), shape=s0, phase=0.3, n_adc=20)
+    seq.add(2e-3, m=(30, -20, 0), shape=s1, alpha=0.4, phase=1.1, n_adc=40)
+    seq.add(1e-3, shape=s0, phase=0.3, flags=SPOIL)
+    seq.add(1e-3, shape=s1, phase=-2.0, n_adc=33)
+    ref = oracle.simulate(obj, seq)
+    check(ctx32, obj, seq, TOL32, ref=ref, label="shapes")
+    check(ctx64, obj, seq, TOL64, ref=ref, label="shapes/fp64")
+
+
+def test_closed_form_spin_echo_on_gpu(ctx64):
+    """GPU FP64 against the closed form directly (echo = j m0 e^{-TE/T2})."""
+    te, n = 40e-3, 16
+    obj = random_spins(333, seed=6, dw_sigma_hz=80.0)
+    got = gpu(ctx64, obj, C.spin_echo_single(te, n, 1e-4))
+    ref = 1j * np.sum(obj.m0.astype(float) * np.exp(-te / obj.t2.astype(float)))
+    assert abs(got[n // 2] - ref) <= 1e-12 * abs(ref)
+
+
+# --------------------------------------------------------------------------
+# determinism and tiling
+# --------------------------------------------------------------------------
+def test_bitwise_repeatable(ctx32):
+    obj, seq = C.c2(48)
+    a = gpu(ctx32, obj, seq)
+    b = gpu(ctx32, obj, seq)
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+def test_every_tiling_matches_oracle(ps, S):
+    obj, seq = C.c2(40)
+    with ps.Context(precision=32, spins_per_lane=S) as ctx:
+        check(ctx, obj, seq, TOL32, label=f"c2[40] S={S}")
+
+
+def test_spin_permutation_and_superposition(ctx32):
+    obj, seq = C.c2(32)
+    a = gpu(ctx32, obj, seq)
+    perm = np.random.default_rng(0).permutation(obj.n_spins)
+    b = gpu(ctx32, obj.take(perm), seq)
+    assert oracle.rel_l2(b, a) <= TOL32
+    half = obj.n_spins // 2
+    c = gpu(ctx32, obj.take(np.arange(half)), seq) + gpu(ctx32, obj.take(np.arange(half, obj.n_spins)), seq)
+    assert oracle.rel_l2(c, a) <= TOL32
