@@ -31,8 +31,12 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak (published)
 FLOPS_ADC_SAMPLE = 8          # p <- p z (complex multiply) and accumulate
 FLOPS_HARD_RF = 15            # 3x3 rotation of (Mx, My, Mz), eq. 3.19
 FLOPS_SHAPE_SUBSTEP = 23      # rotation + complex precession/decay + Mz recovery
-WORKLOAD = ("c2: 2-D 256x256 grid, 4 jittered isochromats/voxel (262,144 spins), "
-            "spin echo 90x/180y TE 20 ms TR 500 ms, 256 phase encodes x 256 samples")
+WORKLOADS = {
+    "c2": ("c2: 2-D 256x256 grid, 4 jittered isochromats/voxel (262,144 spins), "
+           "spin echo 90x/180y TE 20 ms TR 500 ms, 256 phase encodes x 256 samples"),
+    "c3": ("c3: 3-D 128^3 grid x two species (4,194,304 spins), quadratic B0 +-50 Hz, fat -440 Hz; "
+           "GRE with 128-sub-step TBW-4 sinc (30 deg), TE 5 ms TR 10 ms, 128x128 phase encodes x 128 samples"),
+}
 
 
 def algorithmic_flops(seq, n_spins: int) -> float:
@@ -93,15 +97,38 @@ def cpu_baseline(obj, seq, ctx, target_s: float):
             "gpu_rel_l2_on_sample": err}
 
 
+def copy_calibration(n_bytes: int = 1 << 30, reps: int = 5):
+    """A plain copy of n_bytes (read n_bytes, write n_bytes) per launch."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": n_bytes, "copy_bytes_written": n_bytes, "reps": reps,
+                      "ms_per_copy": dt * 1e3, "GB_per_s": 2 * n_bytes / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--spins-per-lane", type=int, default=0, help="0 = autotuned")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
+                    help="c2 (default, the reported workload) or c3 (the 3-D shaped-pulse configuration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="instead of the workload, run a plain 1 GiB device-to-device copy 5 times "
+                         "(reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus N with N > 1 is not supported "
@@ -113,7 +140,7 @@ def main():
     import paper_1305_6861_amd as ps
     from workloads import configs as C
 
-    obj, seq = C.c2()
+    obj, seq = C.c2() if args.workload == "c2" else C.c3()
     dev = ps.to_device(obj)
     ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane)
     packed = ps.pack_sequence(seq)
@@ -138,17 +165,22 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = spin_steps * args.steps / elapsed
     flops = algorithmic_flops(seq, obj.n_spins)
-    k_ms = sum(step_ms) / max(len(step_ms), 1)
+    # a long sequence runs as several time slices (launches) per step: the
+    # step's kernel time is the sum over its launches
+    launches = len(step_ms) // max(args.steps, 1)
+    k_ms = sum(step_ms) / max(args.steps, 1)
     achieved = flops / (k_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_from_profiles(spl),
-            "kernel": "step_kernel<float,%d>" % spl, "kernel_ms": k_ms,
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic_from_profiles(spl) if args.workload == "c2" else None,
+            "kernel": "step_kernel<float,%d>" % spl, "kernel_ms": k_ms, "launches_per_step": launches,
+            "kernel_ms_per_launch": k_ms / max(launches, 1),
             "flops_per_launch": flops, "finalize_ms_per_step": fin_ms / max(args.steps, 1)}
     rec = {"metric": "spin-steps/s", "value": value, "unit": "spin-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": WORKLOAD, "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
+           "config": {"workload": WORKLOADS[args.workload], "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
                       "n_samples": n_samples, "spins_per_lane": spl, "precision": "fp32 stepping, "
                       "fp64 phases and cross-block sums"},
            "eta_spins_per_s": obj.n_spins / (ms_per_step * 1e-3),

@@ -137,6 +137,18 @@ ps_status ps_count(const ps_sequence *seq, int64_t *n_samples, int64_t *n_steps_
 ps_status ps_simulate(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq,
                       double *signal, int64_t n_samples, void *stream);
 
+/* Simulate n_requests independent requests together, stream-ordered on
+ * `stream`.  All workgroup tiles of all requests form one work queue that a
+ * persistent kernel drains (one launch per spins-per-lane class and time
+ * slice round), after the paper's dynamic assignment of more spin blocks than
+ * compute nodes (section 5.3.2).  objs[i], seqs[i], signals[i] and
+ * n_samples[i] are as for ps_simulate.  Each request keeps the tiling and
+ * time slicing it would get alone, so signals[i] is bitwise identical to
+ * ps_simulate on the same context.  On failure no request has been started;
+ * ps_last_error() names the offending request. */
+ps_status ps_simulate_batch(ps_ctx *ctx, int32_t n_requests, const ps_object *objs, const ps_sequence *seqs,
+                            double *const *signals, const int64_t *n_samples, void *stream);
+
 /* The tiling ps_simulate uses for an object of n_spins spins on this
  * context: spins held per lane (the autotuned or configured value) and
  * spins per workgroup (4 waves of 64 lanes). */

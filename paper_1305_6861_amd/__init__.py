@@ -159,6 +159,43 @@ class Context:
         _b.check(_b.lib.ps_kernel_times(self._h, buf, capacity, ctypes.byref(n), ctypes.byref(fin)))
         return [buf[i] for i in range(min(n.value, capacity))], float(fin.value)
 
+    def simulate_batch(self, objs, seqs, stream=None):
+        """Signals of several requests computed together (one persistent
+        launch per spins-per-lane class and time-slice round); each equals,
+        bit for bit, what simulate() returns for that request alone."""
+        import torch
+        if len(objs) != len(seqs):
+            raise PsError(1, "objs and seqs differ in length")
+        n = len(objs)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        devs, packs, outs = [], [], []
+        o_arr = (_b.ps_object * max(n, 1))()
+        s_arr = (_b.ps_sequence * max(n, 1))()
+        sig_arr = (ctypes.c_void_p * max(n, 1))()
+        ns_arr = (ctypes.c_int64 * max(n, 1))()
+        for i, (obj, seq) in enumerate(zip(objs, seqs)):
+            owned = not (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
+                                                       for f in FIELDS))
+            dev = to_device(obj, f"cuda:{self.device}") if owned else obj
+            if owned:
+                for t in dev.values():
+                    t.record_stream(stream)
+            ps = pack_sequence(seq)
+            try:
+                ns, _ = ps.count()
+            except PsError as e:
+                raise PsError(e.status, f"request {i}: {e}") from None
+            out = torch.empty(2 * ns, dtype=torch.float64, device=f"cuda:{self.device}")
+            devs.append(dev); packs.append(ps); outs.append(out)
+            o_arr[i] = _object_struct(dev)
+            s_arr[i] = ps.struct
+            sig_arr[i] = out.data_ptr() if ns else None
+            ns_arr[i] = ns
+        _b.check(_b.lib.ps_simulate_batch(self._h, n, o_arr, s_arr, sig_arr, ns_arr,
+                                          ctypes.c_void_p(stream.cuda_stream)))
+        return [o.view(torch.complex128) for o in outs]
+
     def simulate(self, obj, seq, out=None, stream=None):
         """Signal of one request as a complex128 CUDA tensor (stream-ordered
         on `stream`, default torch's current stream)."""

@@ -106,13 +106,13 @@ ps_status validate_object(const ps_object* obj) {
     return PS_OK;
 }
 
-// Compile + slice a request for a given tiling.
-ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_blocks, Program* prog) {
+// Compile + slice a request for a given number of partial-sum rows.
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, Program* prog) {
     std::string err;
     ps_status st = compile_sequence(seq, prog, &err);
     if (st != PS_OK) return fail(st, err);
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
-    const int64_t per_sample = std::max<int64_t>(n_blocks, 1) * 2 * real_bytes;
+    const int64_t per_sample = std::max<int64_t>(n_rows, 1) * 2 * real_bytes;
     int64_t max_samples = ctx->cfg.max_partial_bytes / per_sample;
     if (max_samples < 64) max_samples = 64;
     plan_slices(prog, max_samples);
@@ -123,22 +123,14 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_blocks, Prog
 // Upload program tables into the context's buffers (stream-ordered).
 ps_status upload(Ctx* ctx, const Program& prog, hipStream_t stream) {
     const size_t ops_bytes = prog.ops.size() * sizeof(Op);
-    const size_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
-    const size_t rows_bytes = prog.rows.size() * real_bytes;
+    const size_t rows_bytes = prog.rows.size() * sizeof(double);
     ps_status st;
     if ((st = ctx->ops.reserve(ops_bytes)) != PS_OK) return st;
     if ((st = ctx->rows.reserve(rows_bytes)) != PS_OK) return st;
     if ((st = ctx->staging.reserve(ops_bytes + rows_bytes)) != PS_OK) return st;
     unsigned char* h = reinterpret_cast<unsigned char*>(ctx->staging.ptr);
     if (ops_bytes) std::memcpy(h, prog.ops.data(), ops_bytes);
-    if (rows_bytes) {
-        if (real_bytes == 8) {
-            std::memcpy(h + ops_bytes, prog.rows.data(), rows_bytes);
-        } else {
-            float* f = reinterpret_cast<float*>(h + ops_bytes);
-            for (size_t i = 0; i < prog.rows.size(); ++i) f[i] = (float)prog.rows[i];
-        }
-    }
+    if (rows_bytes) std::memcpy(h + ops_bytes, prog.rows.data(), rows_bytes);
     hipError_t e;
     if (ops_bytes && (e = hipMemcpyAsync(ctx->ops.ptr, h, ops_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ops)");
@@ -162,8 +154,9 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     const int S = S_override > 0 ? S_override : choose_spins_per_lane(ctx, obj->n_spins);
     const int64_t spb = spins_per_block_of(S);
     const int64_t n_blocks = (obj->n_spins + spb - 1) / spb;
+    const int64_t n_rows = n_blocks * rows_per_block_of(S);
     Program prog;
-    if ((st = prepare(ctx, seq, n_blocks, &prog)) != PS_OK) return st;
+    if ((st = prepare(ctx, seq, n_rows, &prog)) != PS_OK) return st;
     if (n_samples != prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
                                           std::to_string(prog.n_samples));
@@ -180,7 +173,10 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     int64_t max_slice = 0;
     for (const Slice& s : prog.slices) max_slice = std::max(max_slice, s.n_samples);
     const int64_t row_stride = 2 * max_slice;
-    if ((st = ctx->partial.reserve((size_t)(n_blocks * row_stride * real_bytes))) != PS_OK) return st;
+    if ((st = ctx->partial.reserve((size_t)(n_rows * row_stride * real_bytes))) != PS_OK) return st;
+    const int64_t fin_doubles = finalize_scratch_doubles(n_rows, row_stride);
+    if (fin_doubles > 0 && (st = ctx->fin_scratch.reserve((size_t)fin_doubles * sizeof(double))) != PS_OK)
+        return st;
     const bool sliced = prog.slices.size() > 1;
     if (sliced && (st = ctx->state.reserve((size_t)(3 * obj->n_spins * real_bytes))) != PS_OK) return st;
     if ((st = upload(ctx, prog, stream)) != PS_OK) return st;
@@ -188,7 +184,7 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     StepArgs a;
     a.x = obj->x; a.y = obj->y; a.z = obj->z; a.m0 = obj->m0; a.t1 = obj->t1; a.t2 = obj->t2; a.dw = obj->dw;
     a.n_spins = obj->n_spins;
-    a.n_rows = (int32_t)(prog.rows.size() / 9);
+    a.n_shape_rows = (int32_t)(prog.rows.size() / 9);
     a.rows = ctx->rows.ptr;
     a.partial = ctx->partial.ptr;
     a.row_stride = row_stride;
@@ -211,8 +207,9 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
             return hip_fail(e, "step kernel launch");
         if (timing) hipEventRecord(t1, stream);
         if (sl.n_samples > 0 &&
-            (e = launch_finalize(ctx->partial.ptr, ctx->cfg.precision, n_blocks, row_stride, 2 * sl.n_samples,
-                                 signal + 2 * sl.sample_begin, stream)) != hipSuccess)
+            (e = launch_finalize(ctx->partial.ptr, ctx->cfg.precision, n_rows, row_stride, 2 * sl.n_samples,
+                                 signal + 2 * sl.sample_begin, reinterpret_cast<double*>(ctx->fin_scratch.ptr),
+                                 stream)) != hipSuccess)
             return hip_fail(e, "finalize kernel launch");
         if (timing) {
             hipEventRecord(t2, stream);
@@ -289,6 +286,8 @@ void ps_destroy(ps_ctx* handle) {
         for (auto& m : ctx->fin_marks) hipEventDestroy(m.second);   // m.first is a step mark
         for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
         ctx->ops.release(); ctx->rows.release(); ctx->partial.release(); ctx->state.release();
+        ctx->fin_scratch.release(); ctx->batch_tables.release(); ctx->batch_records.release();
+        ctx->staging2.release();
         ctx->staging.release();
     }
     delete ctx;

@@ -1,0 +1,325 @@
+// Batched execution: many independent requests per persistent launch.
+//
+// The paper spreads spin blocks over workstations dynamically, with more
+// blocks than nodes so that faster nodes simply take more (section 5.3.2).
+// Here every request is cut into workgroup tiles, all tiles of all requests
+// form one queue, and a persistent kernel's workgroups pull from it.  A tile
+// writes only its own request's partial rows, and each request keeps the
+// tiling and time slicing it would get alone (both depend only on its own
+// size), so a request's result is bitwise the same alone (ps_simulate) or in
+// any batch.  Requests longer than one time slice run one slice per round,
+// their anchors kept in HBM between rounds.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/parspin.h"
+#include "batch.h"
+#include "ps_kernels.h"
+#include "ps_runtime.h"
+
+namespace ps {
+
+static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* seq, int64_t n_samples,
+                       double* signal, int64_t max_slice_steps, ReqPlan* p) {
+    ps_status st = validate_object(obj);
+    if (st != PS_OK) return st;
+    p->obj = *obj;
+    p->signal = signal;
+    p->S = choose_spins_per_lane(ctx, obj->n_spins);
+    const int64_t spb = spins_per_block_of(p->S);
+    p->n_blocks = (obj->n_spins + spb - 1) / spb;
+    p->n_rows = p->n_blocks * rows_per_block_of(p->S);
+    if ((st = prepare(ctx, seq, p->n_rows, &p->prog)) != PS_OK) return st;
+    if (max_slice_steps > 0) {
+        // a second bound for serving: at most max_slice_steps intervals per
+        // spin per slice, so that long requests yield the device regularly
+        Program& g = p->prog;
+        std::vector<Slice> out;
+        for (const Slice& sl : g.slices) {
+            Slice cur = sl;
+            int64_t steps = 0;
+            int64_t samples_before = 0;
+            for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
+                const Op& op = g.ops[i];
+                const int64_t w = op.kind == OP_ADC ? op.n : (op.kind == OP_SHAPE ? op.n : 1);
+                if (steps > 0 && steps + w > max_slice_steps) {
+                    // cut before op i; ADC offsets restart at the new slice
+                    cur.op_end = i;
+                    cur.n_samples = samples_before;
+                    out.push_back(cur);
+                    cur = Slice();
+                    cur.op_begin = i;
+                    cur.sample_begin = out.back().sample_begin + out.back().n_samples;
+                    steps = 0;
+                    samples_before = 0;
+                }
+                if (op.kind == OP_ADC) {
+                    g.ops[i].aux = (uint32_t)samples_before;
+                    samples_before += op.n;
+                }
+                steps += w;
+            }
+            cur.op_end = sl.op_end;
+            cur.n_samples = samples_before;
+            out.push_back(cur);
+        }
+        g.slices = std::move(out);
+    }
+    if (n_samples != p->prog.n_samples)
+        return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
+                                          std::to_string(p->prog.n_samples));
+    if (n_samples > 0 && !signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
+    int64_t max_slice = 0;
+    for (const Slice& s : p->prog.slices) max_slice = std::max(max_slice, s.n_samples);
+    p->row_stride = 2 * max_slice;
+    p->n_groups = (p->n_rows + row_group_size() - 1) / row_group_size();
+    const size_t rb = ctx->cfg.precision == 64 ? 8 : 4;
+    p->bytes_partial = align_up((size_t)(p->n_rows * p->row_stride) * rb);
+    p->bytes_state = p->prog.slices.size() > 1 ? align_up((size_t)(3 * obj->n_spins) * rb) : 0;
+    p->bytes_mid = p->n_groups > 1 ? align_up((size_t)(p->n_groups * p->row_stride) * sizeof(double)) : 0;
+    p->bytes_ops = align_up(p->prog.ops.size() * sizeof(Op));
+    p->bytes_rows = align_up(p->prog.rows.size() * sizeof(double));
+    return PS_OK;
+}
+
+size_t ReqPlan::device_bytes() const { return bytes_partial + bytes_state + bytes_mid + bytes_ops + bytes_rows; }
+
+size_t ReqPlan::footprint() const {
+    return device_bytes() + (size_t)obj.n_spins * 7 * sizeof(float) + (size_t)prog.n_samples * 2 * sizeof(double);
+}
+
+void ReqPlan::bind(unsigned char* base) {
+    unsigned char* q = base;
+    d_partial = q; q += bytes_partial;
+    d_state = bytes_state ? q : nullptr; q += bytes_state;
+    d_mid = bytes_mid ? reinterpret_cast<double*>(q) : nullptr; q += bytes_mid;
+    d_ops = reinterpret_cast<Op*>(q); q += bytes_ops;
+    d_rows = reinterpret_cast<double*>(q); q += bytes_rows;
+}
+
+StepArgs ReqPlan::args_for_slice(size_t k) const {
+    const Slice& sl = prog.slices[k];
+    StepArgs a;
+    a.x = obj.x; a.y = obj.y; a.z = obj.z; a.m0 = obj.m0; a.t1 = obj.t1; a.t2 = obj.t2; a.dw = obj.dw;
+    a.n_spins = obj.n_spins;
+    a.ops = d_ops + sl.op_begin;
+    a.n_ops = (int32_t)(sl.op_end - sl.op_begin);
+    a.n_shape_rows = (int32_t)(prog.rows.size() / 9);
+    a.rows = d_rows;
+    a.partial = d_partial;
+    a.row_stride = row_stride;
+    a.state = d_state;
+    a.load_state = k > 0;
+    a.save_state = k + 1 < prog.slices.size();
+    return a;
+}
+
+// Host image of one round's launch records, laid out for a single upload.
+struct RoundImage {
+    struct Class {                      // one spins-per-lane class
+        int S;
+        size_t items_off;               // offset of its BatchItem array in the image
+        size_t counter_off;             // offset of its queue counter
+        int32_t n_req;
+        int64_t total;
+        int32_t max_shape_rows;
+    };
+    std::vector<Class> classes;
+    size_t fin_off = 0;
+    int32_t n_fin = 0;
+    int64_t tiles1 = 0, tiles2 = 0;
+};
+
+ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first_slice,
+                     const std::vector<size_t>& n_slices_this_call, hipStream_t stream, DevBuf& arena,
+                     HostBuf& staging, std::vector<RoundImage>* rounds_out) {
+    // plans[i] runs slices first_slice[i] .. first_slice[i] + n_slices_this_call[i] - 1,
+    // one per round.  Tables (ops, rows) must already be resident (uploaded by the caller).
+    (void)rounds_out;
+    size_t max_rounds = 0;
+    for (size_t i = 0; i < plans.size(); ++i) max_rounds = std::max(max_rounds, n_slices_this_call[i]);
+    // build all rounds' records in one host image
+    std::vector<unsigned char> img;
+    auto reserve_bytes = [&](size_t n) {
+        const size_t off = align_up(img.size(), 64);
+        img.resize(off + n);
+        return off;
+    };
+    std::vector<RoundImage> rounds(max_rounds);
+    for (size_t k = 0; k < max_rounds; ++k) {
+        RoundImage& R = rounds[k];
+        std::map<int, std::vector<size_t>> by_S;
+        for (size_t i = 0; i < plans.size(); ++i)
+            if (k < n_slices_this_call[i] && plans[i]->obj.n_spins > 0) by_S[plans[i]->S].push_back(i);
+        for (auto& kv : by_S) {
+            RoundImage::Class c;
+            c.S = kv.first;
+            c.n_req = (int32_t)kv.second.size();
+            c.items_off = reserve_bytes(sizeof(BatchItem) * kv.second.size());
+            c.counter_off = reserve_bytes(sizeof(unsigned long long));
+            int64_t total = 0;
+            int32_t msr = 0;
+            for (size_t q = 0; q < kv.second.size(); ++q) {
+                ReqPlan* p = plans[kv.second[q]];
+                BatchItem it;
+                std::memset(&it, 0, sizeof(it));
+                it.args = p->args_for_slice(first_slice[kv.second[q]] + k);
+                it.item_begin = total;
+                it.n_items = p->n_blocks;
+                total += p->n_blocks;
+                msr = std::max(msr, it.args.n_shape_rows);
+                std::memcpy(img.data() + c.items_off + q * sizeof(BatchItem), &it, sizeof(it));
+            }
+            c.total = total;
+            c.max_shape_rows = msr;
+            std::memset(img.data() + c.counter_off, 0, sizeof(unsigned long long));
+            R.classes.push_back(c);
+        }
+        // finalize records for requests whose slice k has samples
+        std::vector<FinDesc> fd;
+        int64_t t1 = 0, t2 = 0;
+        for (size_t i = 0; i < plans.size(); ++i) {
+            if (k >= n_slices_this_call[i]) continue;
+            ReqPlan* p = plans[i];
+            const Slice& sl = p->prog.slices[first_slice[i] + k];
+            if (sl.n_samples == 0) continue;
+            FinDesc f;
+            std::memset(&f, 0, sizeof(f));
+            f.partial = p->d_partial;
+            f.n_rows = p->n_rows;
+            f.row_stride = p->row_stride;
+            f.n_vals = 2 * sl.n_samples;
+            f.n_groups = p->n_groups;
+            f.out = p->signal + 2 * sl.sample_begin;
+            f.mid = p->d_mid;
+            const int64_t jt = (f.n_vals + 255) / 256;
+            f.tile_begin1 = t1;
+            f.tile_begin2 = t2;
+            t1 += std::max<int64_t>(f.n_groups, 1) * jt;
+            if (f.n_groups > 1) t2 += jt;
+            if (p->obj.n_spins == 0) continue;   // zero-filled separately
+            fd.push_back(f);
+        }
+        // recompute the prefix sums over the records kept
+        t1 = 0; t2 = 0;
+        for (FinDesc& f : fd) {
+            const int64_t jt = (f.n_vals + 255) / 256;
+            f.tile_begin1 = t1; f.tile_begin2 = t2;
+            t1 += std::max<int64_t>(f.n_groups, 1) * jt;
+            if (f.n_groups > 1) t2 += jt;
+        }
+        R.n_fin = (int32_t)fd.size();
+        R.tiles1 = t1; R.tiles2 = t2;
+        if (!fd.empty()) {
+            R.fin_off = reserve_bytes(sizeof(FinDesc) * fd.size());
+            std::memcpy(img.data() + R.fin_off, fd.data(), sizeof(FinDesc) * fd.size());
+        }
+    }
+    if (img.empty()) return PS_OK;
+    ps_status st;
+    if ((st = arena.reserve(img.size())) != PS_OK) return st;
+    if ((st = staging.reserve(img.size())) != PS_OK) return st;
+    std::memcpy(staging.ptr, img.data(), img.size());
+    hipError_t e = hipMemcpyAsync(arena.ptr, staging.ptr, img.size(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch records)");
+    unsigned char* dev = reinterpret_cast<unsigned char*>(arena.ptr);
+    for (size_t k = 0; k < rounds.size(); ++k) {
+        const RoundImage& R = rounds[k];
+        for (const RoundImage::Class& c : R.classes) {
+            e = launch_batch_step(reinterpret_cast<const BatchItem*>(dev + c.items_off), c.n_req, c.total,
+                                  reinterpret_cast<unsigned long long*>(dev + c.counter_off), c.max_shape_rows,
+                                  ctx->cfg.precision, c.S, ctx->n_cu, stream);
+            if (e != hipSuccess) return hip_fail(e, "batch step launch");
+        }
+        if (R.n_fin > 0) {
+            e = launch_batch_finalize(reinterpret_cast<const FinDesc*>(dev + R.fin_off), R.n_fin, R.tiles1,
+                                      R.tiles2, ctx->cfg.precision, stream);
+            if (e != hipSuccess) return hip_fail(e, "batch finalize launch");
+        }
+    }
+    return PS_OK;
+}
+
+ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t staging_off, hipStream_t stream) {
+    size_t need = 0;
+    for (ReqPlan* p : plans) need += p->bytes_ops + p->bytes_rows;
+    ps_status st;
+    if ((st = staging.reserve(staging_off + need)) != PS_OK) return st;
+    unsigned char* h = reinterpret_cast<unsigned char*>(staging.ptr) + staging_off;
+    for (ReqPlan* p : plans) {
+        const size_t ob = p->prog.ops.size() * sizeof(Op), rb = p->prog.rows.size() * sizeof(double);
+        if (ob) {
+            std::memcpy(h, p->prog.ops.data(), ob);
+            hipError_t e = hipMemcpyAsync(p->d_ops, h, ob, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(ops)");
+            h += p->bytes_ops;
+        }
+        if (rb) {
+            std::memcpy(h, p->prog.rows.data(), rb);
+            hipError_t e = hipMemcpyAsync(p->d_rows, h, rb, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(rows)");
+            h += p->bytes_rows;
+        }
+    }
+    return PS_OK;
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const ps_object* objs,
+                                       const ps_sequence* seqs, double* const* signals, const int64_t* n_samples,
+                                       void* stream_v) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    if (n_requests < 0) return fail(PS_E_INVALID_ARG, "n_requests < 0");
+    if (n_requests == 0) return PS_OK;
+    if (!objs || !seqs || !signals || !n_samples) return fail(PS_E_INVALID_ARG, "NULL request array");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    std::vector<ReqPlan> plans((size_t)n_requests);
+    for (int32_t i = 0; i < n_requests; ++i) {
+        ps_status st = plan_request(ctx, &objs[i], &seqs[i], n_samples[i], signals[i], 0, &plans[i]);
+        if (st != PS_OK) return fail(st, "request " + std::to_string(i) + ": " + ps_last_error());
+    }
+    ps_status st;
+    if ((st = wait_previous(ctx)) != PS_OK) return st;
+    size_t total = 0;
+    for (ReqPlan& p : plans) total += p.device_bytes();
+    if ((st = ctx->batch_tables.reserve(std::max<size_t>(total, 256))) != PS_OK) return st;
+    unsigned char* base = reinterpret_cast<unsigned char*>(ctx->batch_tables.ptr);
+    std::vector<ReqPlan*> ptrs;
+    std::vector<size_t> first, count;
+    for (ReqPlan& p : plans) {
+        p.bind(base);
+        base += p.device_bytes();
+        if (p.prog.n_samples == 0) continue;
+        if (p.obj.n_spins == 0) {
+            hipError_t e = launch_fill_zero(p.signal, 2 * p.prog.n_samples, stream);
+            if (e != hipSuccess) return hip_fail(e, "fill");
+            continue;
+        }
+        ptrs.push_back(&p);
+        first.push_back(0);
+        count.push_back(p.prog.slices.size());
+    }
+    if (ptrs.empty()) return PS_OK;
+    // records first in the staging buffer, tables after them
+    if ((st = upload_tables(ptrs, ctx->staging, 0, stream)) != PS_OK) return st;
+    if ((st = run_rounds(ctx, ptrs, first, count, stream, ctx->batch_records, ctx->staging2, nullptr)) != PS_OK)
+        return st;
+    hipError_t e = hipEventRecord(ctx->done, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ctx->pending = true;
+    return PS_OK;
+}

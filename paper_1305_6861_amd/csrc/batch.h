@@ -1,0 +1,51 @@
+// Batched / served execution internals (batch.cpp, server.cpp).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <vector>
+
+#include "../../include/parspin.h"
+#include "compile.h"
+#include "ps_kernels.h"
+#include "ps_runtime.h"
+
+namespace ps {
+
+// One request compiled for its own tiling and slicing.
+struct ReqPlan {
+    ps_object obj{};
+    double* signal = nullptr;
+    Program prog;
+    int S = 1;
+    int64_t n_blocks = 0, n_rows = 0, row_stride = 0, n_groups = 0;
+    size_t bytes_partial = 0, bytes_state = 0, bytes_mid = 0, bytes_ops = 0, bytes_rows = 0;
+    // device placement (bind)
+    void* d_partial = nullptr;
+    void* d_state = nullptr;
+    double* d_mid = nullptr;
+    Op* d_ops = nullptr;
+    double* d_rows = nullptr;
+
+    size_t device_bytes() const;       // library buffers of this request
+    size_t footprint() const;          // + object arrays + output (admission)
+    void bind(unsigned char* base);    // place the buffers at base (256-aligned)
+    StepArgs args_for_slice(size_t k) const;
+};
+
+// Validate, compile and slice one request (max_slice_steps > 0 additionally
+// bounds the intervals per spin in one slice).
+ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* seq, int64_t n_samples,
+                       double* signal, int64_t max_slice_steps, ReqPlan* p);
+
+// Stream-ordered upload of the requests' op and rotation tables.
+ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t staging_off, hipStream_t stream);
+
+struct RoundImage;
+// Run slices first[i] .. first[i] + count[i] - 1 of every plan, one slice per
+// round, each round one persistent launch per spins-per-lane class plus one
+// batched finalize.  Launch records go through arena/staging.
+ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first,
+                     const std::vector<size_t>& count, hipStream_t stream, DevBuf& arena, HostBuf& staging,
+                     std::vector<RoundImage>* rounds_out);
+
+}  // namespace ps

@@ -19,15 +19,23 @@
 // runs for at most 31 steps before it is re-anchored from p <- p Z, so its
 // rounding grows like (31 + n/32) ulps instead of n ulps.
 //
-// Per-sample superposition (eq. 3.32): each lane first sums its S spins,
-// then a butterfly over 32 consecutive samples (64 reals) reduces the 64
-// lanes with permlane32/16 swaps and DPP, leaving lane l with sample l/2,
-// component l%2; the 4 waves are added in LDS in a fixed order and the
-// workgroup writes one partial per sample.  A second kernel sums the
-// workgroup partials in FP64 in workgroup order.  Every order is fixed, so
-// results are bitwise reproducible for a given tiling.
+// Readouts are split across waves by sample chunk instead of by spin: the
+// G waves of a wave group publish their spins' readout anchors in LDS, and
+// wave g of the group then runs chunks g, g + G, g + 2G, ... (32 samples
+// each) for all G * S spins of the group.  Each lane thus sums G * S spins
+// per sample, the butterfly cost is shared by that many spins, and no
+// cross-wave reduction or barrier sits inside the sample loop.
+//
+// Per-sample superposition (eq. 3.32): each lane first sums its G * S
+// spins, then a butterfly over 32 consecutive samples (64 reals) reduces the
+// 64 lanes with permlane32/16 swaps and DPP, leaving lane l with sample l/2,
+// component l%2, and the wave writes that partial sum into its wave group's
+// row.  A second kernel sums all rows in FP64 in row order.  Every order is
+// fixed, so results are bitwise reproducible for a given tiling.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "ps_kernels.h"
 #include "ps_ops.h"
@@ -60,13 +68,16 @@ template <> struct Math<float> {
     // 1 - exp(-t r), formed without cancellation (for t r << 1 the FP32
     // difference 1 - exp(-t r) would keep only a few significant bits).
     static __device__ __forceinline__ float one_minus_expneg(double t, double r) {
-        return (float)(-expm1(-t * r));
+        return -expm1f((float)(-t * r));
     }
     // cos and sin of 2 pi c for a phase c in revolutions (FP64), reduced to
-    // [-1/2, 1/2] in FP64 before rounding to FP32.
+    // [-1/2, 1/2] in FP64 before rounding to FP32, then evaluated by the
+    // hardware sine/cosine, which take revolutions.  Measured on gfx950 over
+    // [-1/2, 1/2]: max abs error 1.25e-7 with zero mean (FP64 reference).
     static __device__ __forceinline__ void cis(double c, float& co, float& si) {
-        float f = (float)(c - rint(c));
-        sincospif(2.0f * f, &si, &co);
+        const float f = (float)(c - rint(c));
+        co = __builtin_amdgcn_cosf(f);
+        si = __builtin_amdgcn_sinf(f);
     }
 };
 
@@ -93,9 +104,9 @@ __device__ __forceinline__ void dpp_stage(float (&v)[64], int lane) {
     const bool upper = (lane & BIT) != 0;
 #pragma unroll
     for (int i = 0; i < HALF; ++i) {
-        float send = upper ? v[i] : v[i + HALF];
-        float keep = upper ? v[i + HALF] : v[i];
-        v[i] = keep + dpp<CTRL>(send);
+        const float lo = v[i] + dpp<CTRL>(v[i]);             // both lanes of a pair sum value i
+        const float hi = v[i + HALF] + dpp<CTRL>(v[i + HALF]);
+        v[i] = upper ? hi : lo;
     }
 }
 
@@ -145,6 +156,22 @@ __device__ __forceinline__ double wave_reduce64(double (&v)[64], int lane) {
 // ---------------------------------------------------------------------------
 // the stepper
 // ---------------------------------------------------------------------------
+// Waves that share their spins during readouts (see the file comment):
+// the readout works on G * S spins per lane.
+template <int S>
+struct ReadoutShare {
+    static constexpr int G = S <= 2 ? 4 : (S == 4 ? 2 : 1);
+};
+
+int64_t rows_per_block_of(int spins_per_lane) {
+    switch (spins_per_lane) {
+        case 1: return kWaves / ReadoutShare<1>::G;
+        case 2: return kWaves / ReadoutShare<2>::G;
+        case 4: return kWaves / ReadoutShare<4>::G;
+        default: return kWaves / ReadoutShare<8>::G;
+    }
+}
+
 template <typename real, int S>
 struct Spins {
     float x[S], y[S], z[S], dw[S], m0[S];
@@ -164,9 +191,13 @@ __device__ __forceinline__ void evaluate(const Spins<real, S>& sp, const Op& op,
                                          real (&mx)[S], real (&my)[S], real (&mz)[S]) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        real e1 = Math<real>::expneg(op.tz, sp.r1[s]);
-        real m0 = (real)sp.m0[s];
-        mz[s] = m0 + (sp.az[s] - m0) * e1;
+        // T1 recovery over tz as Mz_a + (M0 - Mz_a)(1 - E1): in a saturated
+        // steady state Mz << M0, and M0 + (Mz_a - M0) E1 would cancel, turning
+        // the rounding of E1 into a bias that is the same for this spin in
+        // every repetition.
+        const real d1 = Math<real>::one_minus_expneg(op.tz, sp.r1[s]);
+        const real m0 = (real)sp.m0[s];
+        mz[s] = fma(m0 - sp.az[s], d1, sp.az[s]);
         if (mxy_zero) {
             mx[s] = 0; my[s] = 0;
         } else {
@@ -216,17 +247,22 @@ __device__ __forceinline__ void step_delta(double c, double tau, double r2, real
     di = (real)(-2.0 * e2 * s1 * c1);
 }
 
+// One workgroup tile of one request: spins [blk * 256 S, (blk + 1) * 256 S)
+// through the slice's operations, partial sums into the tile's rows.
 template <typename real, int S>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) {
+    constexpr int G = ReadoutShare<S>::G;
+    constexpr int R = G * S;                 // spins per lane inside readouts
     __shared__ Op s_ops[kOpChunk];
-    __shared__ real s_red[2][kWaves][64];
+    __shared__ real s_x[G > 1 ? kWaves : 1][G > 1 ? S : 1][8][64];   // readout anchors
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    real* s_rows = reinterpret_cast<real*>(s_dyn);
+    double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t base = ((int64_t)blockIdx.x * kWaves + wave) * 64 * S;
+    const int64_t base = (blk * kWaves + wave) * 64 * S;
+    __syncthreads();                         // LDS of a previous tile is no longer in use
 
     Spins<real, S> sp;
 #pragma unroll
@@ -252,12 +288,13 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
 
     // shaped-pulse rotation rows -> LDS (made visible by the first barrier below)
     {
-        const real* rows = reinterpret_cast<const real*>(a.rows);
-        for (int i = tid; i < a.n_rows * 9; i += kBlock) s_rows[i] = rows[i];
+        const double* rows = reinterpret_cast<const double*>(a.rows);
+        for (int i = tid; i < a.n_shape_rows * 9; i += kBlock) s_rows[i] = rows[i];
     }
 
-    real* partial = reinterpret_cast<real*>(a.partial) + (int64_t)blockIdx.x * a.row_stride;
-    int red_buf = 0;
+    const int wg = wave % G;                 // position inside the wave group
+    real* partial = reinterpret_cast<real*>(a.partial) +
+                    (blk * (kWaves / G) + wave / G) * a.row_stride;
 
     for (int c0 = 0; c0 < a.n_ops; c0 += kOpChunk) {
         const int cn = min(kOpChunk, a.n_ops - c0);
@@ -284,90 +321,131 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) { sp.ar[s] = 0; sp.ai[s] = 0; }
             } else if (kind == OP_SHAPE) {
-                real mx[S], my[S], mz[S];
-                evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
-                // every sub-step: hard sub-pulse, then precession/decay by u and
-                // T1 recovery, all in "operator minus identity" form (see rotate)
+                // Shaped pulse (eq. 3.23): n_sub sub-steps, each a hard
+                // sub-pulse, precession/decay by u and T1 recovery, all in
+                // "operator minus identity" form (see rotate).  The sub-step
+                // state is carried in FP64: each sub-step adds a small
+                // increment to every component, and in FP32 the roundings of
+                // these many small additions are correlated and drift.  With
+                // packed FP32 unused, an FP64 FMA issues at the FP32 rate.
+                real ex[S], ey[S], ez[S];
+                evaluate<real, S>(sp, op, mxy_zero, ex, ey, ez);
+                double mx[S], my[S], mz[S];
                 const double tau = op.u.adc.tau;
-                real dur[S], dui[S], d1[S], m0r[S];
+                double dur[S], dui[S], d1[S], m0d[S];
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    step_delta<real>(phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), tau,
-                                     sp.r2[s], dur[s], dui[s]);
-                    d1[s] = Math<real>::one_minus_expneg(tau, sp.r1[s]);
-                    m0r[s] = (real)sp.m0[s];
+                    mx[s] = ex[s]; my[s] = ey[s]; mz[s] = ez[s];
+                    step_delta<double>(phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), tau,
+                                       sp.r2[s], dur[s], dui[s]);
+                    d1[s] = -expm1(-tau * sp.r1[s]);
+                    m0d[s] = (double)sp.m0[s];
                 }
                 const int n_sub = (int)__builtin_amdgcn_readfirstlane(op.n);
-                const real* rows = s_rows + 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
+                const double* rows = s_rows + 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
                 for (int q = 0; q < n_sub; ++q) {
-                    rotate<real, S>(rows + 9 * q, mx, my, mz);
+                    rotate<double, S>(rows + 9 * q, mx, my, mz);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        real a_ = mx[s], b_ = my[s];
+                        const double a_ = mx[s], b_ = my[s];
                         mx[s] = fma(a_, dur[s], fma(-b_, dui[s], a_));
                         my[s] = fma(a_, dui[s], fma(b_, dur[s], b_));
-                        mz[s] = fma(m0r[s] - mz[s], d1[s], mz[s]);
+                        mz[s] = fma(m0d[s] - mz[s], d1[s], mz[s]);
                     }
                 }
 #pragma unroll
-                for (int s = 0; s < S; ++s) { sp.ar[s] = mx[s]; sp.ai[s] = my[s]; sp.az[s] = mz[s]; }
+                for (int s = 0; s < S; ++s) { sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s]; }
             } else if (kind == OP_ADC) {
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
                 const double tau = op.u.adc.tau;
-                real pr[S], pi[S], zr[S], zi[S], Zr[S], Zi[S], cr[S], ci[S];
+                // this wave's spins: sample 0 (p0), one sample step (z), one
+                // chunk (Z = z^32) and one group stride (W = z^(32 G)), all
+                // from FP64 phases
+                real ap[S][8];
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    // sample 0
                     real e2 = Math<real>::expneg(op.txy, sp.r2[s]);
                     real c, sn;
                     Math<real>::cis(phase_rev(op.k, op.txy, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), c, sn);
-                    pr[s] = e2 * (sp.ar[s] * c + sp.ai[s] * sn);
-                    pi[s] = e2 * (sp.ai[s] * c - sp.ar[s] * sn);
-                    cr[s] = pr[s]; ci[s] = pi[s];
-                    // one sample step and kT sample steps
+                    ap[s][0] = e2 * (sp.ar[s] * c + sp.ai[s] * sn);
+                    ap[s][1] = e2 * (sp.ai[s] * c - sp.ar[s] * sn);
                     const double ph = phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
                     real ez = Math<real>::expneg(tau, sp.r2[s]);
                     Math<real>::cis(ph, c, sn);
-                    zr[s] = ez * c; zi[s] = -ez * sn;
+                    ap[s][2] = ez * c; ap[s][3] = -ez * sn;
                     real eZ = Math<real>::expneg(tau * kT, sp.r2[s]);
                     Math<real>::cis(ph * kT, c, sn);
-                    Zr[s] = eZ * c; Zi[s] = -eZ * sn;
+                    ap[s][4] = eZ * c; ap[s][5] = -eZ * sn;
+                    if constexpr (G > 1) {
+                        real eW = Math<real>::expneg(tau * (kT * G), sp.r2[s]);
+                        Math<real>::cis(ph * (kT * G), c, sn);
+                        ap[s][6] = eW * c; ap[s][7] = -eW * sn;
+                    } else {
+                        ap[s][6] = ap[s][4]; ap[s][7] = ap[s][5];
+                    }
                 }
-                for (int n0 = 0; n0 < n; n0 += kT) {
+                // the wave group's G * S spins (LDS exchange when G > 1)
+                real pr[R], pi[R], zr[R], zi[R], Wr[R], Wi[R];
+                if constexpr (G > 1) {
+                    __syncthreads();             // earlier readers of s_x are done
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) s_x[wave][s][k][lane] = ap[s][k];
+                    __syncthreads();
+                    const int w0 = (wave / G) * G;
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const int sw = w0 + q / S, ss = q % S;
+                        real p_r = s_x[sw][ss][0][lane], p_i = s_x[sw][ss][1][lane];
+                        const real Zr_ = s_x[sw][ss][4][lane], Zi_ = s_x[sw][ss][5][lane];
+                        zr[q] = s_x[sw][ss][2][lane]; zi[q] = s_x[sw][ss][3][lane];
+                        Wr[q] = s_x[sw][ss][6][lane]; Wi[q] = s_x[sw][ss][7][lane];
+                        for (int k = 0; k < wg; ++k) {   // start at chunk wg: p0 Z^wg
+                            const real t = p_r * Zr_ - p_i * Zi_;
+                            p_i = p_r * Zi_ + p_i * Zr_;
+                            p_r = t;
+                        }
+                        pr[q] = p_r; pi[q] = p_i;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const int s = q % S;
+                        pr[q] = ap[s][0]; pi[q] = ap[s][1]; zr[q] = ap[s][2]; zi[q] = ap[s][3];
+                        Wr[q] = ap[s][6]; Wi[q] = ap[s][7];
+                    }
+                }
+                const int n_chunks = (n + kT - 1) / kT;
+                for (int j = wg; j < n_chunks; j += G) {
+                    real qr[R], qi[R];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) { qr[q] = pr[q]; qi[q] = pi[q]; }
                     real acc[2 * kT];
 #pragma unroll
                     for (int t = 0; t < kT; ++t) {
-                        real sr = pr[0], si = pi[0];
+                        real sr = qr[0], si = qi[0];
 #pragma unroll
-                        for (int s = 1; s < S; ++s) { sr += pr[s]; si += pi[s]; }
+                        for (int q = 1; q < R; ++q) { sr += qr[q]; si += qi[q]; }
                         acc[2 * t] = sr; acc[2 * t + 1] = si;
                         if (t + 1 < kT) {
 #pragma unroll
-                            for (int s = 0; s < S; ++s) {
-                                real a_ = pr[s], b_ = pi[s];
-                                pr[s] = a_ * zr[s] - b_ * zi[s];
-                                pi[s] = a_ * zi[s] + b_ * zr[s];
+                            for (int q = 0; q < R; ++q) {
+                                const real a_ = qr[q], b_ = qi[q];
+                                qr[q] = a_ * zr[q] - b_ * zi[q];
+                                qi[q] = a_ * zi[q] + b_ * zr[q];
                             }
                         }
                     }
 #pragma unroll
-                    for (int s = 0; s < S; ++s) {
-                        real a_ = cr[s], b_ = ci[s];
-                        cr[s] = a_ * Zr[s] - b_ * Zi[s];
-                        ci[s] = a_ * Zi[s] + b_ * Zr[s];
-                        pr[s] = cr[s]; pi[s] = ci[s];
+                    for (int q = 0; q < R; ++q) {     // advance G chunks from the anchor
+                        const real a_ = pr[q], b_ = pi[q];
+                        pr[q] = a_ * Wr[q] - b_ * Wi[q];
+                        pi[q] = a_ * Wi[q] + b_ * Wr[q];
                     }
                     const real v = wave_reduce64(acc, lane);
-                    s_red[red_buf][wave][lane] = v;
-                    __syncthreads();
-                    if (wave == 0) {
-                        real sum = s_red[red_buf][0][lane];
-#pragma unroll
-                        for (int w = 1; w < kWaves; ++w) sum += s_red[red_buf][w][lane];
-                        if (n0 + (lane >> 1) < n) partial[2 * (int64_t)(aux + n0) + lane] = sum;
-                    }
-                    red_buf ^= 1;
+                    if (j * kT + (lane >> 1) < n) partial[2 * (int64_t)(aux + j * kT) + lane] = v;
                 }
             }
         }
@@ -385,14 +463,96 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     }
 }
 
+template <typename real, int S>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
+    step_body<real, S>(a, (int64_t)blockIdx.x);
+}
+
+// Persistent form: workgroups take (request, tile) items from a queue until
+// it is empty.  Items are numbered request by request (BatchItem.item_begin
+// is the prefix sum of the requests' tile counts).  Every item writes only
+// its own rows, so which workgroup runs it never changes a result.
+template <typename real, int S>
+__global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req,
+                                                            int64_t total, unsigned long long* counter) {
+    __shared__ unsigned long long s_item;
+    for (;;) {
+        __syncthreads();                     // every wave is done reading s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t item = (int64_t)s_item;
+        if (item >= total) break;            // every wave of the group sees the same value
+        int lo = 0, hi = n_req - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (reqs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const StepArgs a = reqs[lo].args;
+        step_body<real, S>(a, item - reqs[lo].item_begin);
+    }
+}
+
+// Cross-workgroup sum (FP64, fixed order): partial rows are summed in groups
+// of kRowGroup consecutive rows (pass 1), then the group sums in group order
+// (pass 2); with at most kRowGroup rows pass 1 writes the output directly.
+constexpr int64_t kRowGroup = 64;
+
 template <typename real>
-__global__ void finalize_kernel(const real* __restrict__ partial, int64_t n_blocks, int64_t row_stride,
-                                int64_t n_vals, double* __restrict__ out) {
+__global__ void finalize_rows_kernel(const real* __restrict__ partial, int64_t n_rows, int64_t row_stride,
+                                     int64_t n_vals, double* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_vals) return;
+    const int64_t r0 = (int64_t)blockIdx.y * kRowGroup;
+    const int64_t r1 = min(n_rows, r0 + kRowGroup);
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += (double)partial[r * row_stride + j];
+    out[(int64_t)blockIdx.y * n_vals + j] = s;
+}
+
+__global__ void finalize_groups_kernel(const double* __restrict__ mid, int64_t n_groups, int64_t n_vals,
+                                       double* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_vals) return;
     double s = 0.0;
-    for (int64_t b = 0; b < n_blocks; ++b) s += (double)partial[b * row_stride + j];
+    for (int64_t g = 0; g < n_groups; ++g) s += mid[g * n_vals + j];
     out[j] = s;
+}
+
+// Batched finalize: pass 1 over (request, row group, value tile), pass 2
+// over (request, value tile) for requests with more than one row group.
+__device__ __forceinline__ int find_desc(const FinDesc* d, int n, int64_t t, bool pass2) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((pass2 ? d[mid].tile_begin2 : d[mid].tile_begin1) <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename real>
+__global__ void batch_finalize_pass1(const FinDesc* __restrict__ d, int32_t n) {
+    const int64_t t = blockIdx.x;
+    const FinDesc& f = d[find_desc(d, n, t, false)];
+    const int64_t jt = (f.n_vals + 255) / 256;
+    const int64_t local = t - f.tile_begin1;
+    const int64_t g = local / jt;
+    const int64_t j = (local % jt) * 256 + threadIdx.x;
+    if (j >= f.n_vals) return;
+    const real* partial = reinterpret_cast<const real*>(f.partial);
+    const int64_t r0 = g * kRowGroup, r1 = min(f.n_rows, r0 + kRowGroup);
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += (double)partial[r * f.row_stride + j];
+    if (f.n_groups > 1) f.mid[g * f.n_vals + j] = s; else f.out[j] = s;
+}
+
+__global__ void batch_finalize_pass2(const FinDesc* __restrict__ d, int32_t n) {
+    const int64_t t = blockIdx.x;
+    const FinDesc& f = d[find_desc(d, n, t, true)];
+    const int64_t j = (t - f.tile_begin2) * 256 + threadIdx.x;
+    if (f.n_groups <= 1 || j >= f.n_vals) return;
+    double s = 0.0;
+    for (int64_t g = 0; g < f.n_groups; ++g) s += f.mid[g * f.n_vals + j];
+    f.out[j] = s;
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
@@ -405,9 +565,59 @@ __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
 // ---------------------------------------------------------------------------
 template <typename real, int S>
 static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t st) {
-    const size_t dyn = (size_t)a.n_rows * 9 * sizeof(real);
+    const size_t dyn = (size_t)a.n_shape_rows * 9 * sizeof(double);
     hipLaunchKernelGGL((step_kernel<real, S>), dim3((unsigned)n_blocks), dim3(kBlock), dyn, st, a);
     return hipGetLastError();
+}
+
+template <typename real, int S>
+static hipError_t launch_batch_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
+                                 int32_t max_shape_rows, int n_cu, hipStream_t st) {
+    const size_t dyn = (size_t)max_shape_rows * 9 * sizeof(double);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S>, kBlock, dyn) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t grid = std::min<int64_t>(total, (int64_t)per_cu * n_cu);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((batch_step_kernel<real, S>), dim3((unsigned)grid), dim3(kBlock), dyn, st, reqs, n_req,
+                       total, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
+                             int32_t max_shape_rows, int precision, int spins_per_lane, int n_cu, hipStream_t st) {
+    if (precision == 64) {
+        switch (spins_per_lane) {
+            case 1: return launch_batch_t<double, 1>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+            case 2: return launch_batch_t<double, 2>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (spins_per_lane) {
+        case 1: return launch_batch_t<float, 1>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+        case 2: return launch_batch_t<float, 2>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+        case 4: return launch_batch_t<float, 4>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+        case 8: return launch_batch_t<float, 8>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
+                                 hipStream_t st) {
+    if (tiles1 > 0) {
+        if (precision == 64)
+            hipLaunchKernelGGL(batch_finalize_pass1<double>, dim3((unsigned)tiles1), dim3(256), 0, st, d, n);
+        else
+            hipLaunchKernelGGL(batch_finalize_pass1<float>, dim3((unsigned)tiles1), dim3(256), 0, st, d, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (tiles2 > 0) {
+        hipLaunchKernelGGL(batch_finalize_pass2, dim3((unsigned)tiles2), dim3(256), 0, st, d, n);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 int64_t spins_per_block_of(int spins_per_lane) { return (int64_t)kBlock * spins_per_lane; }
@@ -431,17 +641,32 @@ hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int
     }
 }
 
-hipError_t launch_finalize(const void* partial, int precision, int64_t n_blocks, int64_t row_stride,
-                           int64_t n_vals, double* out, hipStream_t st) {
+int64_t row_group_size() { return kRowGroup; }
+
+int64_t finalize_scratch_doubles(int64_t n_rows, int64_t n_vals) {
+    const int64_t groups = (n_rows + kRowGroup - 1) / kRowGroup;
+    return groups > 1 ? groups * n_vals : 0;
+}
+
+hipError_t launch_finalize(const void* partial, int precision, int64_t n_rows, int64_t row_stride,
+                           int64_t n_vals, double* out, double* scratch, hipStream_t st) {
     if (n_vals <= 0) return hipSuccess;
     const int threads = 256;
-    const int64_t grid = (n_vals + threads - 1) / threads;
+    const int64_t gx = (n_vals + threads - 1) / threads;
+    const int64_t groups = (n_rows + kRowGroup - 1) / kRowGroup;
+    double* dst = groups > 1 ? scratch : out;
+    if (groups > 1 && !scratch) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)gx, (unsigned)std::max<int64_t>(groups, 1));
     if (precision == 64)
-        hipLaunchKernelGGL(finalize_kernel<double>, dim3((unsigned)grid), dim3(threads), 0, st,
-                           reinterpret_cast<const double*>(partial), n_blocks, row_stride, n_vals, out);
+        hipLaunchKernelGGL(finalize_rows_kernel<double>, grid, dim3(threads), 0, st,
+                           reinterpret_cast<const double*>(partial), n_rows, row_stride, n_vals, dst);
     else
-        hipLaunchKernelGGL(finalize_kernel<float>, dim3((unsigned)grid), dim3(threads), 0, st,
-                           reinterpret_cast<const float*>(partial), n_blocks, row_stride, n_vals, out);
+        hipLaunchKernelGGL(finalize_rows_kernel<float>, grid, dim3(threads), 0, st,
+                           reinterpret_cast<const float*>(partial), n_rows, row_stride, n_vals, dst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || groups <= 1) return e;
+    hipLaunchKernelGGL(finalize_groups_kernel, dim3((unsigned)gx), dim3(threads), 0, st, scratch, groups,
+                       n_vals, out);
     return hipGetLastError();
 }
 

@@ -12,22 +12,52 @@ struct StepArgs {
     int64_t n_spins;
     const Op* ops;           // device, this time slice's operations
     int32_t n_ops;
-    int32_t n_rows;          // shaped-pulse rotation rows (9 reals each)
-    const void* rows;        // device, n_rows * 9 reals of the kernel precision
-    void* partial;           // device, gridDim.x rows of row_stride reals
+    int32_t n_shape_rows;    // shaped-pulse rotation rows (9 doubles each)
+    const void* rows;        // device, n_shape_rows * 9 doubles (rotation deltas)
+    void* partial;           // device, gridDim.x * rows_per_block rows of row_stride reals
     int64_t row_stride;      // reals per workgroup row (2 per sample of the slice)
     void* state;             // device, 3 * n_spins reals (Mxy_a re, im, Mz_a), SoA
     int32_t load_state;      // resume from state instead of equilibrium
     int32_t save_state;      // write the anchors back at the end
 };
 
+// One request of a persistent batched launch: its arguments and the number
+// of the first of its tiles in the launch's item sequence.
+struct alignas(16) BatchItem {
+    StepArgs args;
+    int64_t item_begin;
+    int64_t n_items;
+};
+
+// One request of a batched finalize.
+struct alignas(16) FinDesc {
+    const void* partial;     // n_rows rows of row_stride reals
+    int64_t n_rows, row_stride, n_vals;
+    int64_t n_groups;        // row groups (pass 2 needed when > 1)
+    double* out;             // n_vals doubles
+    double* mid;             // n_groups * n_vals doubles when n_groups > 1
+    int64_t tile_begin1;     // first pass-1 block (n_groups * ceil(n_vals/256) blocks)
+    int64_t tile_begin2;     // first pass-2 block (ceil(n_vals/256) blocks if n_groups > 1, else 0)
+};
+
 // Spins handled by one workgroup for a given spins-per-lane choice.
 int64_t spins_per_block_of(int spins_per_lane);
+// Partial-sum rows one workgroup writes (one per wave group).
+int64_t rows_per_block_of(int spins_per_lane);
 
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
                        hipStream_t st);
-hipError_t launch_finalize(const void* partial, int precision, int64_t n_blocks, int64_t row_stride,
-                           int64_t n_vals, double* out, hipStream_t st);
+// Doubles of scratch launch_finalize needs for n_rows rows of n_vals values.
+int64_t finalize_scratch_doubles(int64_t n_rows, int64_t n_vals);
+hipError_t launch_finalize(const void* partial, int precision, int64_t n_rows, int64_t row_stride,
+                           int64_t n_vals, double* out, double* scratch, hipStream_t st);
 hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t st);
+// Persistent launch over total items of the n_req requests in reqs (device);
+// counter (device) must hold 0.
+hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
+                             int32_t max_shape_rows, int precision, int spins_per_lane, int n_cu, hipStream_t st);
+hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
+                                 hipStream_t st);
+int64_t row_group_size();
 
 }  // namespace ps

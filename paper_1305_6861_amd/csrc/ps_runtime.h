@@ -44,8 +44,9 @@ struct Ctx {
     ps_config cfg{};
     int n_cu = 256;
     std::mutex mu;                 // serialises calls on one context
-    DevBuf ops, rows, partial, state;
-    HostBuf staging;
+    DevBuf ops, rows, partial, state, fin_scratch;
+    DevBuf batch_tables, batch_records;   // ps_simulate_batch
+    HostBuf staging, staging2;
     hipEvent_t done = nullptr;     // completion of the last request's work
     bool pending = false;
     // kernel timing (PS_CFG_KERNEL_TIMING): event pairs around launches
@@ -57,7 +58,7 @@ struct Ctx {
 int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins);
 hipEvent_t timing_event(Ctx* ctx);  // from the pool (timing-enabled contexts)
 ps_status validate_object(const ps_object* obj);
-ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_blocks, Program* prog);
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, Program* prog);
 ps_status wait_previous(Ctx* ctx);
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
                       int64_t n_samples, hipStream_t stream, int S_override);
