@@ -149,6 +149,57 @@ ps_status ps_simulate(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq,
 ps_status ps_simulate_batch(ps_ctx *ctx, int32_t n_requests, const ps_object *objs, const ps_sequence *seqs,
                             double *const *signals, const int64_t *n_samples, void *stream);
 
+/* ---- served execution ------------------------------------------------
+ * A scheduler thread (started by the first ps_submit on a context) admits
+ * queued requests in submission order while the sum of their device
+ * footprints stays under ps_config.max_footprint_bytes, and advances every
+ * admitted request by one time slice per iteration in one batched round, so
+ * requests that arrive while others run join at the next iteration
+ * (continuous batching; after the master / compute-node / superposition
+ * roles of sections 5.3.2 and 6.3).  Spin state stays in device memory
+ * between slices.  A request's result is bitwise the same alone or in any
+ * mix.  The object arrays must hold their data when ps_submit is called (no
+ * ordering with the caller's streams); signal must not be read before
+ * ps_poll / ps_wait report completion. */
+
+typedef enum ps_request_state {
+    PS_REQ_QUEUED = 0, PS_REQ_RUNNING = 1, PS_REQ_DONE = 2, PS_REQ_FAILED = 3, PS_REQ_CANCELLED = 4
+} ps_request_state;
+
+typedef struct ps_request_info_t {
+    int32_t state;               /* ps_request_state                                   */
+    int32_t status;              /* final ps_status (PS_OK while not finished)         */
+    double  t_submit, t_admit, t_done;  /* s since the scheduler started; -1 = not yet */
+    int64_t n_slices;            /* time slices the request runs as                    */
+    int64_t footprint_bytes;     /* counted against the admission cap                  */
+    int64_t n_spins, n_steps_per_spin;
+} ps_request_info_t;
+
+typedef struct ps_server_stats_t {
+    int64_t iterations, queued, running, footprint_in_use;
+    double  now;                 /* s since the scheduler started                      */
+} ps_server_stats_t;
+
+/* Queue one request; arguments as for ps_simulate.  Validates and compiles
+ * on the calling thread.  PS_E_TOO_LARGE when the request alone exceeds the
+ * admission cap.  *ticket identifies it in the calls below.  Thread-safe. */
+ps_status ps_submit(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, double *signal,
+                    int64_t n_samples, uint64_t *ticket);
+/* *done = 1 once the request has finished (completed, failed or cancelled). */
+ps_status ps_poll(ps_ctx *ctx, uint64_t ticket, int32_t *done);
+/* Block until the request finishes (timeout_s < 0: no limit).  Returns its
+ * final status, or PS_E_NOT_READY on timeout. */
+ps_status ps_wait(ps_ctx *ctx, uint64_t ticket, double timeout_s);
+/* Cancel: a queued request is dropped, a running one at the next iteration
+ * boundary (its signal is then undefined).  Other requests are unaffected. */
+ps_status ps_cancel(ps_ctx *ctx, uint64_t ticket);
+/* State, status and timing of a request. */
+ps_status ps_request_info(ps_ctx *ctx, uint64_t ticket, ps_request_info_t *out);
+/* Forget a finished request's record (PS_E_NOT_READY while in flight). */
+ps_status ps_release(ps_ctx *ctx, uint64_t ticket);
+/* Scheduler counters (all zero before the first ps_submit). */
+ps_status ps_server_stats(ps_ctx *ctx, ps_server_stats_t *out);
+
 /* The tiling ps_simulate uses for an object of n_spins spins on this
  * context: spins held per lane (the autotuned or configured value) and
  * spins per workgroup (4 waves of 64 lanes). */

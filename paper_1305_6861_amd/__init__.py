@@ -28,7 +28,7 @@ from ._binding import PsError, PS_EV_SPOIL
 
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
-__all__ = ["Context", "PsError", "PS_EV_SPOIL", "count", "pack_sequence", "to_device", "FIELDS"]
+__all__ = ["Context", "Ticket", "PsError", "PS_EV_SPOIL", "count", "pack_sequence", "to_device", "FIELDS"]
 
 
 class PackedSequence:
@@ -196,6 +196,30 @@ class Context:
                                           ctypes.c_void_p(stream.cuda_stream)))
         return [o.view(torch.complex128) for o in outs]
 
+    # ---- served execution -------------------------------------------------
+    def submit(self, obj, seq):
+        """Queue a request on the context's scheduler; returns a Ticket.  The
+        object's device arrays are made ready (current stream synchronised)
+        before submission; the output tensor is owned by the ticket."""
+        import torch
+        owned = not (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
+                                                   for f in FIELDS))
+        dev = to_device(obj, f"cuda:{self.device}") if owned else obj
+        torch.cuda.current_stream(self.device).synchronize()
+        ps = pack_sequence(seq)
+        ns, _ = ps.count()
+        out = torch.empty(2 * ns, dtype=torch.float64, device=f"cuda:{self.device}")
+        o = _object_struct(dev)
+        t = ctypes.c_uint64()
+        _b.check(_b.lib.ps_submit(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                  ctypes.c_void_p(out.data_ptr() if ns else 0), ns, ctypes.byref(t)))
+        return Ticket(self, int(t.value), out, dev)
+
+    def server_stats(self):
+        st = _b.ps_server_stats_t()
+        _b.check(_b.lib.ps_server_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
     def simulate(self, obj, seq, out=None, stream=None):
         """Signal of one request as a complex128 CUDA tensor (stream-ordered
         on `stream`, default torch's current stream)."""
@@ -219,3 +243,34 @@ class Context:
                                     ctypes.c_void_p(out.data_ptr() if n_samples else 0),
                                     n_samples, ctypes.c_void_p(stream.cuda_stream)))
         return out.view(torch.complex128)
+
+
+class Ticket:
+    """Handle of a served request (keeps its device arrays alive)."""
+
+    def __init__(self, ctx: Context, ticket: int, out, dev):
+        self.ctx, self.ticket, self._out, self._dev = ctx, ticket, out, dev
+
+    def done(self) -> bool:
+        d = ctypes.c_int32()
+        _b.check(_b.lib.ps_poll(self.ctx._h, self.ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, timeout_s: float = -1.0):
+        """Block until finished; returns the signal (complex128 CUDA tensor)
+        or raises PsError with the request's failure status."""
+        _b.check(_b.lib.ps_wait(self.ctx._h, self.ticket, float(timeout_s)))
+        return self._out.view(__import__("torch").complex128)
+
+    def cancel(self):
+        _b.check(_b.lib.ps_cancel(self.ctx._h, self.ticket))
+
+    def info(self) -> dict:
+        i = _b.ps_request_info()
+        _b.check(_b.lib.ps_request_info(self.ctx._h, self.ticket, ctypes.byref(i)))
+        d = {f: getattr(i, f) for f, _ in i._fields_}
+        d["state"] = _b.REQ_STATES.get(d["state"], d["state"])
+        return d
+
+    def release(self):
+        _b.check(_b.lib.ps_release(self.ctx._h, self.ticket))

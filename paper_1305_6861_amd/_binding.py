@@ -61,6 +61,20 @@ assert ctypes.sizeof(ps_event) == 64
 assert ctypes.sizeof(ps_rf_shape) == 56
 assert ctypes.sizeof(ps_config) == 32
 
+class ps_request_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("n_slices", ctypes.c_int64),
+                ("footprint_bytes", ctypes.c_int64), ("n_spins", ctypes.c_int64),
+                ("n_steps_per_spin", ctypes.c_int64)]
+
+
+class ps_server_stats_t(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("footprint_in_use", ctypes.c_int64), ("now", ctypes.c_double)]
+
+
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "ps_config_default": (ctypes.c_int, [ctypes.POINTER(ps_config)]),
@@ -74,6 +88,14 @@ SIGNATURES = {
     "ps_simulate_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ps_object),
                                          ctypes.POINTER(ps_sequence), ctypes.POINTER(ctypes.c_void_p),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "ps_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
+                                 ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]),
+    "ps_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "ps_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double]),
+    "ps_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ps_request_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ps_request_info)]),
+    "ps_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ps_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_server_stats_t)]),
     "ps_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int64)]),
     "ps_simulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
