@@ -31,6 +31,146 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak (published)
 FLOPS_ADC_SAMPLE = 8          # p <- p z (complex multiply) and accumulate
 FLOPS_HARD_RF = 15            # 3x3 rotation of (Mx, My, Mz), eq. 3.19
 FLOPS_SHAPE_SUBSTEP = 23      # rotation + complex precession/decay + Mz recovery
+def bench_c4(args):
+    """64 uneven requests: one batched call vs one launch per request."""
+    import torch
+    import paper_1305_6861_amd as ps
+    from workloads import configs as C
+    reqs = C.c4(64)
+    devs = [ps.to_device(o) for o, _ in reqs]
+    packs = [ps.pack_sequence(s) for _, s in reqs]
+    spin_steps = float(sum(o.n_spins * s.n_steps_per_spin for o, s in reqs))
+    ctx = ps.Context()
+    outs = [torch.empty(2 * s.n_samples, dtype=torch.float64, device="cuda") for _, s in reqs]
+
+    def one_per_launch():
+        for d, p, o in zip(devs, packs, outs):
+            ctx.simulate(d, p, out=o)
+
+    def batched():
+        return ctx.simulate_batch(devs, packs)
+
+    res = {}
+    for name, fn in (("one_per_launch", one_per_launch), ("batched", batched)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+    rec = {"metric": "spin-steps/s", "value": spin_steps / res["batched"], "unit": "spin-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["batched"] * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "c4: 64 requests, 2-D N^2 (N log-uniform 16..256), GRE or SE, "
+                                  "U{32..256} phase encodes x N samples, per-request seeds",
+                      "spin_steps": spin_steps},
+           "one_per_launch_ms": res["one_per_launch"] * 1e3,
+           "speedup_vs_one_per_launch": res["one_per_launch"] / res["batched"],
+           "roofline": None, "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        import oracle
+        got = [t.cpu().numpy() for t in batched()]
+        t0 = time.perf_counter()
+        errs = [oracle.rel_l2(g, oracle.simulate(o, s)) for g, (o, s) in zip(got, reqs)]
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": spin_steps / dt, "unit": "spin-steps/s", "cores": oracle.default_threads(),
+                               "kind": "oracle", "sample": "all 64 requests", "gpu_worst_rel_l2": max(errs)}
+    print(json.dumps(rec), flush=True)
+
+
+def bench_c5(args):
+    """Poisson stream: served (continuous batching) vs FIFO one launch per
+    request, both replaying the same arrival schedule in real time."""
+    import numpy as np
+    import torch
+    import paper_1305_6861_amd as ps
+    from workloads import configs as C
+    sched = C.c5_stream(n_requests=args.c5_requests)
+    reqs = [C.c5_request(kind, param) for _, kind, param in sched]
+    devs = [ps.to_device(o) for o, _ in reqs]
+    packs = [ps.pack_sequence(s) for _, s in reqs]
+    torch.cuda.synchronize()
+    spin_steps = float(sum(o.n_spins * s.n_steps_per_spin for o, s in reqs))
+    arrivals = np.array([t for t, _, _ in sched])
+    is3d = np.array([k == "3d" for _, k, _ in sched])
+
+    def replay(submit, finish_all):
+        t0 = time.perf_counter()
+        handles = []
+        for i, t_arr in enumerate(arrivals):
+            now = time.perf_counter() - t0
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            handles.append(submit(i, time.perf_counter() - t0))
+        done = finish_all(handles, t0)
+        return done, time.perf_counter() - t0
+
+    # served
+    ctx = ps.Context()
+    def s_submit(i, t):
+        return (t, ctx.submit(devs[i], packs[i]))
+    def s_finish(handles, t0):
+        lat = []
+        for t_sub, h in handles:
+            h.wait(-1.0)
+            inf = h.info()
+            lat.append(inf["t_done"] - inf["t_submit"])
+        return np.array(lat)
+    lat_s, wall_s = replay(s_submit, s_finish)
+    served_iters = ctx.server_stats()["iterations"]
+    ctx.close()
+    # FIFO one launch per request: a worker thread runs requests in arrival order
+    import queue, threading
+    ctx2 = ps.Context()
+    q = queue.Queue()
+    lat_f = np.zeros(len(reqs))
+    stream = torch.cuda.Stream()
+    def worker(t0_holder):
+        with torch.cuda.stream(stream):
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                i, t_sub = item
+                out = ctx2.simulate(devs[i], packs[i], stream=stream)
+                stream.synchronize()
+                lat_f[i] = time.perf_counter() - t0_holder[0] - t_sub
+    t0h = [0.0]
+    th = threading.Thread(target=worker, args=(t0h,))
+    th.start()
+    def f_submit(i, t):
+        if i == 0:
+            t0h[0] = time.perf_counter() - t
+        q.put((i, t))
+        return i
+    def f_finish(handles, t0):
+        q.put(None)
+        th.join()
+        return lat_f
+    lat_f, wall_f = replay(f_submit, f_finish)
+    ctx2.close()
+
+    def pct(a, p):
+        return float(np.percentile(a, p) * 1e3)
+    rec = {"metric": "spin-steps/s", "value": spin_steps / wall_s, "unit": "spin-steps/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": wall_s * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"c5: Poisson stream of {len(reqs)} requests at 50/s, "
+                                  f"{int(is3d.sum())} of them 3-D 2x64^3 sinc GRE, the rest c4-type",
+                      "spin_steps": spin_steps},
+           "served": {"wall_s": wall_s, "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
+                      "p50_2d_ms": pct(lat_s[~is3d], 50), "p99_2d_ms": pct(lat_s[~is3d], 99),
+                      "p50_3d_ms": pct(lat_s[is3d], 50) if is3d.any() else None,
+                      "iterations": served_iters},
+           "fifo_one_per_launch": {"wall_s": wall_f, "p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
+                                   "p50_2d_ms": pct(lat_f[~is3d], 50), "p99_2d_ms": pct(lat_f[~is3d], 99)},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(rec), flush=True)
+
+
 WORKLOADS = {
     "c2": ("c2: 2-D 256x256 grid, 4 jittered isochromats/voxel (262,144 spins), "
            "spin echo 90x/180y TE 20 ms TR 500 ms, 256 phase encodes x 256 samples"),
@@ -118,8 +258,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--spins-per-lane", type=int, default=0, help="0 = autotuned")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
-                    help="c2 (default, the reported workload) or c3 (the 3-D shaped-pulse configuration)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5"], default="c2",
+                    help="c2 (default, the reported workload), c3 (3-D shaped-pulse configuration), "
+                         "c4 (batched vs one launch per request), c5 (served stream vs FIFO)")
+    ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,6 +277,11 @@ def main():
               "(the spin domain would shard across GPUs with one reduction of the partial signals, "
               "which is not built here)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
 
     import torch
     import paper_1305_6861_amd as ps
