@@ -48,13 +48,20 @@ typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
 /* ps_config.flags: bracket every step-kernel and finalize-kernel launch with
  * HIP events on its stream so that ps_kernel_times() can report durations. */
 #define PS_CFG_KERNEL_TIMING 1u
+/* ps_config.flags: step every shaped pulse sub-step by sub-step.  By default a
+ * shaped pulse that recurs within a time slice is stepped once per spin into
+ * the affine map it applies (every sub-step of eq. 3.23 is affine in M), and
+ * later occurrences apply that map, rotated by their RF phase offset.  Both
+ * give the same signal within FP32 rounding; this flag exists to measure and
+ * test the sub-step path on sequences with repeated shapes. */
+#define PS_CFG_NO_SHAPE_CACHE 2u
 
 typedef struct ps_config {
     int32_t device;              /* HIP device ordinal                                 */
     int32_t precision;           /* 32: FP32 stepping (FP64 phases and cross-block
                                     sums); 64: FP64 throughout                         */
     int32_t spins_per_lane;      /* 0 = autotuned; else 1, 2, 4 or 8 (FP64: 1 or 2)    */
-    int32_t flags;               /* PS_CFG_KERNEL_TIMING                               */
+    int32_t flags;               /* PS_CFG_KERNEL_TIMING | PS_CFG_NO_SHAPE_CACHE       */
     int64_t max_partial_bytes;   /* bound on the per-block partial-sum buffer; longer
                                     sequences run in time slices (0 = default 512 MiB) */
     int64_t max_footprint_bytes; /* admission cap for served requests (0 = 64 GiB)     */

@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID_ARG", 2: "PS_E_NO_MEMORY", 3: "PS_E
                 4: "PS_E_TOO_LARGE", 5: "PS_E_NOT_READY", 6: "PS_E_CANCELLED", 7: "PS_E_NO_DEVICE"}
 PS_EV_SPOIL = 1
 PS_CFG_KERNEL_TIMING = 1
+PS_CFG_NO_SHAPE_CACHE = 2
 
 
 class PsError(RuntimeError):

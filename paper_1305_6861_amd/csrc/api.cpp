@@ -79,9 +79,12 @@ int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins) {
     if (ctx->cfg.spins_per_lane > 0) return ctx->cfg.spins_per_lane;
     // Keep at least ~2 waves per SIMD (2 x 1024 SIMDs) while giving each lane
     // as many spins as possible: more spins per lane amortise the per-sample
-    // lane-sum + butterfly reduction.
+    // lane-sum + butterfly reduction.  Readouts run 8 spins per lane from
+    // S = 2 on (wave groups of 4 at S = 2, of 2 at S = 4), and S = 4 no longer
+    // fits two waves per SIMD in registers, nor its propagator slots in LDS,
+    // so the automatic choice stops at 2.
     const int64_t target_waves = 2 * 4 * (int64_t)std::max(ctx->n_cu, 1);
-    const int maxS = ctx->cfg.precision == 64 ? 2 : 4;
+    const int maxS = 2;
     int S = 1;
     while (S < maxS && n_spins >= (int64_t)(2 * S) * 64 * target_waves) S *= 2;
     return S;
@@ -106,8 +109,14 @@ ps_status validate_object(const ps_object* obj) {
     return PS_OK;
 }
 
-// Compile + slice a request for a given number of partial-sum rows.
-ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, Program* prog) {
+int shape_cache_slots(const Ctx* ctx, int S, const Program& prog) {
+    if (ctx->cfg.flags & PS_CFG_NO_SHAPE_CACHE) return 0;
+    return shape_cache_slots_fitting(ctx->cfg.precision, S, (int32_t)(prog.rows.size() / 9));
+}
+
+// Compile + slice a request for a given number of partial-sum rows and
+// spins per lane.
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog) {
     std::string err;
     ps_status st = compile_sequence(seq, prog, &err);
     if (st != PS_OK) return fail(st, err);
@@ -116,6 +125,7 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, Progra
     int64_t max_samples = ctx->cfg.max_partial_bytes / per_sample;
     if (max_samples < 64) max_samples = 64;
     plan_slices(prog, max_samples);
+    assign_shape_slots(prog, shape_cache_slots(ctx, S, *prog));
     if (ctx->cfg.precision != 64) narrow_rotations(&prog->ops);
     return PS_OK;
 }
@@ -156,7 +166,7 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     const int64_t n_blocks = (obj->n_spins + spb - 1) / spb;
     const int64_t n_rows = n_blocks * rows_per_block_of(S);
     Program prog;
-    if ((st = prepare(ctx, seq, n_rows, &prog)) != PS_OK) return st;
+    if ((st = prepare(ctx, seq, n_rows, S, &prog)) != PS_OK) return st;
     if (n_samples != prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
                                           std::to_string(prog.n_samples));
@@ -197,6 +207,7 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
         a.n_ops = (int32_t)(sl.op_end - sl.op_begin);
         a.load_state = i > 0;
         a.save_state = i + 1 < prog.slices.size();
+        a.n_cache_slots = sl.n_cache_slots;
         hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
         if (timing) {
             t0 = timing_event(ctx); t1 = timing_event(ctx); t2 = timing_event(ctx);

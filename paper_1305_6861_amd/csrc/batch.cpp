@@ -36,7 +36,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
     const int64_t spb = spins_per_block_of(p->S);
     p->n_blocks = (obj->n_spins + spb - 1) / spb;
     p->n_rows = p->n_blocks * rows_per_block_of(p->S);
-    if ((st = prepare(ctx, seq, p->n_rows, &p->prog)) != PS_OK) return st;
+    if ((st = prepare(ctx, seq, p->n_rows, p->S, &p->prog)) != PS_OK) return st;
     if (max_slice_steps > 0) {
         // a second bound for serving: at most max_slice_steps intervals per
         // spin per slice, so that long requests yield the device regularly
@@ -71,6 +71,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
             out.push_back(cur);
         }
         g.slices = std::move(out);
+        assign_shape_slots(&g, shape_cache_slots(ctx, p->S, g));
     }
     if (n_samples != p->prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
@@ -118,6 +119,7 @@ StepArgs ReqPlan::args_for_slice(size_t k) const {
     a.state = d_state;
     a.load_state = k > 0;
     a.save_state = k + 1 < prog.slices.size();
+    a.n_cache_slots = sl.n_cache_slots;
     return a;
 }
 
@@ -129,7 +131,7 @@ struct RoundImage {
         size_t counter_off;             // offset of its queue counter
         int32_t n_req;
         int64_t total;
-        int32_t max_shape_rows;
+        size_t dyn_lds;                 // largest dynamic LDS of its requests
     };
     std::vector<Class> classes;
     size_t fin_off = 0;
@@ -165,7 +167,7 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
             c.items_off = reserve_bytes(sizeof(BatchItem) * kv.second.size());
             c.counter_off = reserve_bytes(sizeof(unsigned long long));
             int64_t total = 0;
-            int32_t msr = 0;
+            size_t dyn = 0;
             for (size_t q = 0; q < kv.second.size(); ++q) {
                 ReqPlan* p = plans[kv.second[q]];
                 BatchItem it;
@@ -174,11 +176,12 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
                 it.item_begin = total;
                 it.n_items = p->n_blocks;
                 total += p->n_blocks;
-                msr = std::max(msr, it.args.n_shape_rows);
+                dyn = std::max(dyn, step_dyn_lds_bytes(ctx->cfg.precision, c.S, it.args.n_shape_rows,
+                                                       it.args.n_cache_slots));
                 std::memcpy(img.data() + c.items_off + q * sizeof(BatchItem), &it, sizeof(it));
             }
             c.total = total;
-            c.max_shape_rows = msr;
+            c.dyn_lds = dyn;
             std::memset(img.data() + c.counter_off, 0, sizeof(unsigned long long));
             R.classes.push_back(c);
         }
@@ -234,7 +237,7 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
         const RoundImage& R = rounds[k];
         for (const RoundImage::Class& c : R.classes) {
             e = launch_batch_step(reinterpret_cast<const BatchItem*>(dev + c.items_off), c.n_req, c.total,
-                                  reinterpret_cast<unsigned long long*>(dev + c.counter_off), c.max_shape_rows,
+                                  reinterpret_cast<unsigned long long*>(dev + c.counter_off), c.dyn_lds,
                                   ctx->cfg.precision, c.S, ctx->n_cu, stream);
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
         }

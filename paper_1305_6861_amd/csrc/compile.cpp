@@ -9,6 +9,7 @@
 #include "compile.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <utility>
@@ -71,7 +72,7 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
     double K[3] = {0, 0, 0};
     double txy = 0, tz = 0;
     bool mxy_zero = true;
-    std::map<std::pair<int32_t, uint64_t>, uint32_t> row_cache;
+    std::map<int32_t, uint32_t> row_of_shape;   // first row of each shape's block
 
     for (int64_t e = 0; e < seq->n_events; ++e) {
         const ps_event& ev = seq->events[e];
@@ -92,27 +93,32 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
 
         if (ev.rf_shape >= 0) {
             const ps_rf_shape& sh = seq->shapes[ev.rf_shape];
-            uint64_t bits;
-            std::memcpy(&bits, &ev.rf_phase, sizeof(bits));
-            auto key = std::make_pair(ev.rf_shape, bits);
-            auto it = row_cache.find(key);
+            auto it = row_of_shape.find(ev.rf_shape);
             uint32_t first;
-            if (it == row_cache.end()) {
+            if (it == row_of_shape.end()) {
                 first = (uint32_t)(p.rows.size() / 9);
                 for (int32_t q = 0; q < sh.n_sub; ++q) {
                     double r[9];
-                    rf_delta(sh.alpha[q], sh.phase[q] + ev.rf_phase, r);
+                    rf_delta(sh.alpha[q], sh.phase[q], r);
                     p.rows.insert(p.rows.end(), r, r + 9);
                 }
-                row_cache.emplace(key, first);
+                row_of_shape.emplace(ev.rf_shape, first);
             } else {
                 first = it->second;
             }
             Op op = blank_op(OP_SHAPE);
             std::memcpy(op.k, K, sizeof(K));
             op.txy = txy; op.tz = tz;
-            op.u.adc.mu[0] = sh.m_sub[0]; op.u.adc.mu[1] = sh.m_sub[1]; op.u.adc.mu[2] = sh.m_sub[2];
-            op.u.adc.tau = sh.tau;
+            op.u.shape.mu[0] = sh.m_sub[0]; op.u.shape.mu[1] = sh.m_sub[1]; op.u.shape.mu[2] = sh.m_sub[2];
+            op.u.shape.tau = sh.tau;
+            op.u.shape.rot[0] = 1.0; op.u.shape.rot[1] = 0.0;
+            if (ev.rf_phase != 0.0) {
+                op.u.shape.rot[0] = std::cos(ev.rf_phase);
+                op.u.shape.rot[1] = std::sin(ev.rf_phase);
+            }
+            op.u.shape.slot = -1;
+            op.u.shape.mode = SHAPE_DIRECT;
+            op.u.shape.shape_id = ev.rf_shape;
             op.n = (uint32_t)sh.n_sub;
             op.aux = first;
             op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
@@ -209,6 +215,44 @@ void plan_slices(Program* p, int64_t max_samples) {
     cur.n_samples = sample - cur.sample_begin;
     if (cur.op_end > cur.op_begin || p->slices.empty()) p->slices.push_back(cur);
     p->ops = std::move(ops);
+}
+
+// Filling a slot steps four vectors through the sub-steps instead of one,
+// so a shape pays off from its fifth occurrence in a slice.
+constexpr int64_t kMinShapeRepeats = 5;
+
+void assign_shape_slots(Program* p, int max_slots) {
+    max_slots = std::max(0, std::min(max_slots, kShapeSlots));
+    for (Slice& sl : p->slices) {
+        // shapes that recur often enough in the slice, most frequent first
+        std::map<int32_t, int64_t> count;
+        std::vector<int32_t> order;
+        for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
+            const Op& op = p->ops[i];
+            if (op.kind != OP_SHAPE) continue;
+            if (count[op.u.shape.shape_id]++ == 0) order.push_back(op.u.shape.shape_id);
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return count[a] > count[b]; });
+        std::map<int32_t, int32_t> slot_of;
+        for (int32_t id : order)
+            if (count[id] >= kMinShapeRepeats && (int)slot_of.size() < max_slots) {
+                const int32_t slot = (int32_t)slot_of.size();
+                slot_of[id] = slot;
+            }
+        sl.n_cache_slots = (int32_t)slot_of.size();
+        std::vector<bool> filled(kShapeSlots, false);
+        for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
+            Op& op = p->ops[i];
+            if (op.kind != OP_SHAPE) continue;
+            auto& sh = op.u.shape;
+            auto it = slot_of.find(sh.shape_id);
+            if (it == slot_of.end()) { sh.slot = -1; sh.mode = SHAPE_DIRECT; continue; }
+            sh.slot = it->second;
+            sh.mode = filled[sh.slot] ? SHAPE_APPLY : SHAPE_FILL;
+            filled[sh.slot] = true;
+        }
+    }
 }
 
 void narrow_rotations(std::vector<Op>* ops) {

@@ -14,6 +14,7 @@ struct Slice {
     int64_t op_begin = 0, op_end = 0;  // operation range of the slice
     int64_t sample_begin = 0;          // index of the slice's first sample
     int64_t n_samples = 0;
+    int32_t n_cache_slots = 0;         // shaped-pulse propagator slots its ops use
 };
 
 struct Program {
@@ -39,6 +40,13 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
 // (ADC operations longer than that are split exactly), setting every ADC
 // op's offset inside its slice.  max_samples >= 1.
 void plan_slices(Program* p, int64_t max_samples);
+
+// Give every shape that occurs often (at least five times) in a time slice a
+// propagator cache slot (at most max_slots <= kShapeSlots per slice, the
+// most frequent shapes first): its first occurrence in the slice fills the
+// slot, later ones apply it.  Other SHAPE ops (all of them when max_slots is
+// 0) step their sub-steps directly.  Run after the slices are final.
+void assign_shape_slots(Program* p, int max_slots);
 
 // Copy of the ops with rotations narrowed to FP32 (precision 32 tables).
 void narrow_rotations(std::vector<Op>* ops);

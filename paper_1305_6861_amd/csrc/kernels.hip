@@ -36,6 +36,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ps_kernels.h"
 #include "ps_ops.h"
@@ -247,6 +248,94 @@ __device__ __forceinline__ void step_delta(double c, double tau, double r2, real
     di = (real)(-2.0 * e2 * s1 * c1);
 }
 
+// LDS of a step workgroup outside the dynamic part (s_ops, s_x below).
+template <typename real, int S>
+constexpr size_t static_lds_bytes() {
+    constexpr int G = ReadoutShare<S>::G;
+    return sizeof(Op) * kOpChunk + sizeof(real) * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 8 * 64 +
+           sizeof(real) * S * 6 * kBlock;
+}
+
+// Shaped-pulse propagator of every spin of this lane (see ps_ops.h): the
+// sub-steps of the direct path are applied in FP64 to the three columns of
+// the identity (the linear part A) and to the zero vector with the T1 source
+// term (the offset b), and the result is stored, narrowed to real, into the
+// lane's slot entries: entry k of spin s at cache[(k * S + s) * kBlock].
+// Calls f(std::integral_constant<int, I>()) for I = B .. E-1: a loop whose
+// index is a compile-time constant even where the body holds a run-time loop
+// (an unroll pragma may leave such a loop rolled, and a run-time index into
+// the per-lane spin arrays would move them to scratch memory).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>());
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <typename real, int S>
+__device__ __forceinline__ void shape_fill(const Spins<real, S>& sp, const Op& op, const double* rows, int n_sub,
+                                           real* cache) {
+    const double tau = op.u.shape.tau;
+    static_for<0, S>([&](auto si) {
+        constexpr int s = decltype(si)::value;
+        double dur, dui;
+        step_delta<double>(phase_rev(op.u.shape.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), tau, sp.r2[s],
+                           dur, dui);
+        const double d1 = -expm1(-tau * sp.r1[s]);
+        const double m0d = (double)sp.m0[s];
+        // vectors 0..2: columns of A; vector 3: b
+        double vx[4] = {1.0, 0.0, 0.0, 0.0}, vy[4] = {0.0, 1.0, 0.0, 0.0}, vz[4] = {0.0, 0.0, 1.0, 0.0};
+        for (int q = 0; q < n_sub; ++q) {
+            rotate<double, 4>(rows + 9 * q, vx, vy, vz);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double a_ = vx[v], b_ = vy[v];
+                vx[v] = fma(a_, dur, fma(-b_, dui, a_));
+                vy[v] = fma(a_, dui, fma(b_, dur, b_));
+                vz[v] = fma(v == 3 ? m0d - vz[v] : -vz[v], d1, vz[v]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            cache[((0 + v) * S + s) * kBlock] = (real)vx[v];   // A[0][v]
+            cache[((3 + v) * S + s) * kBlock] = (real)vy[v];   // A[1][v]
+            cache[((6 + v) * S + s) * kBlock] = (real)vz[v];   // A[2][v]
+        }
+        cache[(9 * S + s) * kBlock] = (real)vx[3];
+        cache[(10 * S + s) * kBlock] = (real)vy[3];
+        cache[(11 * S + s) * kBlock] = (real)vz[3];
+    });
+}
+
+// M <- Rz(phi) (A Rz(-phi) M + b) with (cos phi, sin phi) = (c, sn), from
+// the lane's slot entries; turn == false means phi = 0.
+template <typename real, int S>
+__device__ __forceinline__ void shape_apply(const real* cache, bool turn, real c, real sn, real (&mx)[S],
+                                            real (&my)[S], real (&mz)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        real x = mx[s], y = my[s];
+        if (turn) {
+            const real x0 = x;
+            x = fma(c, x0, sn * y);
+            y = fma(c, y, -sn * x0);
+        }
+        const real z = mz[s];
+        const real* e = cache + s * kBlock;
+        real nx = fma(e[0 * S * kBlock], x, fma(e[1 * S * kBlock], y, fma(e[2 * S * kBlock], z, e[9 * S * kBlock])));
+        real ny = fma(e[3 * S * kBlock], x, fma(e[4 * S * kBlock], y, fma(e[5 * S * kBlock], z, e[10 * S * kBlock])));
+        mz[s] = fma(e[6 * S * kBlock], x, fma(e[7 * S * kBlock], y, fma(e[8 * S * kBlock], z, e[11 * S * kBlock])));
+        if (turn) {
+            const real x0 = nx;
+            nx = fma(c, x0, -sn * ny);
+            ny = fma(c, ny, sn * x0);
+        }
+        mx[s] = nx;
+        my[s] = ny;
+    }
+}
+
 // One workgroup tile of one request: spins [blk * 256 S, (blk + 1) * 256 S)
 // through the slice's operations, partial sums into the tile's rows.
 template <typename real, int S>
@@ -255,8 +344,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
     constexpr int R = G * S;                 // spins per lane inside readouts
     __shared__ Op s_ops[kOpChunk];
     __shared__ real s_x[G > 1 ? kWaves : 1][G > 1 ? S : 1][8][64];   // readout anchors
+    // readout step factors (z, z^32, z^(32 G)) of every spin of the tile for
+    // the (mu, tau) of the last ADC operation; each lane reads only its own
+    __shared__ real s_stepf[S][6][kBlock];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
+    // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
+    // x kBlock reals; every lane reads only the entries it wrote itself
+    real* s_cache = reinterpret_cast<real*>(s_rows + 9 * a.n_shape_rows);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -293,6 +388,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
     }
 
     const int wg = wave % G;                 // position inside the wave group
+    double step_mu[3] = {0.0, 0.0, 0.0}, step_tau = 0.0;
+    bool step_valid = false;
     real* partial = reinterpret_cast<real*>(a.partial) +
                     (blk * (kWaves / G) + wave / G) * a.row_stride;
 
@@ -328,21 +425,42 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                 // increment to every component, and in FP32 the roundings of
                 // these many small additions are correlated and drift.  With
                 // packed FP32 unused, an FP64 FMA issues at the FP32 rate.
+                // The rows hold the shape's own phases; the event's RF phase
+                // conjugates the whole pulse by Rz (see ps_ops.h).
                 real ex[S], ey[S], ez[S];
                 evaluate<real, S>(sp, op, mxy_zero, ex, ey, ez);
+                const uint32_t mode = __builtin_amdgcn_readfirstlane(op.u.shape.mode);
+                const int n_sub = (int)__builtin_amdgcn_readfirstlane(op.n);
+                const double* rows = s_rows + 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
+                if (mode != SHAPE_DIRECT) {
+                    real* cache = s_cache +
+                                  (int)__builtin_amdgcn_readfirstlane(op.u.shape.slot) * (kShapeCacheReals * S * kBlock) +
+                                  tid;
+                    if (mode == SHAPE_FILL) shape_fill<real, S>(sp, op, rows, n_sub, cache);
+                    const double rc = op.u.shape.rot[0], rs = op.u.shape.rot[1];
+                    shape_apply<real, S>(cache, rc != 1.0 || rs != 0.0, (real)rc, (real)rs, ex, ey, ez);
+#pragma unroll
+                    for (int s = 0; s < S; ++s) { sp.ar[s] = ex[s]; sp.ai[s] = ey[s]; sp.az[s] = ez[s]; }
+                    continue;
+                }
                 double mx[S], my[S], mz[S];
-                const double tau = op.u.adc.tau;
+                const double tau = op.u.shape.tau;
+                const double rc = op.u.shape.rot[0], rs = op.u.shape.rot[1];
+                const bool turn = rc != 1.0 || rs != 0.0;
                 double dur[S], dui[S], d1[S], m0d[S];
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     mx[s] = ex[s]; my[s] = ey[s]; mz[s] = ez[s];
-                    step_delta<double>(phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), tau,
+                    if (turn) {                  // Rz(-phi)
+                        const double x0 = mx[s];
+                        mx[s] = fma(rc, x0, rs * my[s]);
+                        my[s] = fma(rc, my[s], -rs * x0);
+                    }
+                    step_delta<double>(phase_rev(op.u.shape.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), tau,
                                        sp.r2[s], dur[s], dui[s]);
                     d1[s] = -expm1(-tau * sp.r1[s]);
                     m0d[s] = (double)sp.m0[s];
                 }
-                const int n_sub = (int)__builtin_amdgcn_readfirstlane(op.n);
-                const double* rows = s_rows + 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
                 for (int q = 0; q < n_sub; ++q) {
                     rotate<double, S>(rows + 9 * q, mx, my, mz);
 #pragma unroll
@@ -354,7 +472,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                     }
                 }
 #pragma unroll
-                for (int s = 0; s < S; ++s) { sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s]; }
+                for (int s = 0; s < S; ++s) {
+                    if (turn) {                  // Rz(phi)
+                        const double x0 = mx[s];
+                        mx[s] = fma(rc, x0, -rs * my[s]);
+                        my[s] = fma(rc, my[s], rs * x0);
+                    }
+                    sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s];
+                }
             } else if (kind == OP_ADC) {
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
@@ -362,7 +487,48 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                 // this wave's spins: sample 0 (p0), one sample step (z), one
                 // chunk (Z = z^32) and one group stride (W = z^(32 G)), all
                 // from FP64 phases
+                // Step factors depend only on (mu, tau) and the spin; successive
+                // readouts of a sequence usually share them, so they are kept
+                // (in LDS, off the register budget) from the previous ADC
+                // operation when (mu, tau) is unchanged.
+                const bool same_step = step_valid && op.u.adc.mu[0] == step_mu[0] &&
+                                       op.u.adc.mu[1] == step_mu[1] && op.u.adc.mu[2] == step_mu[2] &&
+                                       tau == step_tau;
+                // z, Z and W of spin s into f[0..5] (re, im pairs)
+                auto step_factors = [&](int s, real* f) {
+                    real c, sn;
+                    const double ph = phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
+                    real ez = Math<real>::expneg(tau, sp.r2[s]);
+                    Math<real>::cis(ph, c, sn);
+                    f[0] = ez * c; f[1] = -ez * sn;
+                    real eZ = Math<real>::expneg(tau * kT, sp.r2[s]);
+                    Math<real>::cis(ph * kT, c, sn);
+                    f[2] = eZ * c; f[3] = -eZ * sn;
+                    if constexpr (G > 1) {
+                        real eW = Math<real>::expneg(tau * (kT * G), sp.r2[s]);
+                        Math<real>::cis(ph * (kT * G), c, sn);
+                        f[4] = eW * c; f[5] = -eW * sn;
+                    } else {
+                        f[4] = f[2]; f[5] = f[3];
+                    }
+                };
                 real ap[S][8];
+                if (!same_step) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        real f[6];
+                        step_factors(s, f);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) s_stepf[s][k][tid] = f[k];
+                    }
+                    step_mu[0] = op.u.adc.mu[0]; step_mu[1] = op.u.adc.mu[1]; step_mu[2] = op.u.adc.mu[2];
+                    step_tau = tau;
+                    step_valid = true;
+                }
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) ap[s][2 + k] = s_stepf[s][k][tid];
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     real e2 = Math<real>::expneg(op.txy, sp.r2[s]);
@@ -370,20 +536,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                     Math<real>::cis(phase_rev(op.k, op.txy, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), c, sn);
                     ap[s][0] = e2 * (sp.ar[s] * c + sp.ai[s] * sn);
                     ap[s][1] = e2 * (sp.ai[s] * c - sp.ar[s] * sn);
-                    const double ph = phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
-                    real ez = Math<real>::expneg(tau, sp.r2[s]);
-                    Math<real>::cis(ph, c, sn);
-                    ap[s][2] = ez * c; ap[s][3] = -ez * sn;
-                    real eZ = Math<real>::expneg(tau * kT, sp.r2[s]);
-                    Math<real>::cis(ph * kT, c, sn);
-                    ap[s][4] = eZ * c; ap[s][5] = -eZ * sn;
-                    if constexpr (G > 1) {
-                        real eW = Math<real>::expneg(tau * (kT * G), sp.r2[s]);
-                        Math<real>::cis(ph * (kT * G), c, sn);
-                        ap[s][6] = eW * c; ap[s][7] = -eW * sn;
-                    } else {
-                        ap[s][6] = ap[s][4]; ap[s][7] = ap[s][5];
-                    }
                 }
                 // the wave group's G * S spins (LDS exchange when G > 1)
                 real pr[R], pi[R], zr[R], zi[R], Wr[R], Wi[R];
@@ -564,16 +716,52 @@ __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename real, int S>
+static size_t dyn_lds_t(int32_t n_shape_rows, int32_t n_cache_slots) {
+    return (size_t)n_shape_rows * 9 * sizeof(double) +
+           (size_t)n_cache_slots * kShapeCacheReals * S * kBlock * sizeof(real);
+}
+
+size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots) {
+    if (precision == 64) return spins_per_lane == 1 ? dyn_lds_t<double, 1>(n_shape_rows, n_cache_slots)
+                                                    : dyn_lds_t<double, 2>(n_shape_rows, n_cache_slots);
+    switch (spins_per_lane) {
+        case 1: return dyn_lds_t<float, 1>(n_shape_rows, n_cache_slots);
+        case 2: return dyn_lds_t<float, 2>(n_shape_rows, n_cache_slots);
+        case 4: return dyn_lds_t<float, 4>(n_shape_rows, n_cache_slots);
+        default: return dyn_lds_t<float, 8>(n_shape_rows, n_cache_slots);
+    }
+}
+
+int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows) {
+    // FP32: keep a workgroup's LDS within half of a CU's 160 KiB so that two
+    // workgroups (8 waves, the register-bound occupancy) stay resident per
+    // CU; FP64 kernels run one workgroup per CU anyway
+    const size_t kBudget = (precision == 64 ? 160 : 80) * 1024;
+    size_t fixed;
+    if (precision == 64) fixed = spins_per_lane == 1 ? static_lds_bytes<double, 1>() : static_lds_bytes<double, 2>();
+    else switch (spins_per_lane) {
+        case 1: fixed = static_lds_bytes<float, 1>(); break;
+        case 2: fixed = static_lds_bytes<float, 2>(); break;
+        case 4: fixed = static_lds_bytes<float, 4>(); break;
+        default: fixed = static_lds_bytes<float, 8>(); break;
+    }
+    int n = 0;
+    while (n < kShapeSlots &&
+           fixed + step_dyn_lds_bytes(precision, spins_per_lane, n_shape_rows, n + 1) <= kBudget)
+        ++n;
+    return n;
+}
+
+template <typename real, int S>
 static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t st) {
-    const size_t dyn = (size_t)a.n_shape_rows * 9 * sizeof(double);
+    const size_t dyn = dyn_lds_t<real, S>(a.n_shape_rows, a.n_cache_slots);
     hipLaunchKernelGGL((step_kernel<real, S>), dim3((unsigned)n_blocks), dim3(kBlock), dyn, st, a);
     return hipGetLastError();
 }
 
 template <typename real, int S>
 static hipError_t launch_batch_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                                 int32_t max_shape_rows, int n_cu, hipStream_t st) {
-    const size_t dyn = (size_t)max_shape_rows * 9 * sizeof(double);
+                                 size_t dyn, int n_cu, hipStream_t st) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S>, kBlock, dyn) !=
             hipSuccess || per_cu < 1)
@@ -586,19 +774,19 @@ static hipError_t launch_batch_t(const BatchItem* reqs, int32_t n_req, int64_t t
 }
 
 hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                             int32_t max_shape_rows, int precision, int spins_per_lane, int n_cu, hipStream_t st) {
+                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st) {
     if (precision == 64) {
         switch (spins_per_lane) {
-            case 1: return launch_batch_t<double, 1>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
-            case 2: return launch_batch_t<double, 2>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+            case 1: return launch_batch_t<double, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
+            case 2: return launch_batch_t<double, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
             default: return hipErrorInvalidValue;
         }
     }
     switch (spins_per_lane) {
-        case 1: return launch_batch_t<float, 1>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
-        case 2: return launch_batch_t<float, 2>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
-        case 4: return launch_batch_t<float, 4>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
-        case 8: return launch_batch_t<float, 8>(reqs, n_req, total, counter, max_shape_rows, n_cu, st);
+        case 1: return launch_batch_t<float, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
+        case 2: return launch_batch_t<float, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
+        case 4: return launch_batch_t<float, 4>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
+        case 8: return launch_batch_t<float, 8>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -19,6 +19,7 @@ struct StepArgs {
     void* state;             // device, 3 * n_spins reals (Mxy_a re, im, Mz_a), SoA
     int32_t load_state;      // resume from state instead of equilibrium
     int32_t save_state;      // write the anchors back at the end
+    int32_t n_cache_slots;   // shaped-pulse propagator slots the slice's ops use
 };
 
 // One request of a persistent batched launch: its arguments and the number
@@ -47,15 +48,21 @@ int64_t rows_per_block_of(int spins_per_lane);
 
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
                        hipStream_t st);
+// Dynamic LDS of a step workgroup: shaped-pulse rows and propagator slots.
+size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots);
+// Propagator slots (at most kShapeSlots) that fit a step workgroup's LDS
+// budget next to n_shape_rows shaped-pulse rows.
+int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows);
 // Doubles of scratch launch_finalize needs for n_rows rows of n_vals values.
 int64_t finalize_scratch_doubles(int64_t n_rows, int64_t n_vals);
 hipError_t launch_finalize(const void* partial, int precision, int64_t n_rows, int64_t row_stride,
                            int64_t n_vals, double* out, double* scratch, hipStream_t st);
 hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t st);
 // Persistent launch over total items of the n_req requests in reqs (device);
-// counter (device) must hold 0.
+// counter (device) must hold 0; dyn_lds covers every request's
+// step_dyn_lds_bytes.
 hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                             int32_t max_shape_rows, int precision, int spins_per_lane, int n_cu, hipStream_t st);
+                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st);
 hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
                                  hipStream_t st);
 int64_t row_group_size();

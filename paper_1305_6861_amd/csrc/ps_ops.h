@@ -41,7 +41,15 @@ struct alignas(16) Op {
         double r64[9];                           // RF rotation, FP64 tables
         float r32[9];                            // RF rotation, FP32 tables
         struct { double mu[3]; double tau; } adc;  // ADC: per-sample moment and
-                                                   // dwell; SHAPE: per-sub-step
+                                                   // dwell
+        struct {
+            double mu[3];       // per-sub-step moment (same place as adc.mu)
+            double tau;         // sub-step duration (same place as adc.tau)
+            double rot[2];      // cos, sin of the event's RF phase
+            int32_t slot;       // propagator cache slot, or -1 (step directly)
+            uint32_t mode;      // ShapeMode
+            int32_t shape_id;   // index of the shape in the sequence
+        } shape;
     } u;
     uint32_t kind;
     uint32_t flags;
@@ -52,9 +60,28 @@ struct alignas(16) Op {
 static_assert(sizeof(Op) == 128, "Op must be 128 bytes");
 
 // A SHAPE op keeps the shape's sub-step duration and per-sub-step moment in
-// u.adc (mu, tau).  Its sub-step rotations live in a separate table of 9
-// reals per sub-step; the event's RF phase is folded into them, so every
-// distinct (shape, phase) pair gets its own rows.
+// u.shape (mu, tau).  Its sub-step rotations live in a separate table of 9
+// reals per sub-step, one block of rows per shape, built with the shape's own
+// sub-pulse phases.  The event's RF phase phi enters as a conjugation: adding
+// phi to every sub-pulse phase turns each sub-pulse rotation R into
+// Rz(phi) R Rz(-phi) (eq. 3.19), and precession about z and relaxation
+// commute with Rz, so the whole pulse maps M to Rz(phi) P(Rz(-phi) M), P
+// being the pulse at the shape's own phases.  Phase-cycled sequences thus
+// share one block of rows.
 constexpr int kMaxShapeRows = 512;
+
+// Propagator cache for repeated shaped pulses.  For a given spin a shaped
+// pulse (its sub-pulses, its slab gradient, the spin's off-resonance and
+// relaxation over the sub-steps) is one fixed affine map M -> A M + b, since
+// every sub-step of eq. 3.23 is affine in M.  The first occurrence of the
+// shape in a launch builds (A, b) per spin and keeps it in LDS; later
+// occurrences apply it, each with its own phase conjugation as above.
+enum ShapeMode : uint32_t {
+    SHAPE_DIRECT = 0,  // step the sub-steps (no cache)
+    SHAPE_FILL = 1,    // build the slot's map, then apply it
+    SHAPE_APPLY = 2,   // apply the slot's map (rot gives the phase offset)
+};
+constexpr int kShapeSlots = 2;
+constexpr int kShapeCacheReals = 12;  // A (3 x 3, row-major) then b (3)
 
 }  // namespace ps

@@ -1,0 +1,152 @@
+"""GPU: the shaped-pulse propagator cache.
+
+A shaped pulse that recurs within a time slice is stepped once per spin into
+the affine map M -> A M + b it applies (eq. 3.23 sub-steps are affine in M);
+later occurrences apply the map, conjugated by Rz of their RF phase offset.
+Both the cached and the sub-step path are compared with the FP64 oracle, and
+with each other, on sequences that exercise: one shape repeated every
+repetition (3-D slab-selective GRE), quadratic RF phase cycling (phase
+offsets on every application), more recurring shapes than cache slots, a
+hard pulse on the same event as a shape, time slicing (a slot is refilled in
+every slice), every cache-capable tiling, and the batched path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Sequence, Shape, SPOIL, configs as C
+from workloads.phantom import random_spins
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+CACHE_VS_DIRECT32 = 3e-6     # two FP32 paths, each within ~1e-6 of the oracle
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import paper_1305_6861_amd as ps
+    return ps
+
+
+def run(ps, obj, seq, **kw):
+    import torch
+    with ps.Context(**kw) as ctx:
+        out = ctx.simulate(obj, seq)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+def report(label, err):
+    print(f"[cache] {label} rel_l2={err:.3e}", flush=True)
+    return err
+
+
+def rf_spoiled_sinc(n_tr: int, n_adc: int = 24) -> Sequence:
+    """Slab-selective excitation with quadratic RF phase cycling (117 degree
+    increment) and a gradient spoiler instead of ideal spoiling: every
+    application of the cached map has a different phase offset."""
+    seq = Sequence("rf-spoiled sinc")
+    sh = seq.add_shape(C.sinc_shape(48, 2e-5, np.deg2rad(25.0), 4.0, 0.08))
+    inc = np.deg2rad(117.0)
+    for n in range(n_tr):
+        phi = inc * n * (n + 1) / 2.0
+        seq.add(1.5e-3, m=(-30.0, 10.0 * (n % 5 - 2), -40.0), shape=sh, phase=phi)
+        seq.add(n_adc * 2e-5, m=(60.0, 0.0, 0.0), n_adc=n_adc)
+        seq.add(3e-3, m=(0.0, 0.0, 400.0))
+    return seq
+
+
+def three_shapes(n_tr: int) -> Sequence:
+    """Per repetition: sinc excitation, sinc refocusing (with a hard pulse on
+    the same event), and a random-phase small-tip shape; three recurring
+    shapes against two cache slots, so one of them is stepped directly."""
+    rng = np.random.default_rng(11)
+    seq = Sequence("three shapes")
+    s0 = seq.add_shape(C.sinc_shape(40, 2e-5, np.pi / 2, 4.0, 0.1))
+    s1 = seq.add_shape(C.sinc_shape(32, 2.5e-5, np.pi, 3.0, 0.12))
+    s2 = seq.add_shape(Shape(tau=1e-5, m_sub=(2.0, 0.0, 1.0), alpha=rng.uniform(-0.05, 0.1, 24),
+                             phase=rng.uniform(-1.0, 1.0, 24)))
+    for n in range(n_tr):
+        seq.add(2e-3, m=(-20.0, 5.0 * n, -30.0), shape=s0, phase=0.0)
+        seq.add(2e-3, shape=s1, alpha=0.05, phase=np.pi / 2 + 0.01 * n)
+        seq.add(16 * 3e-5, m=(40.0, 0.0, 0.0), n_adc=16)
+        seq.add(1e-3, shape=s2, phase=0.4 * n, flags=SPOIL)
+    return seq
+
+
+def test_3d_recipe_cache_matches_direct_and_oracle(ps):
+    obj, _ = C.c3(16)
+    seq = C.gre_3d_sinc(16, 4, 3)                    # one sinc shape in 12 repetitions
+    ref = oracle.simulate(obj, seq)
+    c32 = run(ps, obj, seq)
+    d32 = run(ps, obj, seq, shape_cache=False)
+    c64 = run(ps, obj, seq, precision=64)
+    d64 = run(ps, obj, seq, precision=64, shape_cache=False)
+    assert report("c3[16] cached", oracle.rel_l2(c32, ref)) <= TOL32
+    assert report("c3[16] direct", oracle.rel_l2(d32, ref)) <= TOL32
+    assert report("c3[16] cached vs direct", oracle.rel_l2(c32, d32)) <= CACHE_VS_DIRECT32
+    assert report("c3[16]/fp64 cached", oracle.rel_l2(c64, ref)) <= TOL64
+    assert report("c3[16]/fp64 direct", oracle.rel_l2(d64, ref)) <= TOL64
+
+
+def test_phase_cycled_applications(ps):
+    """30 distinct RF phases of one 48-sub-step shape: one block of rows
+    (the phase enters by Rz conjugation), on both paths."""
+    obj = random_spins(2500, seed=21, dw_sigma_hz=150.0)
+    seq = rf_spoiled_sinc(30)
+    ref = oracle.simulate(obj, seq)
+    got = run(ps, obj, seq)
+    assert report("rf-spoiled cached", oracle.rel_l2(got, ref)) <= TOL32
+    direct = run(ps, obj, seq, shape_cache=False)
+    assert report("rf-spoiled direct", oracle.rel_l2(direct, ref)) <= TOL32
+    assert report("rf-spoiled cached vs direct", oracle.rel_l2(got, direct)) <= CACHE_VS_DIRECT32
+    assert report("rf-spoiled cached/fp64", oracle.rel_l2(run(ps, obj, seq, precision=64), ref)) <= TOL64
+    assert report("rf-spoiled direct/fp64",
+                  oracle.rel_l2(run(ps, obj, seq, precision=64, shape_cache=False), ref)) <= TOL64
+
+
+def test_more_recurring_shapes_than_slots(ps):
+    obj = random_spins(1800, seed=22, dw_sigma_hz=60.0)
+    seq = three_shapes(9)
+    ref = oracle.simulate(obj, seq)
+    got = run(ps, obj, seq)
+    assert report("three shapes cached", oracle.rel_l2(got, ref)) <= TOL32
+    assert report("three shapes cached vs direct",
+                  oracle.rel_l2(got, run(ps, obj, seq, shape_cache=False))) <= CACHE_VS_DIRECT32
+    assert report("three shapes cached/fp64", oracle.rel_l2(run(ps, obj, seq, precision=64), ref)) <= TOL64
+
+
+def test_cache_refilled_in_every_time_slice(ps):
+    """A small partial-sum buffer cuts the sequence into slices of a few
+    repetitions; every slice refills its slot from its own first occurrence
+    (whose phase differs from slice to slice)."""
+    obj = random_spins(1500, seed=23, dw_sigma_hz=100.0)
+    seq = rf_spoiled_sinc(40, n_adc=24)
+    ref = oracle.simulate(obj, seq)
+    n_rows = 6                                           # 1500 spins at S = 1: 6 workgroups x 1 row
+    sliced = run(ps, obj, seq, spins_per_lane=1, max_partial_bytes=n_rows * 2 * 4 * 24 * 6)
+    whole = run(ps, obj, seq, spins_per_lane=1)
+    assert report("sliced cached", oracle.rel_l2(sliced, ref)) <= TOL32
+    assert report("sliced vs whole", oracle.rel_l2(sliced, whole)) <= CACHE_VS_DIRECT32
+
+
+@pytest.mark.parametrize("S", [1, 2])
+def test_cache_tilings(ps, S):
+    obj, _ = C.c3(12)
+    seq = C.gre_3d_sinc(12, 3, 3)
+    ref = oracle.simulate(obj, seq)
+    assert report(f"c3[12] S={S} cached", oracle.rel_l2(run(ps, obj, seq, spins_per_lane=S), ref)) <= TOL32
+
+
+def test_batched_requests_with_cached_shapes_equal_alone(ps):
+    reqs = [(C.c3(10)[0], C.gre_3d_sinc(10, 3, 2)), (random_spins(700, seed=24), rf_spoiled_sinc(12)),
+            (random_spins(300, seed=25), three_shapes(6)), C.c4_request(1)]
+    import torch
+    with ps.Context() as ctx:
+        outs = [o.cpu().numpy() for o in ctx.simulate_batch([r[0] for r in reqs], [r[1] for r in reqs])]
+        torch.cuda.synchronize()
+    for (obj, seq), got in zip(reqs, outs):
+        np.testing.assert_array_equal(got, run(ps, obj, seq))
+        assert oracle.rel_l2(got, oracle.simulate(obj, seq)) <= TOL32
