@@ -63,7 +63,7 @@ typedef struct ps_config {
     int32_t spins_per_lane;      /* 0 = autotuned; else 1, 2, 4 or 8 (FP64: 1 or 2)    */
     int32_t flags;               /* PS_CFG_KERNEL_TIMING | PS_CFG_NO_SHAPE_CACHE       */
     int64_t max_partial_bytes;   /* bound on the per-block partial-sum buffer; longer
-                                    sequences run in time slices (0 = default 512 MiB) */
+                                    sequences run in time slices (0 = default 2 GiB)   */
     int64_t max_footprint_bytes; /* admission cap for served requests (0 = 64 GiB)     */
 } ps_config;
 

@@ -4,7 +4,8 @@ Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  It shares no code with the GPU library: the stepping is plain
 C (bloch_oracle.c) following section 5.1.1 with eq. 3.19 for hard pulses,
 eq. 3.5 / 3.12 / 3.14 for precession and relaxation, eq. 3.23 for shaped
-pulses and eq. 3.30 - 3.32 for the received signal.
+pulses, eq. 3.30 - 3.32 for the received signal and eq. 3.25 for receive
+coils with an inhomogeneous sensitivity.
 
 Inputs are duck-typed: a spin object exposes float32 arrays x, y, z, m0,
 t1, t2, dw (widened exactly to float64 here), a sequence exposes the
@@ -35,6 +36,13 @@ def _configure(lib):
         [ctypes.c_int64] + [_dp] * 7 +
         [ctypes.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _u32p] +
         [ctypes.c_int32, _i64p, _dp, _dp, _i64p, _dp, _dp] +
+        [ctypes.c_int, ctypes.c_int64, _dp, _dp])
+    lib.oracle_simulate_coils.restype = ctypes.c_int
+    lib.oracle_simulate_coils.argtypes = (
+        [ctypes.c_int64] + [_dp] * 7 +
+        [ctypes.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _u32p] +
+        [ctypes.c_int32, _i64p, _dp, _dp, _i64p, _dp, _dp] +
+        [ctypes.c_int32, _dp, _dp] +
         [ctypes.c_int, ctypes.c_int64, _dp, _dp])
     lib.oracle_rf_pulse.restype = None
     lib.oracle_rf_pulse.argtypes = [_dp, ctypes.c_double, ctypes.c_double]
@@ -70,9 +78,15 @@ def default_threads() -> int:
         return max(1, os.cpu_count() or 1)
 
 
-def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False):
+def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False, coils=None):
     """Signal (complex128, one entry per ADC sample in event order) and,
-    when final_m is set, the final magnetisation (n_spins, 3) float64."""
+    when final_m is set, the final magnetisation (n_spins, 3) float64.
+
+    coils: optional receive sensitivities, a pair (s_x, s_y) of arrays of
+    shape (n_coils, n_spins) holding the transverse components of each
+    coil's sensitivity at each spin (section 3.5.1, eq. 3.24), float32 as
+    the GPU library receives them; the signal is then (n_coils, n_samples),
+    coil c receiving sum_i (S_x Mx + S_y My) + j (S_x My - S_y Mx)."""
     lib = _load()
     n = int(np.asarray(obj.x).shape[0])
     sp = [np.ascontiguousarray(np.asarray(getattr(obj, f), dtype=np.float32), dtype=np.float64)
@@ -96,19 +110,34 @@ def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False):
     sh_alpha = np.concatenate([s.alpha for s in shapes] + [np.zeros(1)]).astype(np.float64)
     sh_phase = np.concatenate([s.phase for s in shapes] + [np.zeros(1)]).astype(np.float64)
     n_samples = int(na.sum())
-    out = np.zeros(2 * n_samples + 1, np.float64)
+    if coils is None:
+        n_coils = 0
+        s_x = s_y = np.zeros(1, np.float64)
+    else:
+        s_x, s_y = (np.asarray(np.asarray(c, dtype=np.float32), dtype=np.float64) for c in coils)
+        if s_x.ndim != 2 or s_x.shape != s_y.shape or s_x.shape[1] != n:
+            raise ValueError(f"coil sensitivities must have shape (n_coils, {n})")
+        n_coils = int(s_x.shape[0])
+        s_x = np.ascontiguousarray(s_x).reshape(-1)
+        s_y = np.ascontiguousarray(s_y).reshape(-1)
+        if s_x.size == 0:
+            s_x = s_y = np.zeros(1, np.float64)
+    out = np.zeros(2 * n_samples * max(n_coils, 1) + 1, np.float64)
     fm = np.zeros(3 * n + 1, np.float64) if final_m else None
     nt = int(n_threads or default_threads())
-    rc = lib.oracle_simulate(
+    rc = lib.oracle_simulate_coils(
         n, *[_ptr(a, _dp) for a in sp],
         ne, _ptr(dt, _dp), _ptr(m, _dp), _ptr(al, _dp), _ptr(ph, _dp), _ptr(sh, _i32p),
         _ptr(na, _i64p), _ptr(fl, _u32p),
         ns, _ptr(sh_nsub, _i64p), _ptr(sh_tau, _dp), _ptr(sh_m, _dp), _ptr(offs, _i64p),
         _ptr(sh_alpha, _dp), _ptr(sh_phase, _dp),
+        n_coils, _ptr(s_x, _dp), _ptr(s_y, _dp),
         nt, n_samples, _ptr(out, _dp), _ptr(fm, _dp) if fm is not None else None)
     if rc != 0:
         raise ValueError(f"oracle_simulate failed with code {rc}")
-    sig = out[:2 * n_samples].view(np.complex128).copy()
+    sig = out[:2 * n_samples * max(n_coils, 1)].view(np.complex128).copy()
+    if coils is not None:
+        sig = sig.reshape(n_coils, n_samples)
     if final_m:
         return sig, fm[:3 * n].reshape(n, 3).copy()
     return sig

@@ -30,6 +30,19 @@
  *    spoiler; the paper has no such primitive);
  *  - T1 or T2 = +inf means no relaxation of that kind (exp(-t/inf) = 1).
  *
+ * Receive coils (section 3.5.1, eq. 3.24 / 3.25): with an inhomogeneous
+ * receive sensitivity S(x) every spin's magnetisation is weighted before the
+ * superposition.  Taking eq. 3.25 through the same steps as eq. 3.28 - 3.31
+ * (laboratory-frame precession at the carrier, time derivative, quadrature
+ * demodulation and low-pass filtering) for a sensitivity with both
+ * transverse components gives, with the constant omega_0 / 2 dropped as for
+ * the homogeneous coil,
+ *     real part  = sum_i  S_x Mx + S_y My       (in-plane dot product)
+ *     imag part  = sum_i  S_x My - S_y Mx       (z component of S x M)
+ * with S at the spin and M in the rotating frame.  S_z does not contribute:
+ * it multiplies the slowly varying Mz, which the demodulation removes.
+ * Without coils S = (1, 0, 0), which gives the sum of Mx + j My.
+ *
  * Every spin is independent.  Threads take contiguous spin ranges and keep
  * private FP64 signal buffers that are summed in thread order at the end.
  */
@@ -55,12 +68,17 @@ typedef struct {
     const int64_t *sh_nsub, *sh_offset;
     const double *sh_tau, *sh_m, *sh_alpha, *sh_phase;
     int64_t n_samples;
+    /* receive coils: transverse sensitivity of each coil at each spin,
+     * coil-major (s_x[c * n_spins + i]); n_coils == 0: one coil S = (1, 0, 0) */
+    int32_t n_coils;
+    int64_t n_spins;
+    const double *s_x, *s_y;
 } problem_t;
 
 typedef struct {
     const problem_t *pb;
     int64_t begin, end;
-    double *signal;   /* 2 * n_samples, private to the thread */
+    double *signal;   /* 2 * n_samples per coil, private to the thread */
     double *final_m;  /* 3 * n_spins, shared, disjoint ranges, may be NULL */
 } job_t;
 
@@ -128,8 +146,17 @@ static void run_spin(const problem_t *pb, int64_t i, double *signal, double *fin
         for (int64_t k = 0; k < K; ++k) {
             precess_relax(M, tau, mu, x, y, z, dw, m0, t1, t2);
             if (n_adc > 0) {
-                signal[2 * sample] += M[0];
-                signal[2 * sample + 1] += M[1];
+                if (pb->n_coils == 0) {
+                    signal[2 * sample] += M[0];
+                    signal[2 * sample + 1] += M[1];
+                } else {
+                    for (int32_t c = 0; c < pb->n_coils; ++c) {
+                        double sx = pb->s_x[c * pb->n_spins + i], sy = pb->s_y[c * pb->n_spins + i];
+                        double *sc = signal + 2 * pb->n_samples * c;
+                        sc[2 * sample] += sx * M[0] + sy * M[1];
+                        sc[2 * sample + 1] += sx * M[1] - sy * M[0];
+                    }
+                }
                 ++sample;
             }
         }
@@ -154,20 +181,26 @@ static void *worker(void *arg)
 }
 
 /* Returns 0 on success, -1 on an invalid argument, -2 on allocation failure.
- * All arrays are host arrays.  out_signal (2 * n_samples, interleaved re/im)
- * and out_final_m (3 * n_spins) may each be NULL. */
-int oracle_simulate(int64_t n_spins,
-                    const double *x, const double *y, const double *z, const double *m0,
-                    const double *t1, const double *t2, const double *dw,
-                    int64_t n_events, const double *ev_dt, const double *ev_m,
-                    const double *ev_alpha, const double *ev_phase, const int32_t *ev_shape,
-                    const int64_t *ev_nadc, const uint32_t *ev_flags,
-                    int32_t n_shapes, const int64_t *sh_nsub, const double *sh_tau,
-                    const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
-                    const double *sh_phase,
-                    int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
+ * All arrays are host arrays.  n_coils == 0: one homogeneous coil, out_signal
+ * holds 2 * n_samples doubles (interleaved re/im); n_coils >= 1: s_x and
+ * s_y hold n_coils * n_spins transverse sensitivities (coil-major) and
+ * out_signal holds n_coils blocks of 2 * n_samples.  out_signal and out_final_m (3 * n_spins)
+ * may each be NULL. */
+int oracle_simulate_coils(int64_t n_spins,
+                          const double *x, const double *y, const double *z, const double *m0,
+                          const double *t1, const double *t2, const double *dw,
+                          int64_t n_events, const double *ev_dt, const double *ev_m,
+                          const double *ev_alpha, const double *ev_phase, const int32_t *ev_shape,
+                          const int64_t *ev_nadc, const uint32_t *ev_flags,
+                          int32_t n_shapes, const int64_t *sh_nsub, const double *sh_tau,
+                          const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
+                          const double *sh_phase,
+                          int32_t n_coils, const double *s_x, const double *s_y,
+                          int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
 {
-    if (n_spins < 0 || n_events < 0 || n_samples < 0 || n_threads < 1)
+    if (n_spins < 0 || n_events < 0 || n_samples < 0 || n_threads < 1 || n_coils < 0)
+        return -1;
+    if (n_coils > 0 && n_spins > 0 && (!s_x || !s_y))
         return -1;
     int64_t total = 0;
     for (int64_t e = 0; e < n_events; ++e) {
@@ -182,7 +215,8 @@ int oracle_simulate(int64_t n_spins,
 
     problem_t pb = {x, y, z, m0, t1, t2, dw, n_events, ev_dt, ev_m, ev_alpha, ev_phase,
                     ev_shape, ev_nadc, ev_flags, n_shapes, sh_nsub, sh_offset, sh_tau, sh_m,
-                    sh_alpha, sh_phase, n_samples};
+                    sh_alpha, sh_phase, n_samples, n_coils, n_spins, s_x, s_y};
+    const int64_t n_vals = 2 * n_samples * (n_coils > 0 ? n_coils : 1);
 
     if (n_threads > n_spins && n_spins > 0)
         n_threads = (int)n_spins;
@@ -200,7 +234,7 @@ int oracle_simulate(int64_t n_spins,
         jobs[t].begin = n_spins * t / n_threads;
         jobs[t].end = n_spins * (t + 1) / n_threads;
         jobs[t].final_m = out_final_m;
-        jobs[t].signal = (double *)calloc((size_t)(2 * n_samples + 1), sizeof(double));
+        jobs[t].signal = (double *)calloc((size_t)(n_vals + 1), sizeof(double));
         if (!jobs[t].signal)
             rc = -2;
     }
@@ -218,9 +252,9 @@ int oracle_simulate(int64_t n_spins,
                 pthread_join(tid[t], NULL);
         free(started);
         if (out_signal) {
-            memset(out_signal, 0, (size_t)(2 * n_samples) * sizeof(double));
+            memset(out_signal, 0, (size_t)n_vals * sizeof(double));
             for (int t = 0; t < n_threads; ++t)
-                for (int64_t s = 0; s < 2 * n_samples; ++s)
+                for (int64_t s = 0; s < n_vals; ++s)
                     out_signal[s] += jobs[t].signal[s];
         }
     }
@@ -229,6 +263,24 @@ int oracle_simulate(int64_t n_spins,
     free(jobs);
     free(tid);
     return rc;
+}
+
+/* The signal of one homogeneous coil, S = (1, 0, 0); see oracle_simulate_coils. */
+int oracle_simulate(int64_t n_spins,
+                    const double *x, const double *y, const double *z, const double *m0,
+                    const double *t1, const double *t2, const double *dw,
+                    int64_t n_events, const double *ev_dt, const double *ev_m,
+                    const double *ev_alpha, const double *ev_phase, const int32_t *ev_shape,
+                    const int64_t *ev_nadc, const uint32_t *ev_flags,
+                    int32_t n_shapes, const int64_t *sh_nsub, const double *sh_tau,
+                    const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
+                    const double *sh_phase,
+                    int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
+{
+    return oracle_simulate_coils(n_spins, x, y, z, m0, t1, t2, dw, n_events, ev_dt, ev_m, ev_alpha,
+                                 ev_phase, ev_shape, ev_nadc, ev_flags, n_shapes, sh_nsub, sh_tau,
+                                 sh_m, sh_offset, sh_alpha, sh_phase, 0, NULL, NULL, n_threads,
+                                 n_samples, out_signal, out_final_m);
 }
 
 /* Single hard pulse applied to one vector, exposed so that tests can compare

@@ -245,7 +245,7 @@ ps_status ps_config_default(ps_config* cfg) {
     cfg->device = 0;
     cfg->precision = 32;
     cfg->spins_per_lane = 0;
-    cfg->max_partial_bytes = 512ll << 20;
+    cfg->max_partial_bytes = 2ll << 30;
     cfg->max_footprint_bytes = 64ll << 30;
     return PS_OK;
 }
@@ -262,7 +262,7 @@ ps_status ps_create(ps_ctx** out, const ps_config* cfg_in) {
         const bool ok = cfg.precision == 64 ? (s == 1 || s == 2) : (s == 1 || s == 2 || s == 4 || s == 8);
         if (!ok) return fail(PS_E_INVALID_ARG, "spins_per_lane not supported for this precision");
     }
-    if (cfg.max_partial_bytes <= 0) cfg.max_partial_bytes = 512ll << 20;
+    if (cfg.max_partial_bytes <= 0) cfg.max_partial_bytes = 2ll << 30;
     if (cfg.max_footprint_bytes <= 0) cfg.max_footprint_bytes = 64ll << 30;
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);

@@ -14,7 +14,10 @@ import pytest
 
 import oracle
 from oracle import build as obuild
+import tests.test_oracle_coils as coil_pins
 import tests.test_oracle_pins as pins
+
+PIN_MODULES = (pins, coil_pins)
 
 MUTANTS = {
     "rf_sign_r02": ("r02 = -sp * sa", "r02 = sp * sa"),
@@ -35,15 +38,31 @@ MUTANTS = {
     "spoil_ignored": ("if (pb->ev_flags[e] & ORACLE_SPOIL) {", "if (0) {"),
     "shape_phase_offset_dropped": ("pb->sh_phase[off + k] + pb->ev_phase[e]", "pb->sh_phase[off + k]"),
     "sample_records_mz": ("signal[2 * sample + 1] += M[1];", "signal[2 * sample + 1] += M[2];"),
+    "coil_imag_sign": ("sc[2 * sample + 1] += sx * M[1] - sy * M[0];",
+                       "sc[2 * sample + 1] += sx * M[1] + sy * M[0];"),
+    "coil_real_drops_sy": ("sc[2 * sample] += sx * M[0] + sy * M[1];", "sc[2 * sample] += sx * M[0];"),
+    "coil_sx_sy_swapped": ("double sx = pb->s_x[c * pb->n_spins + i], sy = pb->s_y[c * pb->n_spins + i];",
+                           "double sx = pb->s_y[c * pb->n_spins + i], sy = pb->s_x[c * pb->n_spins + i];"),
+    "coil_index_ignores_coil": ("double sx = pb->s_x[c * pb->n_spins + i], sy = pb->s_y[c * pb->n_spins + i];",
+                                "double sx = pb->s_x[i], sy = pb->s_y[i];"),
+    "coil_block_offset": ("double *sc = signal + 2 * pb->n_samples * c;",
+                          "double *sc = signal + pb->n_samples * c;"),
 }
 
 
 def _pin_functions():
     out = []
-    for name in dir(pins):
+    for mod in PIN_MODULES:
+        out.extend(_module_pins(mod))
+    return out
+
+
+def _module_pins(mod):
+    out = []
+    for name in dir(mod):
         if not name.startswith("test_"):
             continue
-        fn = getattr(pins, name)
+        fn = getattr(mod, name)
         params = getattr(fn, "pytestmark", [])
         cases = [()]
         for mark in params:

@@ -16,13 +16,16 @@ gradient whose time integral over the interval is given as a moment in
 cycles/m, a duration dt >= 0, and optionally N ADC samples taken after each
 of N equal sub-steps (section 5.1.1).  A shaped pulse is a reusable list of
 equal-length elementary sequences (hard-pulse approximation, eq. 3.23).
+
+Receive coils (section 3.5.1): sensitivity maps S = B1 / i of circular
+loops (coils.py), inputs for multi-coil signals.
 """
 from .sequence import Sequence, Shape, SPOIL, concat
 from .phantom import SpinObject, grid2d, grid3d_two_species, subset
-from . import configs
+from . import coils, configs
 
 __all__ = [
     "Sequence", "Shape", "SPOIL", "concat",
     "SpinObject", "grid2d", "grid3d_two_species", "subset",
-    "configs",
+    "coils", "configs",
 ]
