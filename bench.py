@@ -179,10 +179,11 @@ WORKLOADS = {
 }
 
 
-def algorithmic_flops(seq, n_spins: int) -> float:
+def algorithmic_flops(seq, n_spins: int, n_coils: int = 1) -> float:
+    """Each receive coil has its own readout pass over every spin-sample."""
     n_rf = int(sum(1 for a in seq.rf_alpha if a != 0.0))
     n_sub = int(sum(seq.shapes[int(s)].n_sub for s in seq.rf_shape if s >= 0))
-    return float(n_spins) * (FLOPS_ADC_SAMPLE * seq.n_samples + FLOPS_HARD_RF * n_rf
+    return float(n_spins) * (FLOPS_ADC_SAMPLE * seq.n_samples * max(n_coils, 1) + FLOPS_HARD_RF * n_rf
                              + FLOPS_SHAPE_SUBSTEP * n_sub)
 
 
@@ -208,26 +209,31 @@ def traffic_from_profiles(spl: int):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(obj, seq, ctx, target_s: float):
+def cpu_baseline(obj, seq, ctx, target_s: float, rx=None):
     """Oracle (FP64, all host threads) on every stride-th spin of the
-    workload, stride chosen so that the run takes about target_s."""
+    workload, stride chosen so that the run takes about target_s; rx: the
+    receive-coil sensitivities (s_x, s_y) as numpy arrays, or None."""
     import numpy as np
     import oracle
     from workloads.phantom import subset
     n_steps = seq.n_steps_per_spin
     threads = oracle.default_threads()
+
+    def sub_rx(stride):
+        return None if rx is None else tuple(a[:, ::stride] for a in rx)
+
     probe = subset(obj, 4096)
     t0 = time.perf_counter()
-    oracle.simulate(probe, seq, n_threads=threads)
+    oracle.simulate(probe, seq, n_threads=threads, coils=sub_rx(4096))
     rate = probe.n_spins * n_steps / max(time.perf_counter() - t0, 1e-6)
     want = max(rate * target_s / n_steps, 64)
     stride = 1 << max(0, int(math.floor(math.log2(obj.n_spins / want))))
     sub = subset(obj, stride)
     t0 = time.perf_counter()
-    ref = oracle.simulate(sub, seq, n_threads=threads)
+    ref = oracle.simulate(sub, seq, n_threads=threads, coils=sub_rx(stride))
     dt = time.perf_counter() - t0
     import torch
-    got = ctx.simulate(sub, seq)
+    got = ctx.simulate(sub, seq, coils=sub_rx(stride))
     torch.cuda.synchronize()
     err = oracle.rel_l2(got.cpu().numpy(), ref)
     return {"value": sub.n_spins * n_steps / dt, "unit": "spin-steps/s", "cores": threads,
@@ -264,6 +270,8 @@ def main():
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--coils", type=int, default=0,
+                    help="receive with this many loop coils on a ring around the object (0: one homogeneous coil)")
     ap.add_argument("--no-shape-cache", action="store_true",
                     help="step recurring shaped pulses sub-step by sub-step (default: propagator cache)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -295,18 +303,23 @@ def main():
     ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache)
     packed = ps.pack_sequence(seq)
     n_samples, n_steps = packed.count()
-    out = torch.empty(2 * n_samples, dtype=torch.float64, device="cuda")
+    rx, rx_np = None, None
+    if args.coils > 0:
+        from workloads import coils as coil_maps
+        rx_np = coil_maps.loop_ring(obj, args.coils, ring_radius=0.2, coil_radius=0.06)
+        rx = tuple(torch.from_numpy(a).cuda() for a in rx_np)
+    out = torch.empty(2 * n_samples * max(args.coils, 1), dtype=torch.float64, device="cuda")
     spl, _ = ctx.tile(obj.n_spins)
 
     for _ in range(args.warmup):
-        ctx.simulate(dev, packed, out=out)
+        ctx.simulate(dev, packed, out=out, coils=rx)
     torch.cuda.synchronize()
     ctx.kernel_times()                     # forget warm-up launches
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.simulate(dev, packed, out=out)
+        ctx.simulate(dev, packed, out=out, coils=rx)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms, fin_ms = ctx.kernel_times()
@@ -314,7 +327,7 @@ def main():
     spin_steps = float(obj.n_spins) * n_steps
     ms_per_step = 1e3 * elapsed / args.steps
     value = spin_steps * args.steps / elapsed
-    flops = algorithmic_flops(seq, obj.n_spins)
+    flops = algorithmic_flops(seq, obj.n_spins, args.coils)
     # a long sequence runs as several time slices (launches) per step: the
     # step's kernel time is the sum over its launches
     launches = len(step_ms) // max(args.steps, 1)
@@ -322,7 +335,7 @@ def main():
     achieved = flops / (k_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic_from_profiles(spl) if args.workload == "c2" else None,
+            "traffic": traffic_from_profiles(spl) if args.workload == "c2" and args.coils == 0 else None,
             "kernel": "step_kernel<float,%d>" % spl, "kernel_ms": k_ms, "launches_per_step": launches,
             "kernel_ms_per_launch": k_ms / max(launches, 1),
             "flops_per_step": flops, "flops_per_launch": flops / max(launches, 1),
@@ -337,11 +350,12 @@ def main():
            "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
                       "n_samples": n_samples, "spins_per_lane": spl, "precision": "fp32 stepping, "
-                      "fp64 phases and cross-block sums", "shape_cache": cache},
+                      "fp64 phases and cross-block sums", "shape_cache": cache,
+                      "receive_coils": args.coils or "one homogeneous coil"},
            "eta_spins_per_s": obj.n_spins / (ms_per_step * 1e-3),
            "roofline": roof}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(obj, seq, ctx, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline(obj, seq, ctx, args.cpu_seconds, rx_np)
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)

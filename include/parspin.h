@@ -144,6 +144,31 @@ ps_status ps_count(const ps_sequence *seq, int64_t *n_samples, int64_t *n_steps_
 ps_status ps_simulate(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq,
                       double *signal, int64_t n_samples, void *stream);
 
+/* Receive coils with inhomogeneous sensitivity (section 3.5.1).  The
+ * sensitivity of a coil is S = B1 / i (eq. 3.24); only its transverse
+ * components reach the demodulated signal.  Taking eq. 3.25 through the
+ * demodulation of eq. 3.28 - 3.31 with both transverse components, coil c
+ * receives at every sample
+ *     sum over spins of (S_x - j S_y) (Mx + j My),
+ * S at the spin, M in the rotating frame, the constant omega_0 / 2 dropped.
+ * The homogeneous coil S = (1, 0, 0) gives ps_simulate's signal.
+ * s_x, s_y: DEVICE, FP32, n_coils * n_spins each, coil-major (coil c, spin i
+ * at [c * n_spins + i]); owned by the caller, read during the call's kernels. */
+typedef struct ps_receive {
+    int32_t      n_coils;        /* >= 1                                               */
+    int32_t      reserved;       /* 0                                                  */
+    const float *s_x;            /* DEVICE                                             */
+    const float *s_y;            /* DEVICE                                             */
+} ps_receive;
+
+/* ps_simulate with receive coils: signal (DEVICE) holds rx->n_coils blocks of
+ * 2 * n_samples doubles, coil c's block at signal + 2 * n_samples * c, each
+ * laid out as ps_simulate's.  rx == NULL is ps_simulate.  The spins are
+ * stepped once for all coils; readouts cost one pass per coil.
+ * PS_E_INVALID_ARG for n_coils < 1, a nonzero reserved field or NULL arrays. */
+ps_status ps_simulate_rx(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, const ps_receive *rx,
+                         double *signal, int64_t n_samples, void *stream);
+
 /* Simulate n_requests independent requests together, stream-ordered on
  * `stream`.  All workgroup tiles of all requests form one work queue that a
  * persistent kernel drains (one launch per spins-per-lane class and time

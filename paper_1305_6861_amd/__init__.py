@@ -222,29 +222,55 @@ class Context:
         _b.check(_b.lib.ps_server_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in st._fields_}
 
-    def simulate(self, obj, seq, out=None, stream=None):
+    def simulate(self, obj, seq, out=None, stream=None, coils=None):
         """Signal of one request as a complex128 CUDA tensor (stream-ordered
-        on `stream`, default torch's current stream)."""
+        on `stream`, default torch's current stream).
+
+        coils: optional receive coils, a pair (s_x, s_y) of (n_coils, n_spins)
+        arrays or tensors with each coil's transverse sensitivity at each
+        spin (ps_simulate_rx); the signal is then (n_coils, n_samples)."""
         import torch
         owned = not (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
                                                    for f in FIELDS))
         dev = to_device(obj, f"cuda:{self.device}") if owned else obj
         ps = pack_sequence(seq)
         n_samples, _ = ps.count()
+        n_spins = int(dev["x"].numel())
+        rx, keep = None, []
+        if coils is not None:
+            cs = []
+            for c in coils:
+                t = torch.as_tensor(c, dtype=torch.float32).to(f"cuda:{self.device}").contiguous()
+                if t.dim() != 2 or t.shape[1] != n_spins:
+                    raise PsError(1, f"coil sensitivities must have shape (n_coils, {n_spins})")
+                cs.append(t)
+            if len(cs) != 2 or cs[0].shape != cs[1].shape:
+                raise PsError(1, "coils must be a pair (s_x, s_y) of equal shape")
+            keep = cs
+            rx = _b.ps_receive(int(cs[0].shape[0]), 0, cs[0].data_ptr() if cs[0].numel() else 0,
+                               cs[1].data_ptr() if cs[1].numel() else 0)
+        n_out = rx.n_coils if rx is not None else 1
         if out is None:
-            out = torch.empty(2 * n_samples, dtype=torch.float64, device=f"cuda:{self.device}")
-        elif out.dtype != torch.float64 or out.numel() != 2 * n_samples or not out.is_contiguous():
-            raise PsError(1, "out must be a contiguous float64 tensor of 2 * n_samples entries")
+            out = torch.empty(2 * n_samples * max(n_out, 1), dtype=torch.float64, device=f"cuda:{self.device}")
+        elif out.dtype != torch.float64 or out.numel() != 2 * n_samples * n_out or not out.is_contiguous():
+            raise PsError(1, "out must be a contiguous float64 tensor of 2 * n_samples * n_coils entries")
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         if owned:   # temporaries must outlive the asynchronous work on `stream`
             for t in dev.values():
                 t.record_stream(stream)
+        for t in keep:
+            t.record_stream(stream)
         o = _object_struct(dev)
-        _b.check(_b.lib.ps_simulate(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
-                                    ctypes.c_void_p(out.data_ptr() if n_samples else 0),
-                                    n_samples, ctypes.c_void_p(stream.cuda_stream)))
-        return out.view(torch.complex128)
+        if rx is None:
+            _b.check(_b.lib.ps_simulate(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                        ctypes.c_void_p(out.data_ptr() if n_samples else 0),
+                                        n_samples, ctypes.c_void_p(stream.cuda_stream)))
+            return out.view(torch.complex128)
+        _b.check(_b.lib.ps_simulate_rx(self._h, ctypes.byref(o), ctypes.byref(ps.struct), ctypes.byref(rx),
+                                       ctypes.c_void_p(out.data_ptr() if n_samples else 0),
+                                       n_samples, ctypes.c_void_p(stream.cuda_stream)))
+        return out.view(torch.complex128).view(max(n_out, 0), n_samples)
 
 
 class Ticket:

@@ -58,6 +58,12 @@ class ps_sequence(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("shapes", ctypes.c_void_p)]
 
 
+class ps_receive(ctypes.Structure):
+    _fields_ = [("n_coils", ctypes.c_int32), ("reserved", ctypes.c_int32), ("s_x", ctypes.c_void_p),
+                ("s_y", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(ps_receive) == 24
 assert ctypes.sizeof(ps_event) == 64
 assert ctypes.sizeof(ps_rf_shape) == 56
 assert ctypes.sizeof(ps_config) == 32
@@ -101,6 +107,9 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_int64)]),
     "ps_simulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "ps_simulate_rx": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
+                                      ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p]),
 }
 
 

@@ -20,6 +20,7 @@ static_assert(sizeof(ps_rf_shape) == 56, "ps_rf_shape ABI size");
 static_assert(sizeof(ps_config) == 32, "ps_config ABI size");
 static_assert(sizeof(ps_object) == 64, "ps_object ABI size");
 static_assert(sizeof(ps_sequence) == 32, "ps_sequence ABI size");
+static_assert(sizeof(ps_receive) == 24, "ps_receive ABI size");
 
 namespace ps {
 
@@ -114,14 +115,14 @@ int shape_cache_slots(const Ctx* ctx, int S, const Program& prog) {
     return shape_cache_slots_fitting(ctx->cfg.precision, S, (int32_t)(prog.rows.size() / 9));
 }
 
-// Compile + slice a request for a given number of partial-sum rows and
-// spins per lane.
-ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog) {
+// Compile + slice a request for a given number of partial-sum rows, spins
+// per lane and receive coils (every coil has its own samples in each row).
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils) {
     std::string err;
     ps_status st = compile_sequence(seq, prog, &err);
     if (st != PS_OK) return fail(st, err);
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
-    const int64_t per_sample = std::max<int64_t>(n_rows, 1) * 2 * real_bytes;
+    const int64_t per_sample = std::max<int64_t>(n_rows, 1) * 2 * real_bytes * std::max(n_coils, 1);
     int64_t max_samples = ctx->cfg.max_partial_bytes / per_sample;
     if (max_samples < 64) max_samples = 64;
     plan_slices(prog, max_samples);
@@ -157,16 +158,28 @@ ps_status wait_previous(Ctx* ctx) {
     return PS_OK;
 }
 
+ps_status validate_receive(const ps_receive* rx, const ps_object* obj) {
+    if (!rx) return PS_OK;
+    if (rx->n_coils < 1) return fail(PS_E_INVALID_ARG, "receive: n_coils < 1");
+    if (rx->reserved != 0) return fail(PS_E_INVALID_ARG, "receive: reserved field must be 0");
+    if (obj && obj->n_spins > 0 && (!rx->s_x || !rx->s_y))
+        return fail(PS_E_INVALID_ARG, "receive: sensitivity array is NULL");
+    return PS_OK;
+}
+
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
-                      int64_t n_samples, hipStream_t stream, int S_override) {
+                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx) {
     ps_status st = validate_object(obj);
     if (st != PS_OK) return st;
+    if ((st = validate_receive(rx, obj)) != PS_OK) return st;
+    const int n_coils = rx ? rx->n_coils : 0;
+    const int n_out = std::max(n_coils, 1);
     const int S = S_override > 0 ? S_override : choose_spins_per_lane(ctx, obj->n_spins);
     const int64_t spb = spins_per_block_of(S);
     const int64_t n_blocks = (obj->n_spins + spb - 1) / spb;
     const int64_t n_rows = n_blocks * rows_per_block_of(S);
     Program prog;
-    if ((st = prepare(ctx, seq, n_rows, S, &prog)) != PS_OK) return st;
+    if ((st = prepare(ctx, seq, n_rows, S, &prog, n_coils)) != PS_OK) return st;
     if (n_samples != prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
                                           std::to_string(prog.n_samples));
@@ -174,7 +187,7 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     if (!signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
     hipError_t e;
     if (obj->n_spins == 0) {
-        if ((e = launch_fill_zero(signal, 2 * n_samples, stream)) != hipSuccess) return hip_fail(e, "fill");
+        if ((e = launch_fill_zero(signal, 2 * n_samples * n_out, stream)) != hipSuccess) return hip_fail(e, "fill");
         return PS_OK;
     }
     if ((st = wait_previous(ctx)) != PS_OK) return st;
@@ -182,7 +195,8 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
     int64_t max_slice = 0;
     for (const Slice& s : prog.slices) max_slice = std::max(max_slice, s.n_samples);
-    const int64_t row_stride = 2 * max_slice;
+    const int64_t coil_stride = 2 * max_slice;      // one block of samples per coil in every row
+    const int64_t row_stride = coil_stride * n_out;
     if ((st = ctx->partial.reserve((size_t)(n_rows * row_stride * real_bytes))) != PS_OK) return st;
     const int64_t fin_doubles = finalize_scratch_doubles(n_rows, row_stride);
     if (fin_doubles > 0 && (st = ctx->fin_scratch.reserve((size_t)fin_doubles * sizeof(double))) != PS_OK)
@@ -199,6 +213,10 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     a.partial = ctx->partial.ptr;
     a.row_stride = row_stride;
     a.state = ctx->state.ptr;
+    a.n_coils = n_coils;
+    a.s_x = rx ? rx->s_x : nullptr;
+    a.s_y = rx ? rx->s_y : nullptr;
+    a.coil_stride = coil_stride;
     const Op* ops_dev = reinterpret_cast<const Op*>(ctx->ops.ptr);
     const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
     for (size_t i = 0; i < prog.slices.size(); ++i) {
@@ -217,11 +235,14 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
         if ((e = launch_step(a, ctx->cfg.precision, S, n_blocks, stream)) != hipSuccess)
             return hip_fail(e, "step kernel launch");
         if (timing) hipEventRecord(t1, stream);
-        if (sl.n_samples > 0 &&
-            (e = launch_finalize(ctx->partial.ptr, ctx->cfg.precision, n_rows, row_stride, 2 * sl.n_samples,
-                                 signal + 2 * sl.sample_begin, reinterpret_cast<double*>(ctx->fin_scratch.ptr),
-                                 stream)) != hipSuccess)
-            return hip_fail(e, "finalize kernel launch");
+        for (int c = 0; c < n_out && sl.n_samples > 0; ++c) {
+            const unsigned char* part = reinterpret_cast<const unsigned char*>(ctx->partial.ptr) +
+                                        (size_t)(c * coil_stride * real_bytes);
+            if ((e = launch_finalize(part, ctx->cfg.precision, n_rows, row_stride, 2 * sl.n_samples,
+                                     signal + 2 * n_samples * c + 2 * sl.sample_begin,
+                                     reinterpret_cast<double*>(ctx->fin_scratch.ptr), stream)) != hipSuccess)
+                return hip_fail(e, "finalize kernel launch");
+        }
         if (timing) {
             hipEventRecord(t2, stream);
             ctx->step_marks.emplace_back(t0, t1);
@@ -324,7 +345,17 @@ ps_status ps_simulate(ps_ctx* handle, const ps_object* obj, const ps_sequence* s
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
-    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0);
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, nullptr);
+}
+
+ps_status ps_simulate_rx(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
+                         double* signal, int64_t n_samples, void* stream) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, rx);
 }
 
 ps_status ps_tile(ps_ctx* handle, int64_t n_spins, int32_t* spins_per_lane, int64_t* spins_per_block) {

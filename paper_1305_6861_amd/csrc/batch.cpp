@@ -120,6 +120,10 @@ StepArgs ReqPlan::args_for_slice(size_t k) const {
     a.load_state = k > 0;
     a.save_state = k + 1 < prog.slices.size();
     a.n_cache_slots = sl.n_cache_slots;
+    a.n_coils = 0;
+    a.s_x = nullptr;
+    a.s_y = nullptr;
+    a.coil_stride = row_stride;
     return a;
 }
 

@@ -512,7 +512,6 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                         f[4] = f[2]; f[5] = f[3];
                     }
                 };
-                real ap[S][8];
                 if (!same_step) {
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
@@ -525,18 +524,41 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                     step_tau = tau;
                     step_valid = true;
                 }
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) ap[s][2 + k] = s_stepf[s][k][tid];
+                // sample-0 magnetisation of this lane's spins
+                real p0r[S], p0i[S];
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     real e2 = Math<real>::expneg(op.txy, sp.r2[s]);
                     real c, sn;
                     Math<real>::cis(phase_rev(op.k, op.txy, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), c, sn);
-                    ap[s][0] = e2 * (sp.ar[s] * c + sp.ai[s] * sn);
-                    ap[s][1] = e2 * (sp.ai[s] * c - sp.ar[s] * sn);
+                    p0r[s] = e2 * (sp.ar[s] * c + sp.ai[s] * sn);
+                    p0i[s] = e2 * (sp.ai[s] * c - sp.ar[s] * sn);
                 }
+                // Receive coils: each coil's pass starts from the sample-0
+                // magnetisation weighted by (S_x - j S_y) of that coil at the
+                // spin; the spins' stepping above is shared by all coils.
+                const int n_passes = a.n_coils > 0 ? a.n_coils : 1;
+                for (int coil = 0; coil < n_passes; ++coil) {
+                real ap[S][8];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) ap[s][2 + k] = s_stepf[s][k][tid];
+                    if (a.n_coils > 0) {
+                        const int64_t i = base + s * 64 + lane;
+                        real sx = 0, sy = 0;
+                        if (i < a.n_spins) {
+                            sx = (real)a.s_x[coil * a.n_spins + i];
+                            sy = (real)a.s_y[coil * a.n_spins + i];
+                        }
+                        ap[s][0] = fma(sx, p0r[s], sy * p0i[s]);
+                        ap[s][1] = fma(sx, p0i[s], -sy * p0r[s]);
+                    } else {
+                        ap[s][0] = p0r[s];
+                        ap[s][1] = p0i[s];
+                    }
+                }
+                real* partial_c = partial + coil * a.coil_stride;
                 // the wave group's G * S spins (LDS exchange when G > 1)
                 real pr[R], pi[R], zr[R], zi[R], Wr[R], Wi[R];
                 if constexpr (G > 1) {
@@ -597,8 +619,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                         pi[q] = a_ * Wi[q] + b_ * Wr[q];
                     }
                     const real v = wave_reduce64(acc, lane);
-                    if (j * kT + (lane >> 1) < n) partial[2 * (int64_t)(aux + j * kT) + lane] = v;
+                    if (j * kT + (lane >> 1) < n) partial_c[2 * (int64_t)(aux + j * kT) + lane] = v;
                 }
+                }   // coil passes
             }
         }
     }

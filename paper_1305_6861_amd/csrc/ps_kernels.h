@@ -20,6 +20,9 @@ struct StepArgs {
     int32_t load_state;      // resume from state instead of equilibrium
     int32_t save_state;      // write the anchors back at the end
     int32_t n_cache_slots;   // shaped-pulse propagator slots the slice's ops use
+    int32_t n_coils;         // receive coils (0: one homogeneous coil, no weights)
+    const float *s_x, *s_y;  // device, n_coils * n_spins transverse sensitivities
+    int64_t coil_stride;     // reals between coils' sample blocks inside a row
 };
 
 // One request of a persistent batched launch: its arguments and the number
