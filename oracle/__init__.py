@@ -44,6 +44,13 @@ def _configure(lib):
         [ctypes.c_int32, _i64p, _dp, _dp, _i64p, _dp, _dp] +
         [ctypes.c_int32, _dp, _dp] +
         [ctypes.c_int, ctypes.c_int64, _dp, _dp])
+    lib.oracle_simulate_full.restype = ctypes.c_int
+    lib.oracle_simulate_full.argtypes = (
+        [ctypes.c_int64] + [_dp] * 7 +
+        [ctypes.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _u32p] +
+        [ctypes.c_int32, _i64p, _dp, _dp, _i64p, _dp, _dp] +
+        [ctypes.c_int32, _dp, _dp, _dp] +
+        [ctypes.c_int, ctypes.c_int64, _dp, _dp])
     lib.oracle_rf_pulse.restype = None
     lib.oracle_rf_pulse.argtypes = [_dp, ctypes.c_double, ctypes.c_double]
     lib.oracle_precess_relax.restype = None
@@ -78,7 +85,11 @@ def default_threads() -> int:
         return max(1, os.cpu_count() or 1)
 
 
-def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False, coils=None):
+SNAPSHOT = 2     # event flag: record every spin's magnetisation at the end of the interval
+
+
+def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False, coils=None,
+             snapshots: bool = False):
     """Signal (complex128, one entry per ADC sample in event order) and,
     when final_m is set, the final magnetisation (n_spins, 3) float64.
 
@@ -86,7 +97,11 @@ def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False, c
     shape (n_coils, n_spins) holding the transverse components of each
     coil's sensitivity at each spin (section 3.5.1, eq. 3.24), float32 as
     the GPU library receives them; the signal is then (n_coils, n_samples),
-    coil c receiving sum_i (S_x Mx + S_y My) + j (S_x My - S_y Mx)."""
+    coil c receiving sum_i (S_x Mx + S_y My) + j (S_x My - S_y Mx).
+
+    snapshots: also return the magnetisation of every spin at the end of
+    every event flagged SNAPSHOT (section 7.2), float64 of shape
+    (n_snapshots, 3, n_spins), as the last element of a tuple."""
     lib = _load()
     n = int(np.asarray(obj.x).shape[0])
     sp = [np.ascontiguousarray(np.asarray(getattr(obj, f), dtype=np.float32), dtype=np.float64)
@@ -124,23 +139,28 @@ def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False, c
             s_x = s_y = np.zeros(1, np.float64)
     out = np.zeros(2 * n_samples * max(n_coils, 1) + 1, np.float64)
     fm = np.zeros(3 * n + 1, np.float64) if final_m else None
+    n_snap = int(np.count_nonzero(fl & SNAPSHOT))
+    snap = np.zeros(3 * n * n_snap + 1, np.float64) if snapshots else None
     nt = int(n_threads or default_threads())
-    rc = lib.oracle_simulate_coils(
+    rc = lib.oracle_simulate_full(
         n, *[_ptr(a, _dp) for a in sp],
         ne, _ptr(dt, _dp), _ptr(m, _dp), _ptr(al, _dp), _ptr(ph, _dp), _ptr(sh, _i32p),
         _ptr(na, _i64p), _ptr(fl, _u32p),
         ns, _ptr(sh_nsub, _i64p), _ptr(sh_tau, _dp), _ptr(sh_m, _dp), _ptr(offs, _i64p),
         _ptr(sh_alpha, _dp), _ptr(sh_phase, _dp),
-        n_coils, _ptr(s_x, _dp), _ptr(s_y, _dp),
+        n_coils, _ptr(s_x, _dp), _ptr(s_y, _dp), _ptr(snap, _dp) if snap is not None else None,
         nt, n_samples, _ptr(out, _dp), _ptr(fm, _dp) if fm is not None else None)
     if rc != 0:
         raise ValueError(f"oracle_simulate failed with code {rc}")
     sig = out[:2 * n_samples * max(n_coils, 1)].view(np.complex128).copy()
     if coils is not None:
         sig = sig.reshape(n_coils, n_samples)
+    res = [sig]
     if final_m:
-        return sig, fm[:3 * n].reshape(n, 3).copy()
-    return sig
+        res.append(fm[:3 * n].reshape(n, 3).copy())
+    if snapshots:
+        res.append(snap[:3 * n * n_snap].reshape(n_snap, 3, n).copy())
+    return res[0] if len(res) == 1 else tuple(res)
 
 
 def rf_pulse(M, alpha: float, phase: float) -> np.ndarray:

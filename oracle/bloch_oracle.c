@@ -28,6 +28,9 @@
  *    pulse, then its interval;
  *  - SPOIL sets Mx = My = 0 at the end of the interval (an idealised
  *    spoiler; the paper has no such primitive);
+ *  - SNAPSHOT records every spin's (Mx, My, Mz) at the end of the interval,
+ *    after the spoiler if both are set (the magnetisation output of section
+ *    7.2, the state the next elementary sequence starts from);
  *  - T1 or T2 = +inf means no relaxation of that kind (exp(-t/inf) = 1).
  *
  * Receive coils (section 3.5.1, eq. 3.24 / 3.25): with an inhomogeneous
@@ -53,6 +56,7 @@
 #include <string.h>
 
 #define ORACLE_SPOIL 1u
+#define ORACLE_SNAPSHOT 2u
 
 typedef struct {
     /* spins */
@@ -73,6 +77,8 @@ typedef struct {
     int32_t n_coils;
     int64_t n_spins;
     const double *s_x, *s_y;
+    /* snapshots: [snapshot][component][spin], may be NULL */
+    double *snap;
 } problem_t;
 
 typedef struct {
@@ -120,6 +126,7 @@ static void run_spin(const problem_t *pb, int64_t i, double *signal, double *fin
     double m0 = pb->m0[i], t1 = pb->t1[i], t2 = pb->t2[i], dw = pb->dw[i];
     double M[3] = {0.0, 0.0, m0};
     int64_t sample = 0;
+    int64_t snap = 0;
 
     for (int64_t e = 0; e < pb->n_events; ++e) {
         int32_t sh = pb->ev_shape[e];
@@ -164,6 +171,12 @@ static void run_spin(const problem_t *pb, int64_t i, double *signal, double *fin
             M[0] = 0.0;
             M[1] = 0.0;
         }
+        if (pb->ev_flags[e] & ORACLE_SNAPSHOT) {
+            if (pb->snap)
+                for (int c = 0; c < 3; ++c)
+                    pb->snap[(3 * snap + c) * pb->n_spins + i] = M[c];
+            ++snap;
+        }
     }
     if (final_m) {
         final_m[3 * i] = M[0];
@@ -181,12 +194,14 @@ static void *worker(void *arg)
 }
 
 /* Returns 0 on success, -1 on an invalid argument, -2 on allocation failure.
- * All arrays are host arrays.  n_coils == 0: one homogeneous coil, out_signal
+ * All arrays are host arrays.  out_snap (may be NULL) receives one block of
+ * 3 * n_spins doubles per event flagged SNAPSHOT, in event order, laid out
+ * [component][spin].  n_coils == 0: one homogeneous coil, out_signal
  * holds 2 * n_samples doubles (interleaved re/im); n_coils >= 1: s_x and
  * s_y hold n_coils * n_spins transverse sensitivities (coil-major) and
  * out_signal holds n_coils blocks of 2 * n_samples.  out_signal and out_final_m (3 * n_spins)
  * may each be NULL. */
-int oracle_simulate_coils(int64_t n_spins,
+int oracle_simulate_full(int64_t n_spins,
                           const double *x, const double *y, const double *z, const double *m0,
                           const double *t1, const double *t2, const double *dw,
                           int64_t n_events, const double *ev_dt, const double *ev_m,
@@ -195,7 +210,7 @@ int oracle_simulate_coils(int64_t n_spins,
                           int32_t n_shapes, const int64_t *sh_nsub, const double *sh_tau,
                           const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
                           const double *sh_phase,
-                          int32_t n_coils, const double *s_x, const double *s_y,
+                          int32_t n_coils, const double *s_x, const double *s_y, double *out_snap,
                           int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
 {
     if (n_spins < 0 || n_events < 0 || n_samples < 0 || n_threads < 1 || n_coils < 0)
@@ -215,7 +230,7 @@ int oracle_simulate_coils(int64_t n_spins,
 
     problem_t pb = {x, y, z, m0, t1, t2, dw, n_events, ev_dt, ev_m, ev_alpha, ev_phase,
                     ev_shape, ev_nadc, ev_flags, n_shapes, sh_nsub, sh_offset, sh_tau, sh_m,
-                    sh_alpha, sh_phase, n_samples, n_coils, n_spins, s_x, s_y};
+                    sh_alpha, sh_phase, n_samples, n_coils, n_spins, s_x, s_y, out_snap};
     const int64_t n_vals = 2 * n_samples * (n_coils > 0 ? n_coils : 1);
 
     if (n_threads > n_spins && n_spins > 0)
@@ -265,7 +280,26 @@ int oracle_simulate_coils(int64_t n_spins,
     return rc;
 }
 
-/* The signal of one homogeneous coil, S = (1, 0, 0); see oracle_simulate_coils. */
+/* Signals of receive coils, no snapshots; see oracle_simulate_full. */
+int oracle_simulate_coils(int64_t n_spins,
+                          const double *x, const double *y, const double *z, const double *m0,
+                          const double *t1, const double *t2, const double *dw,
+                          int64_t n_events, const double *ev_dt, const double *ev_m,
+                          const double *ev_alpha, const double *ev_phase, const int32_t *ev_shape,
+                          const int64_t *ev_nadc, const uint32_t *ev_flags,
+                          int32_t n_shapes, const int64_t *sh_nsub, const double *sh_tau,
+                          const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
+                          const double *sh_phase,
+                          int32_t n_coils, const double *s_x, const double *s_y,
+                          int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
+{
+    return oracle_simulate_full(n_spins, x, y, z, m0, t1, t2, dw, n_events, ev_dt, ev_m, ev_alpha,
+                                ev_phase, ev_shape, ev_nadc, ev_flags, n_shapes, sh_nsub, sh_tau,
+                                sh_m, sh_offset, sh_alpha, sh_phase, n_coils, s_x, s_y, NULL,
+                                n_threads, n_samples, out_signal, out_final_m);
+}
+
+/* The signal of one homogeneous coil, S = (1, 0, 0); see oracle_simulate_full. */
 int oracle_simulate(int64_t n_spins,
                     const double *x, const double *y, const double *z, const double *m0,
                     const double *t1, const double *t2, const double *dw,

@@ -16,8 +16,9 @@ import oracle
 from oracle import build as obuild
 import tests.test_oracle_coils as coil_pins
 import tests.test_oracle_pins as pins
+import tests.test_oracle_snapshots as snapshot_pins
 
-PIN_MODULES = (pins, coil_pins)
+PIN_MODULES = (pins, coil_pins, snapshot_pins)
 
 MUTANTS = {
     "rf_sign_r02": ("r02 = -sp * sa", "r02 = sp * sa"),
@@ -47,6 +48,11 @@ MUTANTS = {
                                 "double sx = pb->s_x[i], sy = pb->s_y[i];"),
     "coil_block_offset": ("double *sc = signal + 2 * pb->n_samples * c;",
                           "double *sc = signal + pb->n_samples * c;"),
+    "snapshot_components_reversed": ("pb->snap[(3 * snap + c) * pb->n_spins + i] = M[c];",
+                                     "pb->snap[(3 * snap + c) * pb->n_spins + i] = M[2 - c];"),
+    "snapshot_index_stuck": ("            ++snap;\n", "\n"),
+    "snapshot_spin_major": ("pb->snap[(3 * snap + c) * pb->n_spins + i] = M[c];",
+                            "pb->snap[3 * snap * pb->n_spins + 3 * i + c] = M[c];"),
 }
 
 

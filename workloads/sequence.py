@@ -19,6 +19,8 @@ Field layout (one entry per elementary sequence):
   flags     uint32   SPOIL: transverse magnetisation is set to zero at the
                      end of the interval (an idealised spoiler; an extension,
                      the paper has no such primitive)
+                     SNAPSHOT: the magnetisation of every spin is recorded at
+                     the end of the interval, after a spoiler (section 7.2)
 
 A Shape (eq. 3.23, hard-pulse approximation of a modulated pulse) is n_sub
 equal sub-steps of length tau, each a hard pulse (alpha_i, phase_i + the
@@ -32,6 +34,7 @@ from typing import List, Optional, Sequence as _Seq
 import numpy as np
 
 SPOIL = 1
+SNAPSHOT = 2
 
 
 @dataclasses.dataclass
