@@ -42,6 +42,10 @@ typedef enum ps_status {
 /* ps_event.flags: transverse magnetisation is set to zero at the end of the
  * interval.  An idealised spoiler; the paper has no such primitive. */
 #define PS_EV_SPOIL 1u
+/* ps_event.flags: record the magnetisation (Mx, My, Mz) of every spin at the
+ * end of the interval, after a spoiler (section 7.2: magnetisation instead of
+ * echo data).  Honoured by ps_simulate_ex; the other entry points ignore it. */
+#define PS_EV_SNAPSHOT 2u
 
 typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
 
@@ -92,7 +96,7 @@ typedef struct ps_event {
                                     added to every sub-pulse phase of rf_shape         */
     int32_t  rf_shape;           /* -1, or index into ps_sequence.shapes               */
     uint32_t n_adc;              /* 0, or number of samples (< 2^31)                   */
-    uint32_t flags;              /* PS_EV_SPOIL                                        */
+    uint32_t flags;              /* PS_EV_SPOIL | PS_EV_SNAPSHOT                       */
     uint32_t reserved;           /* must be 0                                          */
 } ps_event;
 
@@ -168,6 +172,20 @@ typedef struct ps_receive {
  * PS_E_INVALID_ARG for n_coils < 1, a nonzero reserved field or NULL arrays. */
 ps_status ps_simulate_rx(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, const ps_receive *rx,
                          double *signal, int64_t n_samples, void *stream);
+
+/* Number of events flagged PS_EV_SNAPSHOT (validates the sequence). */
+ps_status ps_count_snapshots(const ps_sequence *seq, int64_t *n_snapshots);
+
+/* ps_simulate_rx that also records snapshots: after every event flagged
+ * PS_EV_SNAPSHOT, in event order, the magnetisation of every spin in the
+ * rotating frame.  snapshots: DEVICE, n_snapshots * 3 * n_spins reals of the
+ * stepping precision (float for precision 32, double for 64), laid out
+ * [snapshot][component Mx, My, Mz][spin]; n_snapshots must equal
+ * ps_count_snapshots (snapshots may be NULL when it is 0).  rx may be NULL
+ * (one homogeneous coil).  The signal is bitwise that of ps_simulate_rx. */
+ps_status ps_simulate_ex(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, const ps_receive *rx,
+                         double *signal, int64_t n_samples, void *snapshots, int64_t n_snapshots,
+                         void *stream);
 
 /* Simulate n_requests independent requests together, stream-ordered on
  * `stream`.  All workgroup tiles of all requests form one work queue that a

@@ -24,11 +24,12 @@ from typing import Optional
 import numpy as np
 
 from . import _binding as _b
-from ._binding import PsError, PS_EV_SPOIL
+from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT
 
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
-__all__ = ["Context", "Ticket", "PsError", "PS_EV_SPOIL", "count", "pack_sequence", "to_device", "FIELDS"]
+__all__ = ["Context", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence", "to_device",
+           "FIELDS"]
 
 
 class PackedSequence:
@@ -75,6 +76,11 @@ class PackedSequence:
         ns = ctypes.c_int64(); st = ctypes.c_int64()
         _b.check(_b.lib.ps_count(ctypes.byref(self.struct), ctypes.byref(ns), ctypes.byref(st)))
         return int(ns.value), int(st.value)
+
+    def count_snapshots(self) -> int:
+        n = ctypes.c_int64()
+        _b.check(_b.lib.ps_count_snapshots(ctypes.byref(self.struct), ctypes.byref(n)))
+        return int(n.value)
 
 
 def pack_sequence(seq) -> PackedSequence:
@@ -222,13 +228,17 @@ class Context:
         _b.check(_b.lib.ps_server_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in st._fields_}
 
-    def simulate(self, obj, seq, out=None, stream=None, coils=None):
+    def simulate(self, obj, seq, out=None, stream=None, coils=None, snapshots: bool = False):
         """Signal of one request as a complex128 CUDA tensor (stream-ordered
         on `stream`, default torch's current stream).
 
         coils: optional receive coils, a pair (s_x, s_y) of (n_coils, n_spins)
         arrays or tensors with each coil's transverse sensitivity at each
-        spin (ps_simulate_rx); the signal is then (n_coils, n_samples)."""
+        spin (ps_simulate_rx); the signal is then (n_coils, n_samples).
+        snapshots: also return the magnetisation of every spin after every
+        event flagged PS_EV_SNAPSHOT (ps_simulate_ex), a tensor of shape
+        (n_snapshots, 3, n_spins) in the stepping precision: the call then
+        returns (signal, snapshots)."""
         import torch
         owned = not (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
                                                    for f in FIELDS))
@@ -262,15 +272,25 @@ class Context:
         for t in keep:
             t.record_stream(stream)
         o = _object_struct(dev)
-        if rx is None:
-            _b.check(_b.lib.ps_simulate(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
-                                        ctypes.c_void_p(out.data_ptr() if n_samples else 0),
+        sig_ptr = ctypes.c_void_p(out.data_ptr() if n_samples else 0)
+        if snapshots:
+            n_snap = ps.count_snapshots()
+            snap = torch.empty((n_snap, 3, n_spins), dtype=torch.float32 if self.precision == 32 else torch.float64,
+                               device=f"cuda:{self.device}")
+            _b.check(_b.lib.ps_simulate_ex(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                           ctypes.byref(rx) if rx is not None else None, sig_ptr, n_samples,
+                                           ctypes.c_void_p(snap.data_ptr() if snap.numel() else 0), n_snap,
+                                           ctypes.c_void_p(stream.cuda_stream)))
+        elif rx is None:
+            _b.check(_b.lib.ps_simulate(self._h, ctypes.byref(o), ctypes.byref(ps.struct), sig_ptr,
                                         n_samples, ctypes.c_void_p(stream.cuda_stream)))
-            return out.view(torch.complex128)
-        _b.check(_b.lib.ps_simulate_rx(self._h, ctypes.byref(o), ctypes.byref(ps.struct), ctypes.byref(rx),
-                                       ctypes.c_void_p(out.data_ptr() if n_samples else 0),
-                                       n_samples, ctypes.c_void_p(stream.cuda_stream)))
-        return out.view(torch.complex128).view(max(n_out, 0), n_samples)
+        else:
+            _b.check(_b.lib.ps_simulate_rx(self._h, ctypes.byref(o), ctypes.byref(ps.struct), ctypes.byref(rx),
+                                           sig_ptr, n_samples, ctypes.c_void_p(stream.cuda_stream)))
+        sig = out.view(torch.complex128)
+        if rx is not None:
+            sig = sig.view(max(n_out, 0), n_samples)
+        return (sig, snap) if snapshots else sig
 
 
 class Ticket:

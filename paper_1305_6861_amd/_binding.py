@@ -16,6 +16,7 @@ PS_OK = 0
 STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID_ARG", 2: "PS_E_NO_MEMORY", 3: "PS_E_DEVICE",
                 4: "PS_E_TOO_LARGE", 5: "PS_E_NOT_READY", 6: "PS_E_CANCELLED", 7: "PS_E_NO_DEVICE"}
 PS_EV_SPOIL = 1
+PS_EV_SNAPSHOT = 2
 PS_CFG_KERNEL_TIMING = 1
 PS_CFG_NO_SHAPE_CACHE = 2
 
@@ -110,6 +111,10 @@ SIGNATURES = {
     "ps_simulate_rx": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                       ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p]),
+    "ps_count_snapshots": (ctypes.c_int, [ctypes.POINTER(ps_sequence), ctypes.POINTER(ctypes.c_int64)]),
+    "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
+                                      ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }
 
 

@@ -117,9 +117,10 @@ int shape_cache_slots(const Ctx* ctx, int S, const Program& prog) {
 
 // Compile + slice a request for a given number of partial-sum rows, spins
 // per lane and receive coils (every coil has its own samples in each row).
-ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils) {
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils,
+                  bool snapshots) {
     std::string err;
-    ps_status st = compile_sequence(seq, prog, &err);
+    ps_status st = compile_sequence(seq, prog, &err, snapshots);
     if (st != PS_OK) return fail(st, err);
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
     const int64_t per_sample = std::max<int64_t>(n_rows, 1) * 2 * real_bytes * std::max(n_coils, 1);
@@ -168,7 +169,9 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj) {
 }
 
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
-                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx) {
+                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
+                      void* snaps, int64_t n_snapshots) {
+    // n_snapshots < 0: snapshot flags are ignored (entry points without them)
     ps_status st = validate_object(obj);
     if (st != PS_OK) return st;
     if ((st = validate_receive(rx, obj)) != PS_OK) return st;
@@ -179,15 +182,24 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     const int64_t n_blocks = (obj->n_spins + spb - 1) / spb;
     const int64_t n_rows = n_blocks * rows_per_block_of(S);
     Program prog;
-    if ((st = prepare(ctx, seq, n_rows, S, &prog, n_coils)) != PS_OK) return st;
+    const bool want_snaps = n_snapshots >= 0;
+    if ((st = prepare(ctx, seq, n_rows, S, &prog, n_coils, want_snaps)) != PS_OK) return st;
     if (n_samples != prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
                                           std::to_string(prog.n_samples));
-    if (n_samples == 0) return PS_OK;
-    if (!signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
+    if (want_snaps && n_snapshots != prog.n_snapshots)
+        return fail(PS_E_INVALID_ARG, "n_snapshots (" + std::to_string(n_snapshots) +
+                                          ") differs from the sequence's " + std::to_string(prog.n_snapshots));
+    if (want_snaps && prog.n_snapshots > 0 && obj->n_spins > 0 && !snaps)
+        return fail(PS_E_INVALID_ARG, "snapshots is NULL");
+    if (prog.n_snapshots > 0xffffffffll) return fail(PS_E_TOO_LARGE, "too many snapshots");
+    const bool any_snaps = want_snaps && prog.n_snapshots > 0 && obj->n_spins > 0;
+    if (n_samples == 0 && !any_snaps) return PS_OK;
+    if (n_samples > 0 && !signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
     hipError_t e;
     if (obj->n_spins == 0) {
-        if ((e = launch_fill_zero(signal, 2 * n_samples * n_out, stream)) != hipSuccess) return hip_fail(e, "fill");
+        if (n_samples > 0 && (e = launch_fill_zero(signal, 2 * n_samples * n_out, stream)) != hipSuccess)
+            return hip_fail(e, "fill");
         return PS_OK;
     }
     if ((st = wait_previous(ctx)) != PS_OK) return st;
@@ -217,6 +229,7 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     a.s_x = rx ? rx->s_x : nullptr;
     a.s_y = rx ? rx->s_y : nullptr;
     a.coil_stride = coil_stride;
+    a.snaps = any_snaps ? snaps : nullptr;
     const Op* ops_dev = reinterpret_cast<const Op*>(ctx->ops.ptr);
     const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
     for (size_t i = 0; i < prog.slices.size(); ++i) {
@@ -346,6 +359,28 @@ ps_status ps_simulate(ps_ctx* handle, const ps_object* obj, const ps_sequence* s
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, nullptr);
+}
+
+ps_status ps_count_snapshots(const ps_sequence* seq, int64_t* n_snapshots) {
+    clear_error();
+    Program p;
+    std::string err;
+    ps_status st = compile_sequence(seq, &p, &err);
+    if (st != PS_OK) return fail(st, err);
+    if (n_snapshots) *n_snapshots = p.n_snapshots;
+    return PS_OK;
+}
+
+ps_status ps_simulate_ex(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
+                         double* signal, int64_t n_samples, void* snapshots, int64_t n_snapshots, void* stream) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    if (n_snapshots < 0) return fail(PS_E_INVALID_ARG, "n_snapshots < 0");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, rx, snapshots,
+                       n_snapshots);
 }
 
 ps_status ps_simulate_rx(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,

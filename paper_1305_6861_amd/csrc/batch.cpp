@@ -124,6 +124,7 @@ StepArgs ReqPlan::args_for_slice(size_t k) const {
     a.s_x = nullptr;
     a.s_y = nullptr;
     a.coil_stride = row_stride;
+    a.snaps = nullptr;
     return a;
 }
 

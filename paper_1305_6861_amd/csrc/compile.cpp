@@ -43,7 +43,7 @@ static Op blank_op(uint32_t kind) {
     return op;
 }
 
-ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err) {
+ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err, bool snapshots) {
     if (!seq || !out) { *err = "null sequence or output"; return PS_E_INVALID_ARG; }
     if (seq->n_events < 0) { *err = "n_events < 0"; return PS_E_INVALID_ARG; }
     if (seq->n_events > 0 && !seq->events) { *err = "events is NULL"; return PS_E_INVALID_ARG; }
@@ -88,7 +88,7 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
             *err = where + "rf_shape out of range"; return PS_E_INVALID_ARG;
         }
         if (ev.n_adc > 0x7fffffffu) { *err = where + "n_adc too large"; return PS_E_INVALID_ARG; }
-        if (ev.flags & ~PS_EV_SPOIL) { *err = where + "unknown flag bits"; return PS_E_INVALID_ARG; }
+        if (ev.flags & ~(PS_EV_SPOIL | PS_EV_SNAPSHOT)) { *err = where + "unknown flag bits"; return PS_E_INVALID_ARG; }
         if (ev.reserved != 0) { *err = where + "reserved field must be 0"; return PS_E_INVALID_ARG; }
 
         if (ev.rf_shape >= 0) {
@@ -161,11 +161,22 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
             if (!mxy_zero) p.ops.push_back(blank_op(OP_SPOIL));
             K[0] = K[1] = K[2] = 0; txy = 0; mxy_zero = true;
         }
+        if (ev.flags & PS_EV_SNAPSHOT) {
+            if (snapshots) {
+                Op op = blank_op(OP_SNAP);
+                std::memcpy(op.k, K, sizeof(K));
+                op.txy = txy; op.tz = tz;
+                op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
+                op.aux = (uint32_t)p.n_snapshots;
+                p.ops.push_back(op);
+            }
+            p.n_snapshots += 1;
+        }
     }
-    // Operations after the last readout cannot change the signal.
+    // Operations after the last readout or snapshot cannot change an output.
     size_t keep = 0;
     for (size_t i = 0; i < p.ops.size(); ++i)
-        if (p.ops[i].kind == OP_ADC) keep = i + 1;
+        if (p.ops[i].kind == OP_ADC || p.ops[i].kind == OP_SNAP) keep = i + 1;
     p.ops.resize(keep);
     if ((int64_t)(p.rows.size() / 9) > kMaxShapeRows) {
         *err = "shaped pulses need " + std::to_string(p.rows.size() / 9) +

@@ -23,6 +23,7 @@ struct Program {
     int64_t n_samples = 0;
     int64_t n_steps = 0;               // intervals per spin (see ps_count)
     int64_t n_rf = 0, n_shape_substeps = 0, n_adc_ops = 0;
+    int64_t n_snapshots = 0;           // events flagged PS_EV_SNAPSHOT
     std::vector<Slice> slices;
 };
 
@@ -34,7 +35,9 @@ void rf_matrix(double alpha, double phi, double r[9]);
 void rf_delta(double alpha, double phi, double d[9]);
 
 // Validate and compile; on failure returns an error status and sets *err.
-ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err);
+// With snapshots, events flagged PS_EV_SNAPSHOT become OP_SNAP operations;
+// without, the flag is only counted.
+ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err, bool snapshots = false);
 
 // Cut the program into time slices of at most max_samples samples each
 // (ADC operations longer than that are split exactly), setting every ADC

@@ -417,6 +417,20 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
             } else if (kind == OP_SPOIL) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) { sp.ar[s] = 0; sp.ai[s] = 0; }
+            } else if (kind == OP_SNAP) {
+                // magnetisation of every spin at this instant (section 7.2);
+                // the anchors are left as they are
+                real mx[S], my[S], mz[S];
+                evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
+                real* out = reinterpret_cast<real*>(a.snaps) +
+                            (int64_t)__builtin_amdgcn_readfirstlane(op.aux) * 3 * a.n_spins;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int64_t i = base + s * 64 + lane;
+                    if (i < a.n_spins) {
+                        out[i] = mx[s]; out[a.n_spins + i] = my[s]; out[2 * a.n_spins + i] = mz[s];
+                    }
+                }
             } else if (kind == OP_SHAPE) {
                 // Shaped pulse (eq. 3.23): n_sub sub-steps, each a hard
                 // sub-pulse, precession/decay by u and T1 recovery, all in

@@ -23,6 +23,7 @@ struct StepArgs {
     int32_t n_coils;         // receive coils (0: one homogeneous coil, no weights)
     const float *s_x, *s_y;  // device, n_coils * n_spins transverse sensitivities
     int64_t coil_stride;     // reals between coils' sample blocks inside a row
+    void* snaps;             // device, n_snapshots * 3 * n_spins reals (OP_SNAP targets)
 };
 
 // One request of a persistent batched launch: its arguments and the number

@@ -25,6 +25,7 @@ enum OpKind : uint32_t {
     OP_ADC = 2,    // n samples at k, k + mu, ...; txy, txy + tau, ...
     OP_SPOIL = 3,  // Mxy_a := 0 (transverse anchor reset)
     OP_SHAPE = 4,  // shaped pulse: evaluate, then n_sub sub-steps (eq. 3.23)
+    OP_SNAP = 5,   // evaluate and store every spin's M as snapshot aux
 };
 
 enum OpFlags : uint32_t {
@@ -55,7 +56,8 @@ struct alignas(16) Op {
     uint32_t flags;
     uint32_t n;    // ADC: samples; SHAPE: sub-steps
     uint32_t aux;  // ADC: first sample's offset inside the time slice;
-                   // SHAPE: first sub-step index in the shape rotation table
+                   // SHAPE: first sub-step index in the shape rotation table;
+                   // SNAP: snapshot index
 };
 static_assert(sizeof(Op) == 128, "Op must be 128 bytes");
 

@@ -58,13 +58,15 @@ struct Ctx {
 int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins);
 hipEvent_t timing_event(Ctx* ctx);  // from the pool (timing-enabled contexts)
 ps_status validate_object(const ps_object* obj);
-ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils = 0);
+ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils = 0,
+                  bool snapshots = false);
 // Propagator cache slots a request tiled with S spins per lane may use.
 int shape_cache_slots(const Ctx* ctx, int S, const Program& prog);
 ps_status wait_previous(Ctx* ctx);
 ps_status validate_receive(const ps_receive* rx, const ps_object* obj);
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
-                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx);
+                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
+                      void* snaps = nullptr, int64_t n_snapshots = -1);
 void destroy_runtime(Ctx* ctx);    // stops the server if one runs
 
 }  // namespace ps
