@@ -70,6 +70,11 @@ def bench_c4(args):
            "one_per_launch_ms": res["one_per_launch"] * 1e3,
            "speedup_vs_one_per_launch": res["one_per_launch"] / res["batched"],
            "roofline": None, "cpu_baseline": None}
+    if args.workload in PAPER_T78_SECONDS:
+        t_paper = PAPER_T78_SECONDS[args.workload]
+        rec["paper_context"] = {"t_sim_s": t_paper, "source": "Table 7.8, PARSPIN 1.5.0",
+                                "hardware": "PVM cluster of 5 Sun Ultra-1 170",
+                                "speedup_of_this_run": t_paper / (ms_per_step * 1e-3)}
     if not args.no_cpu_baseline:
         import oracle
         got = [t.cpu().numpy() for t in batched()]
@@ -176,7 +181,30 @@ WORKLOADS = {
            "spin echo 90x/180y TE 20 ms TR 500 ms, 256 phase encodes x 256 samples"),
     "c3": ("c3: 3-D 128^3 grid x two species (4,194,304 spins), quadratic B0 +-50 Hz, fat -440 Hz; "
            "GRE with 128-sub-step TBW-4 sinc (30 deg), TE 5 ms TR 10 ms, 128x128 phase encodes x 128 samples"),
+    "t78-tse": ("Table 7.8 2-D turbo spin echo: 100^2 grid (10,000 spins) with the eq. 6.3 Legendre B0, "
+                "128^2 matrix, echo train 16, ESP 10 ms"),
+    "t78-radial": ("Table 7.8 2-D radial: 100^2 grid (10,000 spins) with the eq. 6.3 Legendre B0, "
+                   "128 spokes x 128 samples, spoiled GRE"),
+    "t78-epi": ("Table 7.8 2-D EPI: 100^2 grid (10,000 spins) with the eq. 6.3 Legendre B0, "
+                "single shot, 128 lines x 128 samples"),
+    "t78-se3d": ("Table 7.8 3-D spin echo: 56^3 grid (175,616 spins) with the eq. 6.3 Legendre B0, "
+                 "128 samples x 128 x 64 phase encodes"),
 }
+
+# Table 7.8, PARSPIN 1.5.0 on a PVM cluster of five Sun Ultra-1 170: context only
+# (different hardware, the paper's Shepp-Logan phantom instead of these grids).
+PAPER_T78_SECONDS = {"t78-tse": 18.0, "t78-radial": 13.0, "t78-epi": 11.0, "t78-se3d": 4 * 3600.0}
+
+
+def load_workload(name: str):
+    from workloads import configs as C
+    if name == "c2":
+        return C.c2()
+    if name == "c3":
+        return C.c3()
+    if name.startswith("t78-"):
+        return C.table78(name[4:])
+    raise ValueError(name)
 
 
 def algorithmic_flops(seq, n_spins: int, n_coils: int = 1) -> float:
@@ -297,7 +325,7 @@ def main():
     import paper_1305_6861_amd as ps
     from workloads import configs as C
 
-    obj, seq = C.c2() if args.workload == "c2" else C.c3()
+    obj, seq = load_workload(args.workload)
     dev = ps.to_device(obj)
     cache = not args.no_shape_cache
     ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache)
@@ -354,6 +382,11 @@ def main():
                       "receive_coils": args.coils or "one homogeneous coil"},
            "eta_spins_per_s": obj.n_spins / (ms_per_step * 1e-3),
            "roofline": roof}
+    if args.workload in PAPER_T78_SECONDS:
+        t_paper = PAPER_T78_SECONDS[args.workload]
+        rec["paper_context"] = {"t_sim_s": t_paper, "source": "Table 7.8, PARSPIN 1.5.0",
+                                "hardware": "PVM cluster of 5 Sun Ultra-1 170",
+                                "speedup_of_this_run": t_paper / (ms_per_step * 1e-3)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(obj, seq, ctx, args.cpu_seconds, rx_np)
     else:

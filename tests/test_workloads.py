@@ -134,3 +134,40 @@ def test_grid_is_seeded():
     b = grid2d(16, seed=3, iso_per_voxel=4, jitter=True, dw_sigma_hz=20)
     np.testing.assert_array_equal(a.x, b.x)
     np.testing.assert_array_equal(a.dw, b.dw)
+
+
+def test_legendre_polynomial_matches_scipy():
+    from scipy.special import eval_legendre
+    from workloads.phantom import legendre_p
+    x = np.linspace(-1, 1, 401)
+    for l in (0, 1, 2, 5, 12):
+        np.testing.assert_allclose(legendre_p(l, x), eval_legendre(l, x), rtol=1e-12, atol=1e-13)
+
+
+def test_legendre_b0_field_eq_6_3():
+    """On the z axis P_12(1) = 1, so dB0 = -C (r/R)^12; in the z = 0 plane
+    P_12(0) = 231/1024 (a positive constant); zero field at the centre."""
+    from workloads.phantom import legendre_b0_tesla
+    r = np.linspace(0, 0.3, 13)
+    np.testing.assert_allclose(legendre_b0_tesla(0 * r, 0 * r, r, 2e-5, 0.2), -2e-5 * (r / 0.2) ** 12, rtol=1e-12)
+    np.testing.assert_allclose(legendre_b0_tesla(r, 0 * r, 0 * r, 2e-5, 0.2),
+                               -2e-5 * (r / 0.2) ** 12 * 231 / 1024, rtol=1e-12, atol=1e-30)
+    assert legendre_b0_tesla(0.0, 0.0, 0.0, 1.0, 0.2) == 0.0
+
+
+def test_table78_workloads():
+    from workloads import configs as C
+    sizes = {}
+    for k in C.TABLE78:
+        obj, seq = C.table78(k)
+        sizes[k] = (obj.n_spins, seq.n_samples)
+        assert np.all(np.isfinite(obj.dw))
+    assert sizes["tse"] == sizes["radial"] == sizes["epi"] == (10000, 128 * 128)
+    assert sizes["se3d"] == (56 ** 3, 128 * 128 * 64)
+    # the radial spokes cross the k-space centre at sample n/2
+    seq = C.radial_2d(16, 8)
+    m = seq.m
+    for p in range(8):
+        pre, ro = m[3 * p], m[3 * p + 1]
+        k_mid = pre + ro * (16 // 2 + 1) / 16
+        np.testing.assert_allclose(k_mid, 0.0, atol=1e-9)

@@ -240,3 +240,129 @@ def inversion_recovery(ti: float, read_delay: float = 0.0) -> Sequence:
     seq.add(ti, alpha=math.pi, flags=SPOIL)
     seq.add(read_delay, alpha=math.pi / 2, n_adc=1)
     return seq
+
+
+# --------------------------------------------------------------------------
+# the experiments of Table 7.8 (section 7.3.2) on synthetic objects
+# --------------------------------------------------------------------------
+# The paper times a 2-D turbo spin echo, a 2-D radial and a 2-D EPI
+# acquisition (128^2 matrix, 10,000 spins) and a 3-D spin echo (128^2 x 64,
+# 176,000 spins), with its Shepp-Logan phantom and the Legendre B0 field of
+# eq. 6.3.  Here the objects are tissue-recipe grids of the same spin counts
+# (100^2 and 56^3) with the eq. 6.3 field; the sequences are standard forms
+# of the four acquisitions built from elementary sequences.  The event counts
+# need not equal the paper's (its event granularity is not given).
+LEGENDRE_C_TESLA = 1e-5      # C of eq. 6.3 (free constant, 1 tesla dimension)
+LEGENDRE_RADIUS = 0.2        # radius of the sphere of homogeneity, m
+
+
+def tse_2d(n: int, etl: int, fov: float = FOV, esp: float = 10e-3, tr: float = 2.0,
+           dwell: float = 10e-6, name: str = "tse2d") -> Sequence:
+    """Turbo spin echo (CPMG): per TR a 90x pulse, then etl echoes, each
+    [180y, read prephase + phase encode] [ADC n] [rewind]; the echo (sample
+    n/2) sits midway between refocusing pulses, and k returns to the origin
+    before every 180.  Line order: echo j of TR t takes line j * n_tr + t."""
+    if n % etl:
+        raise ValueError("etl must divide n")
+    n_tr = n // etl
+    seq = Sequence(name)
+    half = n // 2
+    t_pre = esp / 2 - (half + 1) * dwell
+    t_rew = esp / 2 - (n - half - 1) * dwell
+    if t_pre < 0 or t_rew < 0:
+        raise ValueError("echo spacing too short for this readout")
+    for t in range(n_tr):
+        seq.add(esp / 2, alpha=math.pi / 2, phase=0.0)
+        for j in range(etl):
+            ky = (j * n_tr + t - half) / fov
+            seq.add(t_pre, m=(-(half + 1) / fov, ky, 0.0), alpha=math.pi, phase=math.pi / 2)
+            seq.add(n * dwell, m=(n / fov, 0.0, 0.0), n_adc=n)
+            seq.add(t_rew, m=(-(n - half - 1) / fov, -ky, 0.0))
+        seq.add(tr - esp / 2 - etl * esp, flags=SPOIL)
+    seq.meta.update(kind="tse2d", n=n, etl=etl, fov=fov, esp=esp, tr=tr, dwell=dwell)
+    return seq
+
+
+def radial_2d(n: int, n_proj: int, fov: float = FOV, alpha_deg: float = 30.0, tr: float = 10e-3,
+              te: float = 4e-3, dwell: float = 10e-6, name: str = "radial2d") -> Sequence:
+    """Radial spoiled gradient echo: projection p reads a full spoke through
+    the k-space centre at angle pi p / n_proj, with prephaser and readout
+    along (cos, sin) of that angle."""
+    seq = Sequence(name)
+    half = n // 2
+    t_pre = te - (half + 1) * dwell
+    t_rest = tr - t_pre - n * dwell
+    if t_pre < 0 or t_rest < 0:
+        raise ValueError("TE/TR too short for this readout")
+    for p in range(n_proj):
+        th = math.pi * p / n_proj
+        d = (math.cos(th), math.sin(th), 0.0)
+        seq.add(t_pre, m=tuple(-(half + 1) / fov * c for c in d), alpha=alpha_deg * DEG)
+        seq.add(n * dwell, m=tuple(n / fov * c for c in d), n_adc=n)
+        seq.add(t_rest, flags=SPOIL)
+    seq.meta.update(kind="radial2d", n=n, n_proj=n_proj, fov=fov, tr=tr, te=te, dwell=dwell)
+    return seq
+
+
+def epi_2d(n: int, fov: float = FOV, dwell: float = 4e-6, blip: float = 40e-6, t_pre: float = 5e-3,
+           name: str = "epi2d") -> Sequence:
+    """Single-shot gradient-echo EPI: 90x with prephasers to the k-space
+    corner, then n readout lines of alternating polarity with a ky blip of
+    1/fov between lines, and a final spoiled interval."""
+    seq = Sequence(name)
+    half = n // 2
+    seq.add(t_pre, m=(-(half + 1) / fov, -half / fov, 0.0), alpha=math.pi / 2)
+    for line in range(n):
+        sgn = 1.0 if line % 2 == 0 else -1.0
+        seq.add(n * dwell, m=(sgn * n / fov, 0.0, 0.0), n_adc=n)
+        if line + 1 < n:
+            seq.add(blip, m=(0.0, 1.0 / fov, 0.0))
+    seq.add(1e-3, flags=SPOIL)
+    seq.meta.update(kind="epi2d", n=n, fov=fov, dwell=dwell, blip=blip)
+    return seq
+
+
+def se_3d(n: int, n_pe_y: int, n_pe_z: int, fov: float = FOV, te: float = 20e-3, tr: float = 0.5,
+          dwell: float = 10e-6, name: str = "se3d") -> Sequence:
+    """3-D spin echo: per TR [90x, TE/2] [180y, read prephase + (ky, kz)
+    encode] [ADC n] [rest, SPOIL]; kz outer loop."""
+    seq = Sequence(name)
+    half = n // 2
+    t_pre = te / 2 - (half + 1) * dwell
+    t_rest = tr - te / 2 - t_pre - n * dwell
+    if t_pre < 0 or t_rest < 0:
+        raise ValueError("TE/TR too short for this readout")
+    for jz in range(n_pe_z):
+        kz = (jz - n_pe_z // 2) / fov
+        for jy in range(n_pe_y):
+            ky = (jy - n_pe_y // 2) / fov
+            seq.add(te / 2, alpha=math.pi / 2)
+            seq.add(t_pre, m=(-(half + 1) / fov, ky, kz), alpha=math.pi, phase=math.pi / 2)
+            seq.add(n * dwell, m=(n / fov, 0.0, 0.0), n_adc=n)
+            seq.add(t_rest, flags=SPOIL)
+    seq.meta.update(kind="se3d", n=n, n_pe_y=n_pe_y, n_pe_z=n_pe_z, fov=fov, te=te, tr=tr, dwell=dwell)
+    return seq
+
+
+TABLE78 = ("tse", "radial", "epi", "se3d")
+
+
+def table78(kind: str, scale: int = 1) -> Tuple[SpinObject, Sequence]:
+    """One experiment of Table 7.8: scale = 1 is the paper's size (128^2
+    matrix, 10,000 spins; 3-D: 128^2 x 64, 175,616 spins); scale = s divides
+    the matrix and the object side by s (for oracle-sized tests)."""
+    from .phantom import grid2d_legendre, grid3d_legendre
+    n = 128 // scale
+    if kind == "se3d":
+        obj = grid3d_legendre(max(56 // scale, 2), FOV, seed=7804, c_tesla=LEGENDRE_C_TESLA,
+                              radius=LEGENDRE_RADIUS)
+        return obj, se_3d(n, n, max(64 // scale, 1))
+    obj = grid2d_legendre(max(100 // scale, 2), FOV, seed={"tse": 7801, "radial": 7802, "epi": 7803}[kind],
+                          c_tesla=LEGENDRE_C_TESLA, radius=LEGENDRE_RADIUS)
+    if kind == "tse":
+        return obj, tse_2d(n, max(16 // scale, 2))
+    if kind == "radial":
+        return obj, radial_2d(n, n)
+    if kind == "epi":
+        return obj, epi_2d(n)
+    raise ValueError(f"unknown Table 7.8 experiment {kind!r}")

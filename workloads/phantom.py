@@ -181,3 +181,57 @@ def random_spins(n: int, seed: int, fov: float = 0.25, dw_sigma_hz: float = 30.0
         sel = rng.uniform(size=n) < t_inf_frac
         t1 = np.where(sel, np.inf, t1); t2 = np.where(sel, np.inf, t2)
     return SpinObject(x=pos[0], y=pos[1], z=pos[2], m0=rho, t1=t1, t2=t2, dw=dw)
+
+
+GAMMA_RAD = 2.0 * np.pi * 42.577478e6     # 1H gyromagnetic ratio, rad/(s T)
+
+
+def legendre_p(l: int, x) -> np.ndarray:
+    """Legendre polynomial P_l(x) by Bonnet's recursion
+    (k + 1) P_{k+1} = (2k + 1) x P_k - k P_{k-1}."""
+    x = np.asarray(x, np.float64)
+    p0, p1 = np.ones_like(x), x.copy()
+    if l == 0:
+        return p0
+    for k in range(1, l):
+        p0, p1 = p1, ((2 * k + 1) * x * p1 - k * p0) / (k + 1)
+    return p1
+
+
+def legendre_b0_tesla(x, y, z, c_tesla: float, radius: float, order: int = 12) -> np.ndarray:
+    """Main-field deviation of a whole-body magnet outside its sphere of
+    homogeneity (eq. 6.3): dB0 = -C (r / R)^12 P_12(cos theta), r = |x|,
+    theta the angle to the z axis.  Returns tesla, float64."""
+    x = np.asarray(x, np.float64); y = np.asarray(y, np.float64); z = np.asarray(z, np.float64)
+    r = np.sqrt(x * x + y * y + z * z)
+    cos_t = np.divide(z, r, out=np.ones_like(r), where=r > 0)
+    return -c_tesla * (r / radius) ** order * legendre_p(order, cos_t)
+
+
+def grid2d_legendre(n_side: int, fov: float, seed: int, c_tesla: float, radius: float,
+                    gamma: float = GAMMA_RAD) -> SpinObject:
+    """n_side^2 spins on a grid in the z = 0 plane with the tissue recipe and
+    the eq. 6.3 field deviation as off-resonance dw = gamma dB0 (rad/s)."""
+    rng = np.random.default_rng(seed)
+    c = grid_positions(n_side, fov)
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    xx = xx.reshape(-1); yy = yy.reshape(-1)
+    rho, t1, t2 = _tissue(rng, xx.size)
+    dw = gamma * legendre_b0_tesla(xx, yy, np.zeros_like(xx), c_tesla, radius)
+    obj = SpinObject(x=xx, y=yy, z=np.zeros_like(xx), m0=rho, t1=t1, t2=t2, dw=dw)
+    obj.meta.update(kind="grid2d_legendre", n=n_side, fov=fov, seed=seed, c_tesla=c_tesla, radius=radius)
+    return obj
+
+
+def grid3d_legendre(n_side: int, fov: float, seed: int, c_tesla: float, radius: float,
+                    gamma: float = GAMMA_RAD) -> SpinObject:
+    """n_side^3 spins on a grid with the tissue recipe and the eq. 6.3 field."""
+    rng = np.random.default_rng(seed)
+    c = grid_positions(n_side, fov)
+    zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+    xx = xx.reshape(-1); yy = yy.reshape(-1); zz = zz.reshape(-1)
+    rho, t1, t2 = _tissue(rng, xx.size)
+    dw = gamma * legendre_b0_tesla(xx, yy, zz, c_tesla, radius)
+    obj = SpinObject(x=xx, y=yy, z=zz, m0=rho, t1=t1, t2=t2, dw=dw)
+    obj.meta.update(kind="grid3d_legendre", n=n_side, fov=fov, seed=seed, c_tesla=c_tesla, radius=radius)
+    return obj
