@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan", action="store_true",
+                    help="time replays of a compiled plan (HIP graph: no host compile or upload per step)")
     ap.add_argument("--coils", type=int, default=0,
                     help="receive with this many loop coils on a ring around the object (0: one homogeneous coil)")
     ap.add_argument("--no-shape-cache", action="store_true",
@@ -339,18 +341,38 @@ def main():
     out = torch.empty(2 * n_samples * max(args.coils, 1), dtype=torch.float64, device="cuda")
     spl, _ = ctx.tile(obj.n_spins)
 
+    if args.plan:
+        plan = ctx.plan(dev, packed, coils=rx)
+
+        def step():
+            plan.launch()
+    else:
+        def step():
+            ctx.simulate(dev, packed, out=out, coils=rx)
     for _ in range(args.warmup):
-        ctx.simulate(dev, packed, out=out, coils=rx)
+        step()
     torch.cuda.synchronize()
     ctx.kernel_times()                     # forget warm-up launches
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.simulate(dev, packed, out=out, coils=rx)
+        step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms, fin_ms = ctx.kernel_times()
+    if args.plan:
+        # a replay is one graph launch on torch's current stream: bracket each
+        # with events there (step and finalize kernels together)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a_ev, b_ev in evs:
+            a_ev.record()
+            step()
+            b_ev.record()
+        torch.cuda.synchronize()
+        step_ms = [a_ev.elapsed_time(b_ev) for a_ev, b_ev in evs]
+        fin_ms = 0.0
 
     spin_steps = float(obj.n_spins) * n_steps
     ms_per_step = 1e3 * elapsed / args.steps
@@ -368,6 +390,9 @@ def main():
             "kernel_ms_per_launch": k_ms / max(launches, 1),
             "flops_per_step": flops, "flops_per_launch": flops / max(launches, 1),
             "finalize_ms_per_step": fin_ms / max(args.steps, 1)}
+    if args.plan:
+        roof["kernel"] += " + finalize (one graph replay per step)"
+        roof["timing"] = "HIP events around each graph replay on its stream"
     if cache and any(int(x) >= 0 for x in seq.rf_shape):
         # recurring shaped pulses applied from per-spin propagators: the flop
         # basis is the sub-step path's, so achieved and frac are effective
@@ -379,7 +404,8 @@ def main():
            "config": {"workload": WORKLOADS[args.workload], "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
                       "n_samples": n_samples, "spins_per_lane": spl, "precision": "fp32 stepping, "
                       "fp64 phases and cross-block sums", "shape_cache": cache,
-                      "receive_coils": args.coils or "one homogeneous coil"},
+                      "receive_coils": args.coils or "one homogeneous coil",
+                      "step": "plan replay (HIP graph)" if args.plan else "full call: compile, upload, kernels"},
            "eta_spins_per_s": obj.n_spins / (ms_per_step * 1e-3),
            "roofline": roof}
     if args.workload in PAPER_T78_SECONDS:

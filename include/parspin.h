@@ -187,6 +187,23 @@ ps_status ps_simulate_ex(ps_ctx *ctx, const ps_object *obj, const ps_sequence *s
                          double *signal, int64_t n_samples, void *snapshots, int64_t n_snapshots,
                          void *stream);
 
+/* Compiled plans: one request compiled once and its kernel launches captured
+ * in a HIP graph, for callers that simulate the same (object layout,
+ * sequence, coils) many times, e.g. parameter sweeps that rewrite the object
+ * arrays in place.  The plan owns its device tables and work buffers; the
+ * pointers in obj, rx and signal are captured and must stay valid while the
+ * plan exists (their contents may change between replays).  Arguments and
+ * errors as for ps_simulate_rx (rx may be NULL).  Snapshots are not captured. */
+typedef struct ps_plan ps_plan;
+ps_status ps_plan_create(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, const ps_receive *rx,
+                         double *signal, int64_t n_samples, ps_plan **plan);
+/* Replay the plan, stream-ordered on `stream`: one graph launch; the result
+ * is bitwise that of ps_simulate_rx on the same context.  Replays of one plan
+ * share its buffers: launch them on one stream (they then run in order). */
+ps_status ps_plan_launch(ps_plan *plan, void *stream);
+/* Wait for the plan's last replay, then free it. */
+void ps_plan_destroy(ps_plan *plan);
+
 /* Simulate n_requests independent requests together, stream-ordered on
  * `stream`.  All workgroup tiles of all requests form one work queue that a
  * persistent kernel drains (one launch per spins-per-lane class and time

@@ -28,7 +28,7 @@ from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT
 
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
-__all__ = ["Context", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence", "to_device",
+__all__ = ["Context", "Plan", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence", "to_device",
            "FIELDS"]
 
 
@@ -223,6 +223,10 @@ class Context:
                                   ctypes.c_void_p(out.data_ptr() if ns else 0), ns, ctypes.byref(t)))
         return Ticket(self, int(t.value), out, dev)
 
+    def plan(self, obj, seq, coils=None) -> Plan:
+        """Compile once and capture the launches in a HIP graph (ps_plan_create)."""
+        return Plan(self, obj, seq, coils)
+
     def server_stats(self):
         st = _b.ps_server_stats_t()
         _b.check(_b.lib.ps_server_stats(self._h, ctypes.byref(st)))
@@ -246,19 +250,7 @@ class Context:
         ps = pack_sequence(seq)
         n_samples, _ = ps.count()
         n_spins = int(dev["x"].numel())
-        rx, keep = None, []
-        if coils is not None:
-            cs = []
-            for c in coils:
-                t = torch.as_tensor(c, dtype=torch.float32).to(f"cuda:{self.device}").contiguous()
-                if t.dim() != 2 or t.shape[1] != n_spins:
-                    raise PsError(1, f"coil sensitivities must have shape (n_coils, {n_spins})")
-                cs.append(t)
-            if len(cs) != 2 or cs[0].shape != cs[1].shape:
-                raise PsError(1, "coils must be a pair (s_x, s_y) of equal shape")
-            keep = cs
-            rx = _b.ps_receive(int(cs[0].shape[0]), 0, cs[0].data_ptr() if cs[0].numel() else 0,
-                               cs[1].data_ptr() if cs[1].numel() else 0)
+        keep, rx = _receive(coils, n_spins, self.device)
         n_out = rx.n_coils if rx is not None else 1
         if out is None:
             out = torch.empty(2 * n_samples * max(n_out, 1), dtype=torch.float64, device=f"cuda:{self.device}")
@@ -291,6 +283,79 @@ class Context:
         if rx is not None:
             sig = sig.view(max(n_out, 0), n_samples)
         return (sig, snap) if snapshots else sig
+
+
+class Plan:
+    """A request compiled once with its launches captured in a HIP graph
+    (ps_plan_create); launch() replays it.  The object tensors, coil
+    sensitivities and the output tensor are fixed at creation; rewrite their
+    contents in place between launches to simulate new parameters."""
+
+    def __init__(self, ctx: "Context", obj, seq, coils=None):
+        import torch
+        self.ctx = ctx
+        self.obj = obj if (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
+                                                         for f in FIELDS)) else to_device(obj, f"cuda:{ctx.device}")
+        ps = pack_sequence(seq)
+        self.n_samples, _ = ps.count()
+        n_spins = int(self.obj["x"].numel())
+        self.coils, rx = _receive(coils, n_spins, ctx.device)
+        self.n_out = rx.n_coils if rx is not None else 1
+        self.out = torch.zeros(2 * self.n_samples * max(self.n_out, 1), dtype=torch.float64,
+                               device=f"cuda:{ctx.device}")
+        torch.cuda.synchronize(ctx.device)           # inputs resident before the capture
+        o = _object_struct(self.obj)
+        h = ctypes.c_void_p()
+        _b.check(_b.lib.ps_plan_create(ctx._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                       ctypes.byref(rx) if rx is not None else None,
+                                       ctypes.c_void_p(self.out.data_ptr() if self.n_samples else 0),
+                                       self.n_samples, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        """Replay on `stream` (default torch's current stream); returns the
+        signal tensor (complex128, (n_coils, n_samples) with coils)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.ctx.device)
+        _b.check(_b.lib.ps_plan_launch(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        sig = self.out.view(torch.complex128)
+        return sig.view(self.n_out, self.n_samples) if self.coils else sig
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _b.lib.ps_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _receive(coils, n_spins: int, device: int):
+    """(kept tensors, ps_receive or None) for a pair (s_x, s_y)."""
+    import torch
+    if coils is None:
+        return [], None
+    cs = []
+    for c in coils:
+        t = torch.as_tensor(c, dtype=torch.float32).to(f"cuda:{device}").contiguous()
+        if t.dim() != 2 or t.shape[1] != n_spins:
+            raise PsError(1, f"coil sensitivities must have shape (n_coils, {n_spins})")
+        cs.append(t)
+    if len(cs) != 2 or cs[0].shape != cs[1].shape:
+        raise PsError(1, "coils must be a pair (s_x, s_y) of equal shape")
+    rx = _b.ps_receive(int(cs[0].shape[0]), 0, cs[0].data_ptr() if cs[0].numel() else 0,
+                       cs[1].data_ptr() if cs[1].numel() else 0)
+    return cs, rx
 
 
 class Ticket:

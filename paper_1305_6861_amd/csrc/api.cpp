@@ -168,22 +168,22 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj) {
     return PS_OK;
 }
 
-ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
-                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
-                      void* snaps, int64_t n_snapshots) {
+ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
+                      double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
+                      Single* r) {
     // n_snapshots < 0: snapshot flags are ignored (entry points without them)
     ps_status st = validate_object(obj);
     if (st != PS_OK) return st;
     if ((st = validate_receive(rx, obj)) != PS_OK) return st;
-    const int n_coils = rx ? rx->n_coils : 0;
-    const int n_out = std::max(n_coils, 1);
-    const int S = S_override > 0 ? S_override : choose_spins_per_lane(ctx, obj->n_spins);
-    const int64_t spb = spins_per_block_of(S);
-    const int64_t n_blocks = (obj->n_spins + spb - 1) / spb;
-    const int64_t n_rows = n_blocks * rows_per_block_of(S);
-    Program prog;
+    r->n_coils = rx ? rx->n_coils : 0;
+    r->n_out = std::max(r->n_coils, 1);
+    r->S = S_override > 0 ? S_override : choose_spins_per_lane(ctx, obj->n_spins);
+    const int64_t spb = spins_per_block_of(r->S);
+    r->n_blocks = (obj->n_spins + spb - 1) / spb;
+    r->n_rows = r->n_blocks * rows_per_block_of(r->S);
     const bool want_snaps = n_snapshots >= 0;
-    if ((st = prepare(ctx, seq, n_rows, S, &prog, n_coils, want_snaps)) != PS_OK) return st;
+    if ((st = prepare(ctx, seq, r->n_rows, r->S, &r->prog, r->n_coils, want_snaps)) != PS_OK) return st;
+    const Program& prog = r->prog;
     if (n_samples != prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
                                           std::to_string(prog.n_samples));
@@ -193,45 +193,53 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     if (want_snaps && prog.n_snapshots > 0 && obj->n_spins > 0 && !snaps)
         return fail(PS_E_INVALID_ARG, "snapshots is NULL");
     if (prog.n_snapshots > 0xffffffffll) return fail(PS_E_TOO_LARGE, "too many snapshots");
-    const bool any_snaps = want_snaps && prog.n_snapshots > 0 && obj->n_spins > 0;
-    if (n_samples == 0 && !any_snaps) return PS_OK;
+    r->any_snaps = want_snaps && prog.n_snapshots > 0 && obj->n_spins > 0;
     if (n_samples > 0 && !signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
+    r->obj = *obj;
+    r->rx = rx ? *rx : ps_receive{0, 0, nullptr, nullptr};
+    r->signal = signal;
+    r->n_samples = n_samples;
+    r->snaps = r->any_snaps ? snaps : nullptr;
+    int64_t max_slice = 0;
+    for (const Slice& sl : prog.slices) max_slice = std::max(max_slice, sl.n_samples);
+    r->coil_stride = 2 * max_slice;      // one block of samples per coil in every row
+    r->row_stride = r->coil_stride * r->n_out;
+    const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
+    r->partial_bytes = (size_t)(r->n_rows * r->row_stride * real_bytes);
+    r->fin_bytes = (size_t)finalize_scratch_doubles(r->n_rows, r->row_stride) * sizeof(double);
+    r->state_bytes = prog.slices.size() > 1 ? (size_t)(3 * obj->n_spins * real_bytes) : 0;
+    return PS_OK;
+}
+
+bool Single::empty() const { return obj.n_spins == 0 || (n_samples == 0 && !any_snaps); }
+
+ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b, hipStream_t stream,
+                         Ctx* timing_ctx) {
     hipError_t e;
-    if (obj->n_spins == 0) {
-        if (n_samples > 0 && (e = launch_fill_zero(signal, 2 * n_samples * n_out, stream)) != hipSuccess)
+    if (r.obj.n_spins == 0) {
+        if (r.n_samples > 0 && (e = launch_fill_zero(r.signal, 2 * r.n_samples * r.n_out, stream)) != hipSuccess)
             return hip_fail(e, "fill");
         return PS_OK;
     }
-    if ((st = wait_previous(ctx)) != PS_OK) return st;
-
-    const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
-    int64_t max_slice = 0;
-    for (const Slice& s : prog.slices) max_slice = std::max(max_slice, s.n_samples);
-    const int64_t coil_stride = 2 * max_slice;      // one block of samples per coil in every row
-    const int64_t row_stride = coil_stride * n_out;
-    if ((st = ctx->partial.reserve((size_t)(n_rows * row_stride * real_bytes))) != PS_OK) return st;
-    const int64_t fin_doubles = finalize_scratch_doubles(n_rows, row_stride);
-    if (fin_doubles > 0 && (st = ctx->fin_scratch.reserve((size_t)fin_doubles * sizeof(double))) != PS_OK)
-        return st;
-    const bool sliced = prog.slices.size() > 1;
-    if (sliced && (st = ctx->state.reserve((size_t)(3 * obj->n_spins * real_bytes))) != PS_OK) return st;
-    if ((st = upload(ctx, prog, stream)) != PS_OK) return st;
-
+    if (r.n_samples == 0 && !r.any_snaps) return PS_OK;
+    const int precision = ctx->cfg.precision;
+    const int64_t real_bytes = precision == 64 ? 8 : 4;
+    const Program& prog = r.prog;
     StepArgs a;
-    a.x = obj->x; a.y = obj->y; a.z = obj->z; a.m0 = obj->m0; a.t1 = obj->t1; a.t2 = obj->t2; a.dw = obj->dw;
-    a.n_spins = obj->n_spins;
+    a.x = r.obj.x; a.y = r.obj.y; a.z = r.obj.z; a.m0 = r.obj.m0; a.t1 = r.obj.t1; a.t2 = r.obj.t2;
+    a.dw = r.obj.dw;
+    a.n_spins = r.obj.n_spins;
     a.n_shape_rows = (int32_t)(prog.rows.size() / 9);
-    a.rows = ctx->rows.ptr;
-    a.partial = ctx->partial.ptr;
-    a.row_stride = row_stride;
-    a.state = ctx->state.ptr;
-    a.n_coils = n_coils;
-    a.s_x = rx ? rx->s_x : nullptr;
-    a.s_y = rx ? rx->s_y : nullptr;
-    a.coil_stride = coil_stride;
-    a.snaps = any_snaps ? snaps : nullptr;
-    const Op* ops_dev = reinterpret_cast<const Op*>(ctx->ops.ptr);
-    const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
+    a.rows = b.rows;
+    a.partial = b.partial;
+    a.row_stride = r.row_stride;
+    a.state = b.state;
+    a.n_coils = r.n_coils;
+    a.s_x = r.n_coils ? r.rx.s_x : nullptr;
+    a.s_y = r.n_coils ? r.rx.s_y : nullptr;
+    a.coil_stride = r.coil_stride;
+    a.snaps = r.snaps;
+    const Op* ops_dev = reinterpret_cast<const Op*>(b.ops);
     for (size_t i = 0; i < prog.slices.size(); ++i) {
         const Slice& sl = prog.slices[i];
         a.ops = ops_dev + sl.op_begin;
@@ -240,28 +248,48 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
         a.save_state = i + 1 < prog.slices.size();
         a.n_cache_slots = sl.n_cache_slots;
         hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
-        if (timing) {
-            t0 = timing_event(ctx); t1 = timing_event(ctx); t2 = timing_event(ctx);
+        if (timing_ctx) {
+            t0 = timing_event(timing_ctx); t1 = timing_event(timing_ctx); t2 = timing_event(timing_ctx);
             if (!t0 || !t1 || !t2) return fail(PS_E_DEVICE, "timing event creation failed");
             hipEventRecord(t0, stream);
         }
-        if ((e = launch_step(a, ctx->cfg.precision, S, n_blocks, stream)) != hipSuccess)
+        if ((e = launch_step(a, precision, r.S, r.n_blocks, stream)) != hipSuccess)
             return hip_fail(e, "step kernel launch");
-        if (timing) hipEventRecord(t1, stream);
-        for (int c = 0; c < n_out && sl.n_samples > 0; ++c) {
-            const unsigned char* part = reinterpret_cast<const unsigned char*>(ctx->partial.ptr) +
-                                        (size_t)(c * coil_stride * real_bytes);
-            if ((e = launch_finalize(part, ctx->cfg.precision, n_rows, row_stride, 2 * sl.n_samples,
-                                     signal + 2 * n_samples * c + 2 * sl.sample_begin,
-                                     reinterpret_cast<double*>(ctx->fin_scratch.ptr), stream)) != hipSuccess)
+        if (timing_ctx) hipEventRecord(t1, stream);
+        for (int c = 0; c < r.n_out && sl.n_samples > 0; ++c) {
+            const unsigned char* part = reinterpret_cast<const unsigned char*>(b.partial) +
+                                        (size_t)(c * r.coil_stride * real_bytes);
+            if ((e = launch_finalize(part, precision, r.n_rows, r.row_stride, 2 * sl.n_samples,
+                                     r.signal + 2 * r.n_samples * c + 2 * sl.sample_begin, b.fin_scratch,
+                                     stream)) != hipSuccess)
                 return hip_fail(e, "finalize kernel launch");
         }
-        if (timing) {
+        if (timing_ctx) {
             hipEventRecord(t2, stream);
-            ctx->step_marks.emplace_back(t0, t1);
-            ctx->fin_marks.emplace_back(t1, t2);
+            timing_ctx->step_marks.emplace_back(t0, t1);
+            timing_ctx->fin_marks.emplace_back(t1, t2);
         }
     }
+    return PS_OK;
+}
+
+ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
+                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
+                      void* snaps, int64_t n_snapshots) {
+    Single r;
+    ps_status st = plan_single(ctx, obj, seq, rx, signal, n_samples, snaps, n_snapshots, S_override, &r);
+    if (st != PS_OK) return st;
+    if (r.empty()) return enqueue_single(ctx, r, SingleBuffers{}, stream, nullptr);
+    if ((st = wait_previous(ctx)) != PS_OK) return st;
+    if ((st = ctx->partial.reserve(r.partial_bytes)) != PS_OK) return st;
+    if (r.fin_bytes > 0 && (st = ctx->fin_scratch.reserve(r.fin_bytes)) != PS_OK) return st;
+    if (r.state_bytes > 0 && (st = ctx->state.reserve(r.state_bytes)) != PS_OK) return st;
+    if ((st = upload(ctx, r.prog, stream)) != PS_OK) return st;
+    SingleBuffers b{ctx->ops.ptr, ctx->rows.ptr, ctx->partial.ptr, ctx->state.ptr,
+                    reinterpret_cast<double*>(ctx->fin_scratch.ptr)};
+    const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
+    if ((st = enqueue_single(ctx, r, b, stream, timing ? ctx : nullptr)) != PS_OK) return st;
+    hipError_t e;
     if ((e = hipEventRecord(ctx->done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     ctx->pending = true;
     return PS_OK;

@@ -64,6 +64,36 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S,
 int shape_cache_slots(const Ctx* ctx, int S, const Program& prog);
 ps_status wait_previous(Ctx* ctx);
 ps_status validate_receive(const ps_receive* rx, const ps_object* obj);
+
+// One request compiled for a context: program, tiling and buffer sizes.
+struct Single {
+    Program prog;
+    int S = 1, n_coils = 0, n_out = 1;
+    int64_t n_blocks = 0, n_rows = 0, coil_stride = 0, row_stride = 0;
+    bool any_snaps = false;
+    ps_object obj{};
+    ps_receive rx{};
+    double* signal = nullptr;
+    int64_t n_samples = 0;
+    void* snaps = nullptr;
+    size_t partial_bytes = 0, fin_bytes = 0, state_bytes = 0;
+    bool empty() const;            // nothing for the step kernel to do
+};
+// Device tables and work buffers one request's launches use.
+struct SingleBuffers {
+    const void* ops = nullptr;
+    const void* rows = nullptr;
+    void* partial = nullptr;
+    void* state = nullptr;
+    double* fin_scratch = nullptr;
+};
+ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
+                      double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
+                      Single* r);
+// Stream-ordered launches of a planned request (tables already resident in
+// b); kernel timing events go to timing_ctx when it is not NULL.
+ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b, hipStream_t stream,
+                         Ctx* timing_ctx);
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
                       int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
                       void* snaps = nullptr, int64_t n_snapshots = -1);
