@@ -59,13 +59,19 @@ typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
  * give the same signal within FP32 rounding; this flag exists to measure and
  * test the sub-step path on sequences with repeated shapes. */
 #define PS_CFG_NO_SHAPE_CACHE 2u
+/* ps_config.flags: never split readouts across workgroups.  By default an
+ * object too small to fill the device runs each workgroup tile as several
+ * replicas that repeat the tile's RF and shaped-pulse stepping and share its
+ * readouts (a readout changes no spin state); every sample is still computed
+ * once, by the same arithmetic, so the signal is bitwise the same. */
+#define PS_CFG_NO_READOUT_SPLIT 4u
 
 typedef struct ps_config {
     int32_t device;              /* HIP device ordinal                                 */
     int32_t precision;           /* 32: FP32 stepping (FP64 phases and cross-block
                                     sums); 64: FP64 throughout                         */
     int32_t spins_per_lane;      /* 0 = autotuned; else 1, 2, 4 or 8 (FP64: 1 or 2)    */
-    int32_t flags;               /* PS_CFG_KERNEL_TIMING | PS_CFG_NO_SHAPE_CACHE       */
+    int32_t flags;               /* PS_CFG_* bits                                      */
     int64_t max_partial_bytes;   /* bound on the per-block partial-sum buffer; longer
                                     sequences run in time slices (0 = default 2 GiB)   */
     int64_t max_footprint_bytes; /* admission cap for served requests (0 = 64 GiB)     */

@@ -117,14 +117,15 @@ class Context:
 
     def __init__(self, device: int = 0, precision: int = 32, spins_per_lane: int = 0,
                  max_partial_bytes: int = 0, max_footprint_bytes: int = 0, kernel_timing: bool = False,
-                 shape_cache: bool = True):
+                 shape_cache: bool = True, readout_split: bool = True):
         cfg = _b.ps_config()
         _b.check(_b.lib.ps_config_default(ctypes.byref(cfg)))
         cfg.device = device
         cfg.precision = precision
         cfg.spins_per_lane = spins_per_lane
         cfg.flags = (_b.PS_CFG_KERNEL_TIMING if kernel_timing else 0) | \
-            (0 if shape_cache else _b.PS_CFG_NO_SHAPE_CACHE)
+            (0 if shape_cache else _b.PS_CFG_NO_SHAPE_CACHE) | \
+            (0 if readout_split else _b.PS_CFG_NO_READOUT_SPLIT)
         if max_partial_bytes:
             cfg.max_partial_bytes = max_partial_bytes
         if max_footprint_bytes:

@@ -19,6 +19,7 @@ PS_EV_SPOIL = 1
 PS_EV_SNAPSHOT = 2
 PS_CFG_KERNEL_TIMING = 1
 PS_CFG_NO_SHAPE_CACHE = 2
+PS_CFG_NO_READOUT_SPLIT = 4
 
 
 class PsError(RuntimeError):

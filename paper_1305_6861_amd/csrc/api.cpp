@@ -168,6 +168,31 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj) {
     return PS_OK;
 }
 
+// Readout replicas for an object too small to fill the device: enough to
+// give about two workgroups per CU, at most one per readout of the busiest
+// slice, and few enough that the repeated RF / shaped-pulse work of the
+// replicas stays below the readout work they share (per-spin estimates in
+// VALU instructions: ~6 per sample and coil, ~80 per hard pulse or snapshot,
+// ~30 per shaped-pulse sub-step).
+static int choose_replicas(const Ctx* ctx, const Single& r) {
+    if (ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) return 1;
+    const int64_t want = 2 * (int64_t)std::max(ctx->n_cu, 1);
+    if (r.n_blocks <= 0 || r.n_blocks * 2 > want) return 1;
+    const Program& p = r.prog;
+    int64_t max_adc = 0;
+    for (const Slice& sl : p.slices) {
+        int64_t c = 0;
+        for (int64_t i = sl.op_begin; i < sl.op_end; ++i) c += p.ops[i].kind == OP_ADC;
+        max_adc = std::max(max_adc, c);
+    }
+    int64_t R = (want + r.n_blocks - 1) / r.n_blocks;
+    R = std::min<int64_t>(R, std::min<int64_t>(max_adc, 64));
+    const double readout = 6.0 * (double)p.n_samples * r.n_out;
+    const double other = 80.0 * (double)(p.n_rf + p.n_snapshots) + 30.0 * (double)p.n_shape_substeps;
+    if (other > 0) R = std::min<int64_t>(R, std::max<int64_t>(1, (int64_t)(readout / other)));
+    return (int)std::max<int64_t>(R, 1);
+}
+
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
                       double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
                       Single* r) {
@@ -208,6 +233,7 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->partial_bytes = (size_t)(r->n_rows * r->row_stride * real_bytes);
     r->fin_bytes = (size_t)finalize_scratch_doubles(r->n_rows, r->row_stride) * sizeof(double);
     r->state_bytes = prog.slices.size() > 1 ? (size_t)(3 * obj->n_spins * real_bytes) : 0;
+    r->n_replicas = choose_replicas(ctx, *r);
     return PS_OK;
 }
 
@@ -239,6 +265,8 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
     a.s_y = r.n_coils ? r.rx.s_y : nullptr;
     a.coil_stride = r.coil_stride;
     a.snaps = r.snaps;
+    a.n_replicas = r.n_replicas;
+    a.n_tiles = r.n_blocks;
     const Op* ops_dev = reinterpret_cast<const Op*>(b.ops);
     for (size_t i = 0; i < prog.slices.size(); ++i) {
         const Slice& sl = prog.slices[i];

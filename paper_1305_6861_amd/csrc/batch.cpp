@@ -125,6 +125,8 @@ StepArgs ReqPlan::args_for_slice(size_t k) const {
     a.s_y = nullptr;
     a.coil_stride = row_stride;
     a.snaps = nullptr;
+    a.n_replicas = 1;
+    a.n_tiles = n_blocks;
     return a;
 }
 

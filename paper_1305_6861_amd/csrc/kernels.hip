@@ -339,7 +339,7 @@ __device__ __forceinline__ void shape_apply(const real* cache, bool turn, real c
 // One workgroup tile of one request: spins [blk * 256 S, (blk + 1) * 256 S)
 // through the slice's operations, partial sums into the tile's rows.
 template <typename real, int S>
-__device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) {
+__device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, const int rep) {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int R = G * S;                 // spins per lane inside readouts
     __shared__ Op s_ops[kOpChunk];
@@ -389,6 +389,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
 
     const int wg = wave % G;                 // position inside the wave group
     double step_mu[3] = {0.0, 0.0, 0.0}, step_tau = 0.0;
+    int adc_seen = 0;                        // readouts met so far (replica split)
     bool step_valid = false;
     real* partial = reinterpret_cast<real*>(a.partial) +
                     (blk * (kWaves / G) + wave / G) * a.row_stride;
@@ -419,7 +420,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                 for (int s = 0; s < S; ++s) { sp.ar[s] = 0; sp.ai[s] = 0; }
             } else if (kind == OP_SNAP) {
                 // magnetisation of every spin at this instant (section 7.2);
-                // the anchors are left as they are
+                // the anchors are left as they are; replica 0 stores it
+                if (rep != 0) continue;
                 real mx[S], my[S], mz[S];
                 evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
                 real* out = reinterpret_cast<real*>(a.snaps) +
@@ -495,6 +497,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
                     sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s];
                 }
             } else if (kind == OP_ADC) {
+                // A readout changes no spin state, so replicas of this tile
+                // share the slice's readouts round-robin and skip the others.
+                if (a.n_replicas > 1 && (adc_seen++ % a.n_replicas) != rep) continue;
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
                 const double tau = op.u.adc.tau;
@@ -640,7 +645,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
         }
     }
 
-    if (a.save_state) {
+    if (a.save_state && rep == 0) {
         real* st = reinterpret_cast<real*>(a.state);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -652,9 +657,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk) 
     }
 }
 
+// Workgroup b runs tile b % n_tiles as readout replica b / n_tiles.
 template <typename real, int S>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
-    step_body<real, S>(a, (int64_t)blockIdx.x);
+    const int64_t b = blockIdx.x;
+    step_body<real, S>(a, b % a.n_tiles, (int)(b / a.n_tiles));
 }
 
 // Persistent form: workgroups take (request, tile) items from a queue until
@@ -677,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchItem* __r
             if (reqs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
         }
         const StepArgs a = reqs[lo].args;
-        step_body<real, S>(a, item - reqs[lo].item_begin);
+        step_body<real, S>(a, item - reqs[lo].item_begin, 0);
     }
 }
 
@@ -792,7 +799,10 @@ int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape
 template <typename real, int S>
 static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t st) {
     const size_t dyn = dyn_lds_t<real, S>(a.n_shape_rows, a.n_cache_slots);
-    hipLaunchKernelGGL((step_kernel<real, S>), dim3((unsigned)n_blocks), dim3(kBlock), dyn, st, a);
+    StepArgs b = a;
+    b.n_tiles = n_blocks;
+    if (b.n_replicas < 1) b.n_replicas = 1;
+    hipLaunchKernelGGL((step_kernel<real, S>), dim3((unsigned)(n_blocks * b.n_replicas)), dim3(kBlock), dyn, st, b);
     return hipGetLastError();
 }
 

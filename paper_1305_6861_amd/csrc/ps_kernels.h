@@ -24,6 +24,8 @@ struct StepArgs {
     const float *s_x, *s_y;  // device, n_coils * n_spins transverse sensitivities
     int64_t coil_stride;     // reals between coils' sample blocks inside a row
     void* snaps;             // device, n_snapshots * 3 * n_spins reals (OP_SNAP targets)
+    int32_t n_replicas;      // readout replicas per tile (>= 1; launch_step only)
+    int64_t n_tiles;         // workgroup tiles of the object (set by launch_step)
 };
 
 // One request of a persistent batched launch: its arguments and the number
@@ -50,6 +52,8 @@ int64_t spins_per_block_of(int spins_per_lane);
 // Partial-sum rows one workgroup writes (one per wave group).
 int64_t rows_per_block_of(int spins_per_lane);
 
+// Launches n_blocks * a.n_replicas workgroups: every tile of the object
+// once per readout replica (replicas split the slice's readouts).
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
                        hipStream_t st);
 // Dynamic LDS of a step workgroup: shaped-pulse rows and propagator slots.

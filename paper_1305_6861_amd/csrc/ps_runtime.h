@@ -69,6 +69,7 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj);
 struct Single {
     Program prog;
     int S = 1, n_coils = 0, n_out = 1;
+    int n_replicas = 1;            // readout replicas per tile
     int64_t n_blocks = 0, n_rows = 0, coil_stride = 0, row_stride = 0;
     bool any_snaps = false;
     ps_object obj{};
