@@ -70,11 +70,6 @@ def bench_c4(args):
            "one_per_launch_ms": res["one_per_launch"] * 1e3,
            "speedup_vs_one_per_launch": res["one_per_launch"] / res["batched"],
            "roofline": None, "cpu_baseline": None}
-    if args.workload in PAPER_T78_SECONDS:
-        t_paper = PAPER_T78_SECONDS[args.workload]
-        rec["paper_context"] = {"t_sim_s": t_paper, "source": "Table 7.8, PARSPIN 1.5.0",
-                                "hardware": "PVM cluster of 5 Sun Ultra-1 170",
-                                "speedup_of_this_run": t_paper / (ms_per_step * 1e-3)}
     if not args.no_cpu_baseline:
         import oracle
         got = [t.cpu().numpy() for t in batched()]

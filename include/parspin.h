@@ -225,7 +225,9 @@ ps_status ps_simulate_batch(ps_ctx *ctx, int32_t n_requests, const ps_object *ob
 /* ---- served execution ------------------------------------------------
  * A scheduler thread (started by the first ps_submit on a context) admits
  * queued requests in submission order while the sum of their device
- * footprints stays under ps_config.max_footprint_bytes, and advances every
+ * footprints stays under ps_config.max_footprint_bytes (a request of at least
+ * 2.5e10 spin-steps waits while another such request runs, letting smaller
+ * ones behind it through), and advances every
  * admitted request by one time slice per iteration in one batched round, so
  * requests that arrive while others run join at the next iteration
  * (continuous batching; after the master / compute-node / superposition

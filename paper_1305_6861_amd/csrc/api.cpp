@@ -168,29 +168,32 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj) {
     return PS_OK;
 }
 
-// Readout replicas for an object too small to fill the device: enough to
-// give about two workgroups per CU, at most one per readout of the busiest
-// slice, and few enough that the repeated RF / shaped-pulse work of the
-// replicas stays below the readout work they share (per-spin estimates in
-// VALU instructions: ~6 per sample and coil, ~80 per hard pulse or snapshot,
-// ~30 per shaped-pulse sub-step).
-static int choose_replicas(const Ctx* ctx, const Single& r) {
-    if (ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) return 1;
-    const int64_t want = 2 * (int64_t)std::max(ctx->n_cu, 1);
-    if (r.n_blocks <= 0 || r.n_blocks * 2 > want) return 1;
-    const Program& p = r.prog;
+// Largest useful number of readout replicas of one tile of a program: at
+// most one per readout of its busiest slice, and few enough that the
+// repeated RF / shaped-pulse work of the replicas stays below the readout
+// work they share (per-spin estimates in VALU instructions: ~6 per sample
+// and coil, ~80 per hard pulse or snapshot, ~30 per shaped-pulse sub-step).
+int replica_bound(const Program& p, int n_out) {
     int64_t max_adc = 0;
     for (const Slice& sl : p.slices) {
         int64_t c = 0;
         for (int64_t i = sl.op_begin; i < sl.op_end; ++i) c += p.ops[i].kind == OP_ADC;
         max_adc = std::max(max_adc, c);
     }
-    int64_t R = (want + r.n_blocks - 1) / r.n_blocks;
-    R = std::min<int64_t>(R, std::min<int64_t>(max_adc, 64));
-    const double readout = 6.0 * (double)p.n_samples * r.n_out;
+    int64_t R = std::min<int64_t>(max_adc, 64);
+    const double readout = 6.0 * (double)p.n_samples * std::max(n_out, 1);
     const double other = 80.0 * (double)(p.n_rf + p.n_snapshots) + 30.0 * (double)p.n_shape_substeps;
     if (other > 0) R = std::min<int64_t>(R, std::max<int64_t>(1, (int64_t)(readout / other)));
     return (int)std::max<int64_t>(R, 1);
+}
+
+// Readout replicas for a launch of n_tiles workgroup tiles: none when the
+// tiles alone give every CU a workgroup, else enough for about two per CU.
+int replicas_for_load(const Ctx* ctx, int64_t n_tiles, int bound) {
+    if (ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) return 1;
+    const int64_t want = 2 * (int64_t)std::max(ctx->n_cu, 1);
+    if (n_tiles <= 0 || n_tiles * 2 > want) return 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((want + n_tiles - 1) / n_tiles, bound));
 }
 
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
@@ -233,7 +236,7 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->partial_bytes = (size_t)(r->n_rows * r->row_stride * real_bytes);
     r->fin_bytes = (size_t)finalize_scratch_doubles(r->n_rows, r->row_stride) * sizeof(double);
     r->state_bytes = prog.slices.size() > 1 ? (size_t)(3 * obj->n_spins * real_bytes) : 0;
-    r->n_replicas = choose_replicas(ctx, *r);
+    r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out));
     return PS_OK;
 }
 

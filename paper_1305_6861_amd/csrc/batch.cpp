@@ -73,6 +73,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
         g.slices = std::move(out);
         assign_shape_slots(&g, shape_cache_slots(ctx, p->S, g));
     }
+    p->max_replicas = replica_bound(p->prog, 1);
     if (n_samples != p->prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
                                           std::to_string(p->prog.n_samples));
@@ -105,7 +106,7 @@ void ReqPlan::bind(unsigned char* base) {
     d_rows = reinterpret_cast<double*>(q); q += bytes_rows;
 }
 
-StepArgs ReqPlan::args_for_slice(size_t k) const {
+StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     const Slice& sl = prog.slices[k];
     StepArgs a;
     a.x = obj.x; a.y = obj.y; a.z = obj.z; a.m0 = obj.m0; a.t1 = obj.t1; a.t2 = obj.t2; a.dw = obj.dw;
@@ -125,7 +126,7 @@ StepArgs ReqPlan::args_for_slice(size_t k) const {
     a.s_y = nullptr;
     a.coil_stride = row_stride;
     a.snaps = nullptr;
-    a.n_replicas = 1;
+    a.n_replicas = std::max(n_replicas, 1);
     a.n_tiles = n_blocks;
     return a;
 }
@@ -175,14 +176,18 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
             c.counter_off = reserve_bytes(sizeof(unsigned long long));
             int64_t total = 0;
             size_t dyn = 0;
+            // readout replicas when the round's tiles of this class leave CUs idle
+            int64_t tiles = 0;
+            for (size_t q = 0; q < kv.second.size(); ++q) tiles += plans[kv.second[q]]->n_blocks;
             for (size_t q = 0; q < kv.second.size(); ++q) {
                 ReqPlan* p = plans[kv.second[q]];
+                const int R = replicas_for_load(ctx, tiles, p->max_replicas);
                 BatchItem it;
                 std::memset(&it, 0, sizeof(it));
-                it.args = p->args_for_slice(first_slice[kv.second[q]] + k);
+                it.args = p->args_for_slice(first_slice[kv.second[q]] + k, R);
                 it.item_begin = total;
-                it.n_items = p->n_blocks;
-                total += p->n_blocks;
+                it.n_items = p->n_blocks * R;
+                total += it.n_items;
                 dyn = std::max(dyn, step_dyn_lds_bytes(ctx->cfg.precision, c.S, it.args.n_shape_rows,
                                                        it.args.n_cache_slots));
                 std::memcpy(img.data() + c.items_off + q * sizeof(BatchItem), &it, sizeof(it));

@@ -17,6 +17,7 @@ struct ReqPlan {
     double* signal = nullptr;
     Program prog;
     int S = 1;
+    int max_replicas = 1;              // readout replicas one tile can use
     int64_t n_blocks = 0, n_rows = 0, row_stride = 0, n_groups = 0;
     size_t bytes_partial = 0, bytes_state = 0, bytes_mid = 0, bytes_ops = 0, bytes_rows = 0;
     // device placement (bind)
@@ -29,7 +30,7 @@ struct ReqPlan {
     size_t device_bytes() const;       // library buffers of this request
     size_t footprint() const;          // + object arrays + output (admission)
     void bind(unsigned char* base);    // place the buffers at base (256-aligned)
-    StepArgs args_for_slice(size_t k) const;
+    StepArgs args_for_slice(size_t k, int n_replicas = 1) const;
 };
 
 // Validate, compile and slice one request (max_slice_steps > 0 additionally

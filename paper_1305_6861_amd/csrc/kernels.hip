@@ -664,10 +664,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     step_body<real, S>(a, b % a.n_tiles, (int)(b / a.n_tiles));
 }
 
-// Persistent form: workgroups take (request, tile) items from a queue until
-// it is empty.  Items are numbered request by request (BatchItem.item_begin
-// is the prefix sum of the requests' tile counts).  Every item writes only
-// its own rows, so which workgroup runs it never changes a result.
+// Persistent form: workgroups take (request, tile, readout replica) items
+// from a queue until it is empty.  Items are numbered request by request
+// (BatchItem.item_begin is the prefix sum of the requests' item counts, a
+// request's items being its tiles times its replicas, replica-major).  Every
+// item writes only its own rows and samples, so which workgroup runs it
+// never changes a result.
 template <typename real, int S>
 __global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req,
                                                             int64_t total, unsigned long long* counter) {
@@ -684,7 +686,8 @@ __global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchItem* __r
             if (reqs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
         }
         const StepArgs a = reqs[lo].args;
-        step_body<real, S>(a, item - reqs[lo].item_begin, 0);
+        const int64_t local = item - reqs[lo].item_begin;   // replica-major over the tiles
+        step_body<real, S>(a, local % a.n_tiles, (int)(local / a.n_tiles));
     }
 }
 

@@ -47,9 +47,16 @@ struct Request {
     void* mem = nullptr;
     size_t mem_bytes = 0;
     size_t footprint = 0;
+    bool large = false;                // see kLargeWork
     double t_submit = 0, t_admit = -1, t_done = -1;
     std::string error;
 };
+
+// Requests of at least this many spin-steps (a few ms of the whole device)
+// run one at a time: sharing the device among several of them only delays
+// them all, while small requests keep joining every iteration beside the
+// one that runs.
+constexpr double kLargeWork = 2.5e10;
 
 // Device memory for admitted requests: freed blocks are kept and reused.
 struct Pool {
@@ -92,7 +99,7 @@ struct Server {
     DevBuf records;
     HostBuf staging_rec, staging_tab;
     Pool pool;
-    int64_t max_slice_steps = 16384;
+    int64_t max_slice_steps = 65536;
     // counters
     uint64_t iterations = 0;
 
@@ -130,18 +137,24 @@ void Server::loop() {
                     ++it;
                 }
             }
-            // FIFO admission while the footprint fits
-            while (!queue.empty()) {
-                auto& r = queue.front();
+            // admission in submission order while the footprint fits; a large
+            // request waits (without holding up the small ones behind it)
+            // while another large one runs
+            bool large_active = false;
+            for (auto& r : active) large_active = large_active || r->large;
+            for (auto it = queue.begin(); it != queue.end();) {
+                auto& r = *it;
                 if (r->cancel) {
                     finish(r, RQ_CANCELLED, PS_E_CANCELLED, "cancelled");
-                    queue.pop_front();
+                    it = queue.erase(it);
                     continue;
                 }
+                if (r->large && large_active) { ++it; continue; }
                 if (used + r->footprint > (size_t)ctx->cfg.max_footprint_bytes) break;
                 used += r->footprint;
+                large_active = large_active || r->large;
                 admitted.push_back(r);
-                queue.pop_front();
+                it = queue.erase(it);
             }
             changed.notify_all();
         }
@@ -293,6 +306,7 @@ ps_status ps_submit(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq
         if ((st = plan_request(ctx, obj, seq, n_samples, signal, steps, &r->plan)) != PS_OK) return st;
     }
     r->footprint = r->plan.footprint();
+    r->large = (double)r->plan.obj.n_spins * (double)r->plan.prog.n_steps >= kLargeWork;
     if (r->footprint > (size_t)ctx->cfg.max_footprint_bytes)
         return fail(PS_E_TOO_LARGE, "request footprint " + std::to_string(r->footprint) +
                                         " bytes exceeds the cap of " + std::to_string(ctx->cfg.max_footprint_bytes));

@@ -26,7 +26,7 @@ def _np(t):
 
 def _small_3d():
     obj = grid3d_two_species(24, seed=77)                    # 27,648 spins
-    seq = C.gre_3d_sinc(24, 24, 8)                            # 192 TRs: several time slices
+    seq = C.gre_3d_sinc(24, 24, 24)                           # 576 TRs: several time slices
     return obj, seq
 
 
@@ -129,3 +129,39 @@ def test_served_edge_requests(ps):
             t0.info()
     assert z.shape == (12,) and np.all(z == 0)
     assert e.shape == (0,)
+
+
+def test_c5_stream_sample_against_the_oracle(ps):
+    """The served configuration's own requests: the first 200 2-D requests
+    of the c5 arrival schedule (every 16th spin) and its first 20 3-D
+    2 x 64^3 sinc-GRE jobs (every 256th spin, full sequences), submitted
+    together and served with continuous batching; each result within the
+    FP32 bar of the oracle, a few also bitwise equal to the request alone."""
+    from workloads.phantom import subset
+    sched = C.c5_stream(n_requests=2000)
+    two_d = [(k, p) for _, k, p in sched if k == "c4"][:200]
+    three_d = [(k, p) for _, k, p in sched if k == "3d"][:20]
+    reqs = []
+    for k, p in two_d:
+        o, s = C.c5_request(k, p)
+        reqs.append((subset(o, 16, p % 16), s))
+    for k, p in three_d:
+        o, s = C.c5_request(k, p)
+        reqs.append((subset(o, 256, p % 256), s))
+    with ps.Context() as ctx:
+        tickets = [ctx.submit(o, s) for o, s in reqs]
+        outs = [_np(t.wait(120.0)) for t in tickets]
+        stats = ctx.server_stats()
+        alone = {i: _np(ctx.submit(*reqs[i]).wait(120.0)) for i in (0, 57, 199, 200, 219)}
+    for i, a in alone.items():
+        np.testing.assert_array_equal(outs[i], a)
+    worst2, worst3 = 0.0, 0.0
+    for i, ((o, s), got) in enumerate(zip(reqs, outs)):
+        err = oracle.rel_l2(got, oracle.simulate(o, s))
+        if i < 200:
+            worst2 = max(worst2, err)
+        else:
+            worst3 = max(worst3, err)
+    print(f"[serve] c5 sample: 200 2-D worst rel_l2 {worst2:.3e}, 20 3-D worst {worst3:.3e}, "
+          f"iterations {stats['iterations']}", flush=True)
+    assert worst2 <= TOL32 and worst3 <= TOL32
