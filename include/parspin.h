@@ -193,6 +193,26 @@ ps_status ps_simulate_ex(ps_ctx *ctx, const ps_object *obj, const ps_sequence *s
                          double *signal, int64_t n_samples, void *snapshots, int64_t n_snapshots,
                          void *stream);
 
+/* Spin spacing a sequence needs (section 5.2), from the K-t formalism
+ * (section 4.2; host computation, no device).  Every gradient moment of seq
+ * (per ADC sample inside readouts, per sub-step inside shapes) must be an
+ * integer multiple of dk[d] cycles/m on each axis d (dk[d] = 0: no moment on
+ * that axis).  The configuration populations of one reference tissue
+ * (t1, t2 in s, > 0, +inf allowed) are tracked through the sequence; then
+ *   grey_step == 0: k_max[d] = the largest |k_d| of any configuration with a
+ *                   population above 1e-12 M0 at any instant (eq. 5.1);
+ *   grey_step > 0:  at every ADC sample the outer transverse configurations
+ *                   whose populations add up to at most grey_step / 2 of the
+ *                   largest one are left out (eq. 5.4 / 5.5, grey_step being
+ *                   the grey-value step, e.g. 1/256);
+ * k_max in cycles/m, and dx_max[d] = 1 / (2 k_max[d]) m, the largest spin
+ * spacing free of aliasing (eq. 5.2 with k in cycles/m; +inf where k_max is
+ * 0).  *n_configs_peak (may be NULL): the most transverse configurations
+ * populated at once.  PS_E_INVALID_ARG for a moment off the lattice or an
+ * invalid sequence, PS_E_TOO_LARGE past 2^22 configurations. */
+ps_status ps_kt_extent(const ps_sequence *seq, const double dk[3], double t1, double t2, double grey_step,
+                       double k_max[3], double dx_max[3], int64_t *n_configs_peak);
+
 /* Compiled plans: one request compiled once and its kernel launches captured
  * in a HIP graph, for callers that simulate the same (object layout,
  * sequence, coils) many times, e.g. parameter sweeps that rewrite the object

@@ -28,8 +28,8 @@ from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT
 
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
-__all__ = ["Context", "Plan", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence", "to_device",
-           "FIELDS"]
+__all__ = ["Context", "Plan", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence",
+           "to_device", "kt_extent", "min_spins", "FIELDS"]
 
 
 class PackedSequence:
@@ -90,6 +90,31 @@ def pack_sequence(seq) -> PackedSequence:
 def count(seq):
     """(n_samples, n_steps_per_spin) of a sequence, validated by the library."""
     return pack_sequence(seq).count()
+
+
+def kt_extent(seq, dk, t1: float, t2: float, grey_step: float = 0.0) -> dict:
+    """Spin spacing the sequence needs (ps_kt_extent, section 5.2): k_max and
+    dx_max per axis (cycles/m, m) for lattice steps dk (cycles/m per axis)
+    and the reference tissue (t1, t2); grey_step > 0 leaves out outer
+    configurations too weak to show at that grey-value step (eq. 5.4 / 5.5)."""
+    ps = pack_sequence(seq)
+    dkv = (ctypes.c_double * 3)(*[float(v) for v in dk])
+    km = (ctypes.c_double * 3)()
+    dx = (ctypes.c_double * 3)()
+    peak = ctypes.c_int64()
+    _b.check(_b.lib.ps_kt_extent(ctypes.byref(ps.struct), dkv, float(t1), float(t2), float(grey_step), km, dx,
+                                 ctypes.byref(peak)))
+    return {"k_max": np.array(km[:]), "dx_max": np.array(dx[:]), "n_configs_peak": int(peak.value)}
+
+
+def min_spins(extent_m, dx_max) -> int:
+    """Spins needed to cover an object of the given extent (m per axis) at
+    the spacing dx_max per axis (eq. 5.2): prod ceil(extent / dx_max)."""
+    n = 1
+    for e, d in zip(extent_m, dx_max):
+        if e > 0 and np.isfinite(d):
+            n *= int(np.ceil(e / d))
+    return n
 
 
 def to_device(obj, device="cuda"):

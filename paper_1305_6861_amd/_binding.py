@@ -117,6 +117,9 @@ SIGNATURES = {
                                       ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "ps_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ps_kt_extent": (ctypes.c_int, [ctypes.POINTER(ps_sequence), ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "ps_plan_destroy": (None, [ctypes.c_void_p]),
     "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                       ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
