@@ -4,8 +4,9 @@ Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  It shares no code with the GPU library: the stepping is plain
 C (bloch_oracle.c) following section 5.1.1 with eq. 3.19 for hard pulses,
 eq. 3.5 / 3.12 / 3.14 for precession and relaxation, eq. 3.23 for shaped
-pulses, eq. 3.30 - 3.32 for the received signal and eq. 3.25 for receive
-coils with an inhomogeneous sensitivity.
+pulses, eq. 3.30 - 3.32 for the received signal, eq. 3.25 for receive
+coils with an inhomogeneous sensitivity, and per-sample trajectory tables
+(samples at listed instants and moments inside an interval).
 
 Inputs are duck-typed: a spin object exposes float32 arrays x, y, z, m0,
 t1, t2, dw (widened exactly to float64 here), a sequence exposes the
@@ -50,6 +51,14 @@ def _configure(lib):
         [ctypes.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _u32p] +
         [ctypes.c_int32, _i64p, _dp, _dp, _i64p, _dp, _dp] +
         [ctypes.c_int32, _dp, _dp, _dp] +
+        [ctypes.c_int, ctypes.c_int64, _dp, _dp])
+    lib.oracle_simulate_traj.restype = ctypes.c_int
+    lib.oracle_simulate_traj.argtypes = (
+        [ctypes.c_int64] + [_dp] * 7 +
+        [ctypes.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _u32p] +
+        [ctypes.c_int32, _i64p, _dp, _dp, _i64p, _dp, _dp] +
+        [ctypes.c_int32, _dp, _dp, _dp] +
+        [_i32p, ctypes.c_int32, _i64p, _i64p, _dp, _dp] +
         [ctypes.c_int, ctypes.c_int64, _dp, _dp])
     lib.oracle_rf_pulse.restype = None
     lib.oracle_rf_pulse.argtypes = [_dp, ctypes.c_double, ctypes.c_double]
@@ -141,14 +150,24 @@ def simulate(obj, seq, n_threads: Optional[int] = None, final_m: bool = False, c
     fm = np.zeros(3 * n + 1, np.float64) if final_m else None
     n_snap = int(np.count_nonzero(fl & SNAPSHOT))
     snap = np.zeros(3 * n * n_snap + 1, np.float64) if snapshots else None
+    trajs = list(getattr(seq, "trajectories", []))
+    ev_tr = (np.ascontiguousarray(seq.trajectory, np.int32) if ne and hasattr(seq, "trajectory")
+             else np.full(max(ne, 1), -1, np.int32))
+    tr_n = np.array([t.n for t in trajs] or [0], np.int64)
+    tr_off = np.zeros(max(len(trajs), 1), np.int64)
+    if trajs:
+        tr_off[1:len(trajs)] = np.cumsum(tr_n[:len(trajs)])[:-1]
+    tr_k = np.concatenate([t.k.reshape(-1) for t in trajs] + [np.zeros(3)]).astype(np.float64)
+    tr_t = np.concatenate([t.t for t in trajs] + [np.zeros(1)]).astype(np.float64)
     nt = int(n_threads or default_threads())
-    rc = lib.oracle_simulate_full(
+    rc = lib.oracle_simulate_traj(
         n, *[_ptr(a, _dp) for a in sp],
         ne, _ptr(dt, _dp), _ptr(m, _dp), _ptr(al, _dp), _ptr(ph, _dp), _ptr(sh, _i32p),
         _ptr(na, _i64p), _ptr(fl, _u32p),
         ns, _ptr(sh_nsub, _i64p), _ptr(sh_tau, _dp), _ptr(sh_m, _dp), _ptr(offs, _i64p),
         _ptr(sh_alpha, _dp), _ptr(sh_phase, _dp),
         n_coils, _ptr(s_x, _dp), _ptr(s_y, _dp), _ptr(snap, _dp) if snap is not None else None,
+        _ptr(ev_tr, _i32p), len(trajs), _ptr(tr_n, _i64p), _ptr(tr_off, _i64p), _ptr(tr_k, _dp), _ptr(tr_t, _dp),
         nt, n_samples, _ptr(out, _dp), _ptr(fm, _dp) if fm is not None else None)
     if rc != 0:
         raise ValueError(f"oracle_simulate failed with code {rc}")

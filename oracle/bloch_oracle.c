@@ -28,6 +28,11 @@
  *    pulse, then its interval;
  *  - SPOIL sets Mx = My = 0 at the end of the interval (an idealised
  *    spoiler; the paper has no such primitive);
+ *  - an event with a trajectory takes its samples at the listed instants t_s
+ *    after the interval start, where the moment accumulated since the start
+ *    is k_s: the interval is cut at those instants (precession and relaxation
+ *    over each piece with its own moment), the magnetisation recorded at
+ *    each, and the last piece runs to dt with the remaining moment m - k_last;
  *  - SNAPSHOT records every spin's (Mx, My, Mz) at the end of the interval,
  *    after the spoiler if both are set (the magnetisation output of section
  *    7.2, the state the next elementary sequence starts from);
@@ -79,6 +84,12 @@ typedef struct {
     const double *s_x, *s_y;
     /* snapshots: [snapshot][component][spin], may be NULL */
     double *snap;
+    /* trajectories: event e uses trajectory ev_traj[e] (-1: equal sub-steps);
+     * trajectory j has tr_n[j] samples at rows tr_off[j] .. of tr_k (3 per
+     * row) and tr_t */
+    const int32_t *ev_traj;
+    const int64_t *tr_n, *tr_off;
+    const double *tr_k, *tr_t;
 } problem_t;
 
 typedef struct {
@@ -120,6 +131,22 @@ static void precess_relax(double M[3], double tau, const double mu[3],
     M[2] = e1 * M[2] + m0 * (1.0 - e1);
 }
 
+/* Add spin i's magnetisation M to sample `sample` of every coil's signal. */
+static void record(const problem_t *pb, int64_t i, double *signal, int64_t sample, const double M[3])
+{
+    if (pb->n_coils == 0) {
+        signal[2 * sample] += M[0];
+        signal[2 * sample + 1] += M[1];
+        return;
+    }
+    for (int32_t c = 0; c < pb->n_coils; ++c) {
+        double sx = pb->s_x[c * pb->n_spins + i], sy = pb->s_y[c * pb->n_spins + i];
+        double *sc = signal + 2 * pb->n_samples * c;
+        sc[2 * sample] += sx * M[0] + sy * M[1];
+        sc[2 * sample + 1] += sx * M[1] - sy * M[0];
+    }
+}
+
 static void run_spin(const problem_t *pb, int64_t i, double *signal, double *final_m)
 {
     double x = pb->x[i], y = pb->y[i], z = pb->z[i];
@@ -146,25 +173,33 @@ static void run_spin(const problem_t *pb, int64_t i, double *signal, double *fin
             rf_pulse(M, pb->ev_alpha[e], pb->ev_phase[e]);
 
         int64_t n_adc = pb->ev_nadc[e];
-        int64_t K = n_adc > 0 ? n_adc : 1;
-        double tau = pb->ev_dt[e] / (double)K;
-        double mu[3] = {pb->ev_m[3 * e] / (double)K, pb->ev_m[3 * e + 1] / (double)K,
-                        pb->ev_m[3 * e + 2] / (double)K};
-        for (int64_t k = 0; k < K; ++k) {
-            precess_relax(M, tau, mu, x, y, z, dw, m0, t1, t2);
-            if (n_adc > 0) {
-                if (pb->n_coils == 0) {
-                    signal[2 * sample] += M[0];
-                    signal[2 * sample + 1] += M[1];
-                } else {
-                    for (int32_t c = 0; c < pb->n_coils; ++c) {
-                        double sx = pb->s_x[c * pb->n_spins + i], sy = pb->s_y[c * pb->n_spins + i];
-                        double *sc = signal + 2 * pb->n_samples * c;
-                        sc[2 * sample] += sx * M[0] + sy * M[1];
-                        sc[2 * sample + 1] += sx * M[1] - sy * M[0];
-                    }
-                }
+        int32_t tj = pb->ev_traj ? pb->ev_traj[e] : -1;
+        if (tj >= 0) {
+            /* samples at the trajectory's instants, then the rest of the interval */
+            double t_prev = 0.0, k_prev[3] = {0.0, 0.0, 0.0};
+            const double *tk = pb->tr_k + 3 * pb->tr_off[tj], *tt = pb->tr_t + pb->tr_off[tj];
+            for (int64_t q = 0; q < n_adc; ++q) {
+                double mu[3] = {tk[3 * q] - k_prev[0], tk[3 * q + 1] - k_prev[1], tk[3 * q + 2] - k_prev[2]};
+                precess_relax(M, tt[q] - t_prev, mu, x, y, z, dw, m0, t1, t2);
+                record(pb, i, signal, sample, M);
                 ++sample;
+                t_prev = tt[q];
+                k_prev[0] = tk[3 * q]; k_prev[1] = tk[3 * q + 1]; k_prev[2] = tk[3 * q + 2];
+            }
+            double mu[3] = {pb->ev_m[3 * e] - k_prev[0], pb->ev_m[3 * e + 1] - k_prev[1],
+                            pb->ev_m[3 * e + 2] - k_prev[2]};
+            precess_relax(M, pb->ev_dt[e] - t_prev, mu, x, y, z, dw, m0, t1, t2);
+        } else {
+            int64_t K = n_adc > 0 ? n_adc : 1;
+            double tau = pb->ev_dt[e] / (double)K;
+            double mu[3] = {pb->ev_m[3 * e] / (double)K, pb->ev_m[3 * e + 1] / (double)K,
+                            pb->ev_m[3 * e + 2] / (double)K};
+            for (int64_t k = 0; k < K; ++k) {
+                precess_relax(M, tau, mu, x, y, z, dw, m0, t1, t2);
+                if (n_adc > 0) {
+                    record(pb, i, signal, sample, M);
+                    ++sample;
+                }
             }
         }
         if (pb->ev_flags[e] & ORACLE_SPOIL) {
@@ -201,7 +236,7 @@ static void *worker(void *arg)
  * s_y hold n_coils * n_spins transverse sensitivities (coil-major) and
  * out_signal holds n_coils blocks of 2 * n_samples.  out_signal and out_final_m (3 * n_spins)
  * may each be NULL. */
-int oracle_simulate_full(int64_t n_spins,
+int oracle_simulate_traj(int64_t n_spins,
                           const double *x, const double *y, const double *z, const double *m0,
                           const double *t1, const double *t2, const double *dw,
                           int64_t n_events, const double *ev_dt, const double *ev_m,
@@ -211,10 +246,30 @@ int oracle_simulate_full(int64_t n_spins,
                           const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
                           const double *sh_phase,
                           int32_t n_coils, const double *s_x, const double *s_y, double *out_snap,
+                          const int32_t *ev_traj, int32_t n_traj, const int64_t *tr_n, const int64_t *tr_off,
+                          const double *tr_k, const double *tr_t,
                           int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
 {
-    if (n_spins < 0 || n_events < 0 || n_samples < 0 || n_threads < 1 || n_coils < 0)
+    if (n_spins < 0 || n_events < 0 || n_samples < 0 || n_threads < 1 || n_coils < 0 || n_traj < 0)
         return -1;
+    if (ev_traj)
+        for (int64_t e = 0; e < n_events; ++e) {
+            if (ev_traj[e] >= n_traj || ev_traj[e] < -1)
+                return -1;
+            if (ev_traj[e] >= 0) {
+                int64_t n = tr_n[ev_traj[e]], off = tr_off[ev_traj[e]];
+                if (n != ev_nadc[e])
+                    return -1;
+                double tp = 0.0;
+                for (int64_t q = 0; q < n; ++q) {
+                    if (!(tr_t[off + q] >= tp))
+                        return -1;
+                    tp = tr_t[off + q];
+                }
+                if (!(ev_dt[e] >= tp))
+                    return -1;
+            }
+        }
     if (n_coils > 0 && n_spins > 0 && (!s_x || !s_y))
         return -1;
     int64_t total = 0;
@@ -230,7 +285,8 @@ int oracle_simulate_full(int64_t n_spins,
 
     problem_t pb = {x, y, z, m0, t1, t2, dw, n_events, ev_dt, ev_m, ev_alpha, ev_phase,
                     ev_shape, ev_nadc, ev_flags, n_shapes, sh_nsub, sh_offset, sh_tau, sh_m,
-                    sh_alpha, sh_phase, n_samples, n_coils, n_spins, s_x, s_y, out_snap};
+                    sh_alpha, sh_phase, n_samples, n_coils, n_spins, s_x, s_y, out_snap,
+                    ev_traj, tr_n, tr_off, tr_k, tr_t};
     const int64_t n_vals = 2 * n_samples * (n_coils > 0 ? n_coils : 1);
 
     if (n_threads > n_spins && n_spins > 0)
@@ -280,7 +336,27 @@ int oracle_simulate_full(int64_t n_spins,
     return rc;
 }
 
-/* Signals of receive coils, no snapshots; see oracle_simulate_full. */
+/* Without trajectories; see oracle_simulate_traj. */
+int oracle_simulate_full(int64_t n_spins,
+                         const double *x, const double *y, const double *z, const double *m0,
+                         const double *t1, const double *t2, const double *dw,
+                         int64_t n_events, const double *ev_dt, const double *ev_m,
+                         const double *ev_alpha, const double *ev_phase, const int32_t *ev_shape,
+                         const int64_t *ev_nadc, const uint32_t *ev_flags,
+                         int32_t n_shapes, const int64_t *sh_nsub, const double *sh_tau,
+                         const double *sh_m, const int64_t *sh_offset, const double *sh_alpha,
+                         const double *sh_phase,
+                         int32_t n_coils, const double *s_x, const double *s_y, double *out_snap,
+                         int n_threads, int64_t n_samples, double *out_signal, double *out_final_m)
+{
+    return oracle_simulate_traj(n_spins, x, y, z, m0, t1, t2, dw, n_events, ev_dt, ev_m, ev_alpha,
+                                ev_phase, ev_shape, ev_nadc, ev_flags, n_shapes, sh_nsub, sh_tau,
+                                sh_m, sh_offset, sh_alpha, sh_phase, n_coils, s_x, s_y, out_snap,
+                                NULL, 0, NULL, NULL, NULL, NULL, n_threads, n_samples, out_signal,
+                                out_final_m);
+}
+
+/* Signals of receive coils, no snapshots; see oracle_simulate_traj. */
 int oracle_simulate_coils(int64_t n_spins,
                           const double *x, const double *y, const double *z, const double *m0,
                           const double *t1, const double *t2, const double *dw,

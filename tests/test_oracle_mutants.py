@@ -17,8 +17,9 @@ from oracle import build as obuild
 import tests.test_oracle_coils as coil_pins
 import tests.test_oracle_pins as pins
 import tests.test_oracle_snapshots as snapshot_pins
+import tests.test_oracle_trajectory as trajectory_pins
 
-PIN_MODULES = (pins, coil_pins, snapshot_pins)
+PIN_MODULES = (pins, coil_pins, snapshot_pins, trajectory_pins)
 
 MUTANTS = {
     "rf_sign_r02": ("r02 = -sp * sa", "r02 = sp * sa"),
@@ -51,6 +52,11 @@ MUTANTS = {
     "snapshot_components_reversed": ("pb->snap[(3 * snap + c) * pb->n_spins + i] = M[c];",
                                      "pb->snap[(3 * snap + c) * pb->n_spins + i] = M[2 - c];"),
     "snapshot_index_stuck": ("            ++snap;\n", "\n"),
+    "traj_last_piece_dropped": ("precess_relax(M, pb->ev_dt[e] - t_prev, mu, x, y, z, dw, m0, t1, t2);", ""),
+    "traj_moment_not_differenced": (
+        "double mu[3] = {tk[3 * q] - k_prev[0], tk[3 * q + 1] - k_prev[1], tk[3 * q + 2] - k_prev[2]};",
+        "double mu[3] = {tk[3 * q], tk[3 * q + 1], tk[3 * q + 2]};"),
+    "traj_time_not_differenced": ("precess_relax(M, tt[q] - t_prev, mu", "precess_relax(M, tt[q], mu"),
     "snapshot_spin_major": ("pb->snap[(3 * snap + c) * pb->n_spins + i] = M[c];",
                             "pb->snap[3 * snap * pb->n_spins + 3 * i + c] = M[c];"),
 }

@@ -20,12 +20,12 @@ equal-length elementary sequences (hard-pulse approximation, eq. 3.23).
 Receive coils (section 3.5.1): sensitivity maps S = B1 / i of circular
 loops (coils.py), inputs for multi-coil signals.
 """
-from .sequence import Sequence, Shape, SPOIL, SNAPSHOT, concat
+from .sequence import Sequence, Shape, Trajectory, SPOIL, SNAPSHOT, concat
 from .phantom import SpinObject, grid2d, grid3d_two_species, subset
 from . import coils, configs
 
 __all__ = [
-    "Sequence", "Shape", "SPOIL", "SNAPSHOT", "concat",
+    "Sequence", "Shape", "Trajectory", "SPOIL", "SNAPSHOT", "concat",
     "SpinObject", "grid2d", "grid3d_two_species", "subset",
     "coils", "configs",
 ]

@@ -25,6 +25,14 @@ Field layout (one entry per elementary sequence):
 A Shape (eq. 3.23, hard-pulse approximation of a modulated pulse) is n_sub
 equal sub-steps of length tau, each a hard pulse (alpha_i, phase_i + the
 event's rf_phase) followed by precession under the per-sub-step moment m_sub.
+
+A Trajectory replaces the equal ADC sub-steps of an interval by explicit
+sample instants: sample s is taken t[s] seconds after the interval start,
+when the gradient moment accumulated since the start is k[s] (cycles/m);
+the interval still ends after dt with total moment m.  An event refers to
+one with trajectory = index (n_adc must equal its length); -1 means the
+equal sub-steps of section 5.1.1.  Piecewise-constant gradients sampled on
+any raster (spirals, curved or variable-rate readouts) fit this form.
 """
 from __future__ import annotations
 
@@ -56,24 +64,41 @@ class Shape:
         return int(self.alpha.shape[0])
 
 
+@dataclasses.dataclass
+class Trajectory:
+    k: np.ndarray                    # (n, 3) cycles/m accumulated since the interval start
+    t: np.ndarray                    # (n,) s since the interval start, increasing
+
+    def __post_init__(self):
+        self.k = np.ascontiguousarray(self.k, dtype=np.float64).reshape(-1, 3)
+        self.t = np.ascontiguousarray(self.t, dtype=np.float64).reshape(-1)
+        if self.k.shape[0] != self.t.shape[0] or self.t.shape[0] < 1:
+            raise ValueError("trajectory k must be (n, 3) and t (n,), n >= 1")
+
+    @property
+    def n(self) -> int:
+        return int(self.t.shape[0])
+
+
 class Sequence:
-    """Growable list of elementary sequences plus a shape library."""
+    """Growable list of elementary sequences plus shape and trajectory libraries."""
 
     def __init__(self, name: str = "seq"):
         self.name = name
         self._rows: List[tuple] = []
         self.shapes: List[Shape] = []
+        self.trajectories: List[Trajectory] = []
         self.meta: dict = {}
         self._frozen = None
 
     # -- building -----------------------------------------------------------
     def add(self, dt: float, m=(0.0, 0.0, 0.0), alpha: float = 0.0, phase: float = 0.0,
-            shape: int = -1, n_adc: int = 0, flags: int = 0) -> "Sequence":
+            shape: int = -1, n_adc: int = 0, flags: int = 0, trajectory: int = -1) -> "Sequence":
         m = tuple(float(v) for v in m)
         if len(m) != 3:
             raise ValueError("moment must have 3 components")
         self._rows.append((float(dt), m, float(alpha), float(phase), int(shape),
-                           int(n_adc), int(flags)))
+                           int(n_adc), int(flags), int(trajectory)))
         self._frozen = None
         return self
 
@@ -81,6 +106,11 @@ class Sequence:
         self.shapes.append(shape)
         self._frozen = None
         return len(self.shapes) - 1
+
+    def add_trajectory(self, traj: Trajectory) -> int:
+        self.trajectories.append(traj)
+        self._frozen = None
+        return len(self.trajectories) - 1
 
     # -- array views ----------------------------------------------------------
     def _freeze(self):
@@ -93,11 +123,12 @@ class Sequence:
             s = np.empty(n, np.int32)
             na = np.empty(n, np.int64)
             fl = np.empty(n, np.uint32)
-            for i, (dti, mi, ai, pi, si, ni, fi) in enumerate(self._rows):
+            tr = np.empty(n, np.int32)
+            for i, (dti, mi, ai, pi, si, ni, fi, ti) in enumerate(self._rows):
                 dt[i] = dti; m[i] = mi; a[i] = ai; p[i] = pi
-                s[i] = si; na[i] = ni; fl[i] = fi
+                s[i] = si; na[i] = ni; fl[i] = fi; tr[i] = ti
             self._frozen = dict(dt=dt, m=m, rf_alpha=a, rf_phase=p, rf_shape=s,
-                                n_adc=na, flags=fl)
+                                n_adc=na, flags=fl, trajectory=tr)
         return self._frozen
 
     @property
@@ -118,6 +149,8 @@ class Sequence:
     def n_adc(self) -> np.ndarray: return self._freeze()["n_adc"]
     @property
     def flags(self) -> np.ndarray: return self._freeze()["flags"]
+    @property
+    def trajectory(self) -> np.ndarray: return self._freeze()["trajectory"]
 
     @property
     def n_samples(self) -> int:
@@ -140,6 +173,7 @@ class Sequence:
         out = Sequence(self.name + f"[:{n_events}]")
         out._rows = list(self._rows[:n_events])
         out.shapes = list(self.shapes)
+        out.trajectories = list(self.trajectories)
         out.meta = dict(self.meta)
         return out
 
@@ -153,7 +187,9 @@ def concat(seqs: _Seq[Sequence], name: Optional[str] = None) -> Sequence:
     out = Sequence(name or "+".join(s.name for s in seqs))
     for s in seqs:
         base = len(out.shapes)
+        tbase = len(out.trajectories)
         out.shapes.extend(s.shapes)
-        for (dt, m, a, p, sh, na, fl) in s._rows:
-            out._rows.append((dt, m, a, p, sh + base if sh >= 0 else -1, na, fl))
+        out.trajectories.extend(s.trajectories)
+        for (dt, m, a, p, sh, na, fl, tr) in s._rows:
+            out._rows.append((dt, m, a, p, sh + base if sh >= 0 else -1, na, fl, tr + tbase if tr >= 0 else -1))
     return out
