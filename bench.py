@@ -182,6 +182,9 @@ WORKLOADS = {
                    "128 spokes x 128 samples, spoiled GRE"),
     "t78-epi": ("Table 7.8 2-D EPI: 100^2 grid (10,000 spins) with the eq. 6.3 Legendre B0, "
                 "single shot, 128 lines x 128 samples"),
+    "spiral": ("2-D spiral: the c2 object (256x256 grid, 4 jittered isochromats/voxel, 262,144 spins), "
+               "32-interleave spiral spoiled GRE to k_max = 256/(2 FOV), 2048 samples per interleave at 4 us "
+               "(per-sample trajectory tables), TR 20 ms"),
     "t78-se3d": ("Table 7.8 3-D spin echo: 56^3 grid (175,616 spins) with the eq. 6.3 Legendre B0, "
                  "128 samples x 128 x 64 phase encodes"),
 }
@@ -199,6 +202,9 @@ def load_workload(name: str):
         return C.c3()
     if name.startswith("t78-"):
         return C.table78(name[4:])
+    if name == "spiral":
+        obj, _ = C.c2()
+        return obj, C.spiral_2d(32, 2048, res=256)
     raise ValueError(name)
 
 
@@ -385,6 +391,9 @@ def main():
             "kernel_ms_per_launch": k_ms / max(launches, 1),
             "flops_per_step": flops, "flops_per_launch": flops / max(launches, 1),
             "finalize_ms_per_step": fin_ms / max(args.steps, 1)}
+    if args.workload == "spiral":
+        roof["flops_basis"] = ("8 per spin-sample, the unit of the recurrence readout; tabulated samples are "
+                               "evaluated directly (FP64 phase, sin/cos, exp) at several times that cost")
     if args.plan:
         roof["kernel"] += " + finalize (one graph replay per step)"
         roof["timing"] = "HIP events around each graph replay on its stream"

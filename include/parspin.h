@@ -46,6 +46,12 @@ typedef enum ps_status {
  * end of the interval, after a spoiler (section 7.2: magnetisation instead of
  * echo data).  Honoured by ps_simulate_ex; the other entry points ignore it. */
 #define PS_EV_SNAPSHOT 2u
+/* ps_event.flags: the event's n_adc samples follow the trajectory table
+ * ps_sequence.trajectories[ps_event.trajectory] instead of the n_adc equal
+ * sub-steps: sample s is taken t[s] after the interval start, when the
+ * moment accumulated since the start is k[s]; the interval still ends after
+ * dt with total moment m.  Without this flag ps_event.trajectory must be 0. */
+#define PS_EV_TRAJECTORY 4u
 
 typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
 
@@ -102,8 +108,9 @@ typedef struct ps_event {
                                     added to every sub-pulse phase of rf_shape         */
     int32_t  rf_shape;           /* -1, or index into ps_sequence.shapes               */
     uint32_t n_adc;              /* 0, or number of samples (< 2^31)                   */
-    uint32_t flags;              /* PS_EV_SPOIL | PS_EV_SNAPSHOT                       */
-    uint32_t reserved;           /* must be 0                                          */
+    uint32_t flags;              /* PS_EV_SPOIL | PS_EV_SNAPSHOT | PS_EV_TRAJECTORY    */
+    uint32_t trajectory;         /* with PS_EV_TRAJECTORY: index into
+                                    ps_sequence.trajectories; else 0                   */
 } ps_event;
 
 /* A shaped pulse in the hard-pulse approximation (eq. 3.23): n_sub equal
@@ -118,12 +125,24 @@ typedef struct ps_rf_shape {
     const double *phase;         /* HOST, n_sub phases, rad                            */
 } ps_rf_shape;
 
+/* Sample instants of a non-uniform readout (spirals, curved or variable-rate
+ * trajectories played as piecewise-constant gradients): n samples; k[3 s ..
+ * 3 s + 2] is the moment (cycles/m) accumulated from the interval start to
+ * sample s, t[s] its time after the interval start (s, 0 <= t[0] <= t[1] ...
+ * <= dt of every event that uses it). */
+typedef struct ps_trajectory {
+    int64_t       n;
+    const double *k;             /* HOST, 3 n                                          */
+    const double *t;             /* HOST, n                                            */
+} ps_trajectory;
+
 typedef struct ps_sequence {
-    int64_t            n_events;
-    const ps_event    *events;   /* HOST                                               */
-    int32_t            n_shapes;
-    int32_t            reserved;
-    const ps_rf_shape *shapes;   /* HOST                                               */
+    int64_t              n_events;
+    const ps_event      *events;        /* HOST                                        */
+    int32_t              n_shapes;
+    int32_t              n_trajectories;
+    const ps_rf_shape   *shapes;        /* HOST                                        */
+    const ps_trajectory *trajectories;  /* HOST, may be NULL when n_trajectories = 0   */
 } ps_sequence;
 
 /* Fill *cfg with the defaults (device 0, precision 32, autotuned tiles). */

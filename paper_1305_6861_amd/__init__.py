@@ -24,7 +24,7 @@ from typing import Optional
 import numpy as np
 
 from . import _binding as _b
-from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT
+from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT, PS_EV_TRAJECTORY
 
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
@@ -48,12 +48,16 @@ class PackedSequence:
             sh = np.asarray(seq.rf_shape, np.int64)
             na = np.asarray(seq.n_adc, np.int64)
             fl = np.asarray(seq.flags, np.int64)
+            tr = (np.asarray(seq.trajectory, np.int64) if hasattr(seq, "trajectory")
+                  else np.full(n, -1, np.int64))
             if np.any(na < 0) or np.any(na > 0x7FFFFFFF):
                 raise PsError(1, "n_adc out of range")
+            fl = np.where(tr >= 0, fl | _b.PS_EV_TRAJECTORY, fl)
             rec = np.zeros(n, dtype=np.dtype([("dt", "<f8"), ("m", "<f8", (3,)), ("a", "<f8"), ("p", "<f8"),
                                                ("s", "<i4"), ("n", "<u4"), ("f", "<u4"), ("r", "<u4")]))
             rec["dt"] = dt; rec["m"] = m; rec["a"] = al; rec["p"] = ph
             rec["s"] = sh.astype(np.int32); rec["n"] = na.astype(np.uint32); rec["f"] = fl.astype(np.uint32)
+            rec["r"] = np.where(tr >= 0, tr, 0).astype(np.uint32)
             ctypes.memmove(self._events, rec.ctypes.data, rec.nbytes)
         shapes = list(getattr(seq, "shapes", []))
         self._keep = []
@@ -69,8 +73,17 @@ class PackedSequence:
                 rec.m_sub[d] = float(np.asarray(s.m_sub, np.float64).reshape(3)[d])
             rec.alpha = a.ctypes.data
             rec.phase = p.ctypes.data
-        self.struct = _b.ps_sequence(n, ctypes.addressof(self._events), len(shapes), 0,
-                                     ctypes.addressof(self._shapes))
+        trajs = list(getattr(seq, "trajectories", []))
+        self._trajs = (_b.ps_trajectory * max(len(trajs), 1))()
+        for i, t in enumerate(trajs):
+            k = np.ascontiguousarray(t.k, np.float64).reshape(-1)
+            tt = np.ascontiguousarray(t.t, np.float64).reshape(-1)
+            self._keep += [k, tt]
+            self._trajs[i].n = int(tt.shape[0])
+            self._trajs[i].k = k.ctypes.data
+            self._trajs[i].t = tt.ctypes.data
+        self.struct = _b.ps_sequence(n, ctypes.addressof(self._events), len(shapes), len(trajs),
+                                     ctypes.addressof(self._shapes), ctypes.addressof(self._trajs))
 
     def count(self):
         ns = ctypes.c_int64(); st = ctypes.c_int64()

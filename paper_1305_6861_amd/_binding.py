@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID_ARG", 2: "PS_E_NO_MEMORY", 3: "PS_E
                 4: "PS_E_TOO_LARGE", 5: "PS_E_NOT_READY", 6: "PS_E_CANCELLED", 7: "PS_E_NO_DEVICE"}
 PS_EV_SPOIL = 1
 PS_EV_SNAPSHOT = 2
+PS_EV_TRAJECTORY = 4
 PS_CFG_KERNEL_TIMING = 1
 PS_CFG_NO_SHAPE_CACHE = 2
 PS_CFG_NO_READOUT_SPLIT = 4
@@ -47,7 +48,7 @@ class ps_object(ctypes.Structure):
 class ps_event(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("m", ctypes.c_double * 3), ("rf_alpha", ctypes.c_double),
                 ("rf_phase", ctypes.c_double), ("rf_shape", ctypes.c_int32), ("n_adc", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("trajectory", ctypes.c_uint32)]
 
 
 class ps_rf_shape(ctypes.Structure):
@@ -55,9 +56,13 @@ class ps_rf_shape(ctypes.Structure):
                 ("m_sub", ctypes.c_double * 3), ("alpha", ctypes.c_void_p), ("phase", ctypes.c_void_p)]
 
 
+class ps_trajectory(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_void_p), ("t", ctypes.c_void_p)]
+
+
 class ps_sequence(ctypes.Structure):
     _fields_ = [("n_events", ctypes.c_int64), ("events", ctypes.c_void_p), ("n_shapes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("shapes", ctypes.c_void_p)]
+                ("n_trajectories", ctypes.c_int32), ("shapes", ctypes.c_void_p), ("trajectories", ctypes.c_void_p)]
 
 
 class ps_receive(ctypes.Structure):
@@ -67,6 +72,8 @@ class ps_receive(ctypes.Structure):
 
 assert ctypes.sizeof(ps_receive) == 24
 assert ctypes.sizeof(ps_event) == 64
+assert ctypes.sizeof(ps_trajectory) == 24
+assert ctypes.sizeof(ps_sequence) == 40
 assert ctypes.sizeof(ps_rf_shape) == 56
 assert ctypes.sizeof(ps_config) == 32
 

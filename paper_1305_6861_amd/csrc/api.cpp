@@ -19,7 +19,8 @@ static_assert(sizeof(ps_event) == 64, "ps_event ABI size");
 static_assert(sizeof(ps_rf_shape) == 56, "ps_rf_shape ABI size");
 static_assert(sizeof(ps_config) == 32, "ps_config ABI size");
 static_assert(sizeof(ps_object) == 64, "ps_object ABI size");
-static_assert(sizeof(ps_sequence) == 32, "ps_sequence ABI size");
+static_assert(sizeof(ps_sequence) == 40, "ps_sequence ABI size");
+static_assert(sizeof(ps_trajectory) == 24, "ps_trajectory ABI size");
 static_assert(sizeof(ps_receive) == 24, "ps_receive ABI size");
 
 namespace ps {
@@ -136,18 +137,24 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S,
 ps_status upload(Ctx* ctx, const Program& prog, hipStream_t stream) {
     const size_t ops_bytes = prog.ops.size() * sizeof(Op);
     const size_t rows_bytes = prog.rows.size() * sizeof(double);
+    const size_t traj_bytes = prog.traj.size() * sizeof(double);
     ps_status st;
     if ((st = ctx->ops.reserve(ops_bytes)) != PS_OK) return st;
     if ((st = ctx->rows.reserve(rows_bytes)) != PS_OK) return st;
-    if ((st = ctx->staging.reserve(ops_bytes + rows_bytes)) != PS_OK) return st;
+    if ((st = ctx->traj.reserve(traj_bytes)) != PS_OK) return st;
+    if ((st = ctx->staging.reserve(ops_bytes + rows_bytes + traj_bytes)) != PS_OK) return st;
     unsigned char* h = reinterpret_cast<unsigned char*>(ctx->staging.ptr);
     if (ops_bytes) std::memcpy(h, prog.ops.data(), ops_bytes);
     if (rows_bytes) std::memcpy(h + ops_bytes, prog.rows.data(), rows_bytes);
+    if (traj_bytes) std::memcpy(h + ops_bytes + rows_bytes, prog.traj.data(), traj_bytes);
     hipError_t e;
     if (ops_bytes && (e = hipMemcpyAsync(ctx->ops.ptr, h, ops_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ops)");
     if (rows_bytes && (e = hipMemcpyAsync(ctx->rows.ptr, h + ops_bytes, rows_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(rows)");
+    if (traj_bytes && (e = hipMemcpyAsync(ctx->traj.ptr, h + ops_bytes + rows_bytes, traj_bytes,
+                                          hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(trajectories)");
     return PS_OK;
 }
 
@@ -177,7 +184,7 @@ int replica_bound(const Program& p, int n_out) {
     int64_t max_adc = 0;
     for (const Slice& sl : p.slices) {
         int64_t c = 0;
-        for (int64_t i = sl.op_begin; i < sl.op_end; ++i) c += p.ops[i].kind == OP_ADC;
+        for (int64_t i = sl.op_begin; i < sl.op_end; ++i) c += p.ops[i].kind == OP_ADC || p.ops[i].kind == OP_ADCT;
         max_adc = std::max(max_adc, c);
     }
     int64_t R = std::min<int64_t>(max_adc, 64);
@@ -260,6 +267,7 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
     a.n_spins = r.obj.n_spins;
     a.n_shape_rows = (int32_t)(prog.rows.size() / 9);
     a.rows = b.rows;
+    a.traj = reinterpret_cast<const double*>(b.traj);
     a.partial = b.partial;
     a.row_stride = r.row_stride;
     a.state = b.state;
@@ -316,7 +324,7 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     if (r.fin_bytes > 0 && (st = ctx->fin_scratch.reserve(r.fin_bytes)) != PS_OK) return st;
     if (r.state_bytes > 0 && (st = ctx->state.reserve(r.state_bytes)) != PS_OK) return st;
     if ((st = upload(ctx, r.prog, stream)) != PS_OK) return st;
-    SingleBuffers b{ctx->ops.ptr, ctx->rows.ptr, ctx->partial.ptr, ctx->state.ptr,
+    SingleBuffers b{ctx->ops.ptr, ctx->rows.ptr, ctx->traj.ptr, ctx->partial.ptr, ctx->state.ptr,
                     reinterpret_cast<double*>(ctx->fin_scratch.ptr)};
     const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
     if ((st = enqueue_single(ctx, r, b, stream, timing ? ctx : nullptr)) != PS_OK) return st;
@@ -389,7 +397,7 @@ void ps_destroy(ps_ctx* handle) {
         for (auto& m : ctx->step_marks) { hipEventDestroy(m.first); hipEventDestroy(m.second); }
         for (auto& m : ctx->fin_marks) hipEventDestroy(m.second);   // m.first is a step mark
         for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
-        ctx->ops.release(); ctx->rows.release(); ctx->partial.release(); ctx->state.release();
+        ctx->ops.release(); ctx->rows.release(); ctx->traj.release(); ctx->partial.release(); ctx->state.release();
         ctx->fin_scratch.release(); ctx->batch_tables.release(); ctx->batch_records.release();
         ctx->staging2.release();
         ctx->staging.release();

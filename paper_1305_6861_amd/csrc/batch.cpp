@@ -48,7 +48,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
             int64_t samples_before = 0;
             for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
                 const Op& op = g.ops[i];
-                const int64_t w = op.kind == OP_ADC ? op.n : (op.kind == OP_SHAPE ? op.n : 1);
+                const int64_t w = (op.kind == OP_ADC || op.kind == OP_ADCT || op.kind == OP_SHAPE) ? op.n : 1;
                 if (steps > 0 && steps + w > max_slice_steps) {
                     // cut before op i; ADC offsets restart at the new slice
                     cur.op_end = i;
@@ -60,7 +60,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
                     steps = 0;
                     samples_before = 0;
                 }
-                if (op.kind == OP_ADC) {
+                if (op.kind == OP_ADC || op.kind == OP_ADCT) {
                     g.ops[i].aux = (uint32_t)samples_before;
                     samples_before += op.n;
                 }
@@ -88,10 +88,13 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
     p->bytes_mid = p->n_groups > 1 ? align_up((size_t)(p->n_groups * p->row_stride) * sizeof(double)) : 0;
     p->bytes_ops = align_up(p->prog.ops.size() * sizeof(Op));
     p->bytes_rows = align_up(p->prog.rows.size() * sizeof(double));
+    p->bytes_traj = align_up(p->prog.traj.size() * sizeof(double));
     return PS_OK;
 }
 
-size_t ReqPlan::device_bytes() const { return bytes_partial + bytes_state + bytes_mid + bytes_ops + bytes_rows; }
+size_t ReqPlan::device_bytes() const {
+    return bytes_partial + bytes_state + bytes_mid + bytes_ops + bytes_rows + bytes_traj;
+}
 
 size_t ReqPlan::footprint() const {
     return device_bytes() + (size_t)obj.n_spins * 7 * sizeof(float) + (size_t)prog.n_samples * 2 * sizeof(double);
@@ -104,6 +107,7 @@ void ReqPlan::bind(unsigned char* base) {
     d_mid = bytes_mid ? reinterpret_cast<double*>(q) : nullptr; q += bytes_mid;
     d_ops = reinterpret_cast<Op*>(q); q += bytes_ops;
     d_rows = reinterpret_cast<double*>(q); q += bytes_rows;
+    d_traj = reinterpret_cast<double*>(q); q += bytes_traj;
 }
 
 StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
@@ -115,6 +119,7 @@ StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     a.n_ops = (int32_t)(sl.op_end - sl.op_begin);
     a.n_shape_rows = (int32_t)(prog.rows.size() / 9);
     a.rows = d_rows;
+    a.traj = d_traj;
     a.partial = d_partial;
     a.row_stride = row_stride;
     a.state = d_state;
@@ -264,7 +269,7 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
 
 ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t staging_off, hipStream_t stream) {
     size_t need = 0;
-    for (ReqPlan* p : plans) need += p->bytes_ops + p->bytes_rows;
+    for (ReqPlan* p : plans) need += p->bytes_ops + p->bytes_rows + p->bytes_traj;
     ps_status st;
     if ((st = staging.reserve(staging_off + need)) != PS_OK) return st;
     unsigned char* h = reinterpret_cast<unsigned char*>(staging.ptr) + staging_off;
@@ -281,6 +286,13 @@ ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t s
             hipError_t e = hipMemcpyAsync(p->d_rows, h, rb, hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(rows)");
             h += p->bytes_rows;
+        }
+        const size_t tb = p->prog.traj.size() * sizeof(double);
+        if (tb) {
+            std::memcpy(h, p->prog.traj.data(), tb);
+            hipError_t e = hipMemcpyAsync(p->d_traj, h, tb, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(trajectories)");
+            h += p->bytes_traj;
         }
     }
     return PS_OK;

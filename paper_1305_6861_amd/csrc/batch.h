@@ -19,13 +19,14 @@ struct ReqPlan {
     int S = 1;
     int max_replicas = 1;              // readout replicas one tile can use
     int64_t n_blocks = 0, n_rows = 0, row_stride = 0, n_groups = 0;
-    size_t bytes_partial = 0, bytes_state = 0, bytes_mid = 0, bytes_ops = 0, bytes_rows = 0;
+    size_t bytes_partial = 0, bytes_state = 0, bytes_mid = 0, bytes_ops = 0, bytes_rows = 0, bytes_traj = 0;
     // device placement (bind)
     void* d_partial = nullptr;
     void* d_state = nullptr;
     double* d_mid = nullptr;
     Op* d_ops = nullptr;
     double* d_rows = nullptr;
+    double* d_traj = nullptr;
 
     size_t device_bytes() const;       // library buffers of this request
     size_t footprint() const;          // + object arrays + output (admission)

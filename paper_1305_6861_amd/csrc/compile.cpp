@@ -49,6 +49,21 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
     if (seq->n_events > 0 && !seq->events) { *err = "events is NULL"; return PS_E_INVALID_ARG; }
     if (seq->n_shapes < 0) { *err = "n_shapes < 0"; return PS_E_INVALID_ARG; }
     if (seq->n_shapes > 0 && !seq->shapes) { *err = "shapes is NULL"; return PS_E_INVALID_ARG; }
+    if (seq->n_trajectories < 0) { *err = "n_trajectories < 0"; return PS_E_INVALID_ARG; }
+    if (seq->n_trajectories > 0 && !seq->trajectories) { *err = "trajectories is NULL"; return PS_E_INVALID_ARG; }
+    for (int32_t j = 0; j < seq->n_trajectories; ++j) {
+        const ps_trajectory& tr = seq->trajectories[j];
+        const std::string where = "trajectory " + std::to_string(j) + ": ";
+        if (tr.n < 1 || tr.n > 0x7fffffffll || !tr.k || !tr.t) { *err = where + "n < 1 or NULL arrays"; return PS_E_INVALID_ARG; }
+        double tp = 0.0;
+        for (int64_t q = 0; q < tr.n; ++q) {
+            if (!finite(tr.t[q]) || tr.t[q] < tp) { *err = where + "times must be finite, >= 0 and non-decreasing"; return PS_E_INVALID_ARG; }
+            tp = tr.t[q];
+            if (!finite(tr.k[3 * q]) || !finite(tr.k[3 * q + 1]) || !finite(tr.k[3 * q + 2])) {
+                *err = where + "moment not finite"; return PS_E_INVALID_ARG;
+            }
+        }
+    }
 
     for (int32_t s = 0; s < seq->n_shapes; ++s) {
         const ps_rf_shape& sh = seq->shapes[s];
@@ -88,8 +103,18 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
             *err = where + "rf_shape out of range"; return PS_E_INVALID_ARG;
         }
         if (ev.n_adc > 0x7fffffffu) { *err = where + "n_adc too large"; return PS_E_INVALID_ARG; }
-        if (ev.flags & ~(PS_EV_SPOIL | PS_EV_SNAPSHOT)) { *err = where + "unknown flag bits"; return PS_E_INVALID_ARG; }
-        if (ev.reserved != 0) { *err = where + "reserved field must be 0"; return PS_E_INVALID_ARG; }
+        if (ev.flags & ~(PS_EV_SPOIL | PS_EV_SNAPSHOT | PS_EV_TRAJECTORY)) {
+            *err = where + "unknown flag bits"; return PS_E_INVALID_ARG;
+        }
+        const ps_trajectory* tr = nullptr;
+        if (ev.flags & PS_EV_TRAJECTORY) {
+            if ((int64_t)ev.trajectory >= seq->n_trajectories) { *err = where + "trajectory out of range"; return PS_E_INVALID_ARG; }
+            tr = &seq->trajectories[ev.trajectory];
+            if ((int64_t)ev.n_adc != tr->n) { *err = where + "n_adc differs from the trajectory's sample count"; return PS_E_INVALID_ARG; }
+            if (tr->t[tr->n - 1] > ev.dt) { *err = where + "trajectory runs past the interval"; return PS_E_INVALID_ARG; }
+        } else if (ev.trajectory != 0) {
+            *err = where + "trajectory must be 0 without PS_EV_TRAJECTORY"; return PS_E_INVALID_ARG;
+        }
 
         if (ev.rf_shape >= 0) {
             const ps_rf_shape& sh = seq->shapes[ev.rf_shape];
@@ -140,7 +165,25 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
         }
 
         const int64_t n = (int64_t)ev.n_adc;
-        if (n > 0) {
+        if (tr) {
+            // samples at tabulated instants: rows hold absolute (moment, time)
+            // since the anchors, so any piece of the op can start anywhere
+            Op op = blank_op(OP_ADCT);
+            std::memcpy(op.k, K, sizeof(K));
+            op.txy = txy;
+            op.n = (uint32_t)n;
+            op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
+            op.u.tab.row = p.traj.size() / 4;
+            for (int64_t q = 0; q < n; ++q) {
+                p.traj.push_back(K[0] + tr->k[3 * q]);
+                p.traj.push_back(K[1] + tr->k[3 * q + 1]);
+                p.traj.push_back(K[2] + tr->k[3 * q + 2]);
+                p.traj.push_back(txy + tr->t[q]);
+            }
+            p.ops.push_back(op);
+            p.n_samples += n;
+            p.n_adc_ops += 1;
+        } else if (n > 0) {
             Op op = blank_op(OP_ADC);
             const double mu[3] = {ev.m[0] / (double)n, ev.m[1] / (double)n, ev.m[2] / (double)n};
             const double tau = ev.dt / (double)n;
@@ -155,7 +198,9 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
         }
         K[0] += ev.m[0]; K[1] += ev.m[1]; K[2] += ev.m[2];
         txy += ev.dt; tz += ev.dt;
-        p.n_steps += n > 0 ? n : 1;
+        // intervals per spin: the samples' pieces, plus the rest of a
+        // trajectory interval after its last sample
+        p.n_steps += n > 0 ? n + (tr && tr->t[n - 1] < ev.dt ? 1 : 0) : 1;
 
         if (ev.flags & PS_EV_SPOIL) {
             if (!mxy_zero) p.ops.push_back(blank_op(OP_SPOIL));
@@ -176,7 +221,7 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
     // Operations after the last readout or snapshot cannot change an output.
     size_t keep = 0;
     for (size_t i = 0; i < p.ops.size(); ++i)
-        if (p.ops[i].kind == OP_ADC || p.ops[i].kind == OP_SNAP) keep = i + 1;
+        if (p.ops[i].kind == OP_ADC || p.ops[i].kind == OP_ADCT || p.ops[i].kind == OP_SNAP) keep = i + 1;
     p.ops.resize(keep);
     if ((int64_t)(p.rows.size() / 9) > kMaxShapeRows) {
         *err = "shaped pulses need " + std::to_string(p.rows.size() / 9) +
@@ -205,7 +250,7 @@ void plan_slices(Program* p, int64_t max_samples) {
         cur.sample_begin = sample;
     };
     for (const Op& op0 : p->ops) {
-        if (op0.kind != OP_ADC) { ops.push_back(op0); continue; }
+        if (op0.kind != OP_ADC && op0.kind != OP_ADCT) { ops.push_back(op0); continue; }
         int64_t done = 0;
         const int64_t n = op0.n;
         while (done < n) {
@@ -213,8 +258,12 @@ void plan_slices(Program* p, int64_t max_samples) {
             if (room <= 0) { close_slice(); room = max_samples; }
             const int64_t take = std::min<int64_t>(room, n - done);
             Op op = op0;
-            for (int d = 0; d < 3; ++d) op.k[d] = op0.k[d] + (double)done * op0.u.adc.mu[d];
-            op.txy = op0.txy + (double)done * op0.u.adc.tau;
+            if (op0.kind == OP_ADCT) {
+                op.u.tab.row = op0.u.tab.row + (uint64_t)done;
+            } else {
+                for (int d = 0; d < 3; ++d) op.k[d] = op0.k[d] + (double)done * op0.u.adc.mu[d];
+                op.txy = op0.txy + (double)done * op0.u.adc.tau;
+            }
             op.n = (uint32_t)take;
             op.aux = (uint32_t)(sample - cur.sample_begin);
             ops.push_back(op);

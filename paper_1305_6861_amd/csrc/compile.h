@@ -20,6 +20,7 @@ struct Slice {
 struct Program {
     std::vector<Op> ops;               // rotation deltas R - I in FP64 (r64)
     std::vector<double> rows;          // shaped-pulse rotation deltas, 9 per sub-step
+    std::vector<double> traj;          // trajectory sample rows: K + k_s (3), txy + t_s
     int64_t n_samples = 0;
     int64_t n_steps = 0;               // intervals per spin (see ps_count)
     int64_t n_rf = 0, n_shape_substeps = 0, n_adc_ops = 0;

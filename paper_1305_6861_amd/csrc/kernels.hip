@@ -496,6 +496,74 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     }
                     sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s];
                 }
+            } else if (kind == OP_ADCT) {
+                // Readout at tabulated instants (non-uniform trajectories):
+                // every sample is evaluated directly from the anchors,
+                //   p_s = Mxy_a E2(t_s) exp(-j 2 pi (k_s . x + dw t_s / 2 pi)),
+                // with the phase in FP64 from the absolute (k_s, t_s) rows.
+                // Each wave sums its own spins over 32-sample chunks; a wave
+                // group's waves add their chunk sums in LDS in wave order.
+                if (a.n_replicas > 1 && (adc_seen++ % a.n_replicas) != rep) continue;
+                const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
+                const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
+                const uint64_t row_u = op.u.tab.row;
+                const int64_t row0 = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(row_u >> 32)) << 32) |
+                                               (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)row_u));
+                const double* table = a.traj + 4 * row0;
+                const int n_chunks = (n + kT - 1) / kT;
+                real* red = &s_x[0][0][0][0];         // G x 64 chunk sums (s_x is free here)
+                const int n_passes = a.n_coils > 0 ? a.n_coils : 1;
+                for (int coil = 0; coil < n_passes; ++coil) {
+                    real wr[S], wi[S];               // coil-weighted anchors
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        wr[s] = sp.ar[s]; wi[s] = sp.ai[s];
+                        if (a.n_coils > 0) {
+                            const int64_t i = base + s * 64 + lane;
+                            real sx = 0, sy = 0;
+                            if (i < a.n_spins) {
+                                sx = (real)a.s_x[coil * a.n_spins + i];
+                                sy = (real)a.s_y[coil * a.n_spins + i];
+                            }
+                            wr[s] = fma(sx, sp.ar[s], sy * sp.ai[s]);
+                            wi[s] = fma(sx, sp.ai[s], -sy * sp.ar[s]);
+                        }
+                    }
+                    real* partial_c = partial + coil * a.coil_stride;
+                    for (int j = 0; j < n_chunks; ++j) {
+                        real acc[2 * kT];
+#pragma unroll
+                        for (int t = 0; t < kT; ++t) {
+                            const int smp = min(j * kT + t, n - 1);   // rows past n are never stored
+                            const double* row = table + 4 * smp;
+                            const double kx = row[0], ky = row[1], kz = row[2], tt = row[3];
+                            real sr = 0, si = 0;
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                const double ph = fma(kx, (double)sp.x[s], fma(ky, (double)sp.y[s],
+                                                  fma(kz, (double)sp.z[s], (double)sp.dw[s] * kInv2Pi * tt)));
+                                real c, sn;
+                                Math<real>::cis(ph, c, sn);
+                                const real e2 = Math<real>::expneg(tt, sp.r2[s]);
+                                sr += e2 * fma(wr[s], c, wi[s] * sn);
+                                si += e2 * fma(wi[s], c, -wr[s] * sn);
+                            }
+                            acc[2 * t] = sr; acc[2 * t + 1] = si;
+                        }
+                        real v = wave_reduce64(acc, lane);
+                        if constexpr (G > 1) {
+                            __syncthreads();             // earlier readers of red are done
+                            red[wave * 64 + lane] = v;
+                            __syncthreads();
+                            if (wg == 0) {
+                                v = red[wave * 64 + lane];
+#pragma unroll
+                                for (int g = 1; g < G; ++g) v += red[(wave + g) * 64 + lane];
+                            }
+                        }
+                        if (wg == 0 && j * kT + (lane >> 1) < n) partial_c[2 * (int64_t)(aux + j * kT) + lane] = v;
+                    }
+                }
             } else if (kind == OP_ADC) {
                 // A readout changes no spin state, so replicas of this tile
                 // share the slice's readouts round-robin and skip the others.

@@ -20,7 +20,7 @@ namespace ps {
 struct Plan {
     Ctx* ctx = nullptr;
     Single r;
-    DevBuf ops, rows, partial, state, fin;
+    DevBuf ops, rows, traj, partial, state, fin;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;       // completion of the last replay
@@ -33,7 +33,7 @@ static void plan_free(Plan* p) {
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->done) hipEventDestroy(p->done);
-    p->ops.release(); p->rows.release(); p->partial.release(); p->state.release(); p->fin.release();
+    p->ops.release(); p->rows.release(); p->traj.release(); p->partial.release(); p->state.release(); p->fin.release();
     delete p;
 }
 
@@ -64,7 +64,9 @@ ps_status ps_plan_create(ps_ctx* handle, const ps_object* obj, const ps_sequence
     SingleBuffers b;
     if (!p->r.empty()) {
         const size_t ops_bytes = prog.ops.size() * sizeof(Op), rows_bytes = prog.rows.size() * sizeof(double);
+        const size_t traj_bytes = prog.traj.size() * sizeof(double);
         if ((st = p->ops.reserve(ops_bytes)) != PS_OK || (st = p->rows.reserve(rows_bytes)) != PS_OK ||
+            (st = p->traj.reserve(traj_bytes)) != PS_OK ||
             (st = p->partial.reserve(p->r.partial_bytes)) != PS_OK ||
             (p->r.fin_bytes && (st = p->fin.reserve(p->r.fin_bytes)) != PS_OK) ||
             (p->r.state_bytes && (st = p->state.reserve(p->r.state_bytes)) != PS_OK)) {
@@ -72,11 +74,12 @@ ps_status ps_plan_create(ps_ctx* handle, const ps_object* obj, const ps_sequence
             return st;
         }
         if ((ops_bytes && (e = hipMemcpy(p->ops.ptr, prog.ops.data(), ops_bytes, hipMemcpyHostToDevice)) != hipSuccess) ||
-            (rows_bytes && (e = hipMemcpy(p->rows.ptr, prog.rows.data(), rows_bytes, hipMemcpyHostToDevice)) != hipSuccess)) {
+            (rows_bytes && (e = hipMemcpy(p->rows.ptr, prog.rows.data(), rows_bytes, hipMemcpyHostToDevice)) != hipSuccess) ||
+            (traj_bytes && (e = hipMemcpy(p->traj.ptr, prog.traj.data(), traj_bytes, hipMemcpyHostToDevice)) != hipSuccess)) {
             plan_free(p);
             return hip_fail(e, "hipMemcpy(plan tables)");
         }
-        b = SingleBuffers{p->ops.ptr, p->rows.ptr, p->partial.ptr, p->state.ptr,
+        b = SingleBuffers{p->ops.ptr, p->rows.ptr, p->traj.ptr, p->partial.ptr, p->state.ptr,
                           reinterpret_cast<double*>(p->fin.ptr)};
     }
     // capture the launches on a private stream (default priority)

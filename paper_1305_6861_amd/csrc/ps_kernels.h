@@ -24,6 +24,7 @@ struct StepArgs {
     const float *s_x, *s_y;  // device, n_coils * n_spins transverse sensitivities
     int64_t coil_stride;     // reals between coils' sample blocks inside a row
     void* snaps;             // device, n_snapshots * 3 * n_spins reals (OP_SNAP targets)
+    const double* traj;      // device, trajectory rows (K + k_s, txy + t_s), 4 doubles each
     int32_t n_replicas;      // readout replicas per tile (>= 1; launch_step only)
     int64_t n_tiles;         // workgroup tiles of the object (set by launch_step)
 };

@@ -26,6 +26,8 @@ enum OpKind : uint32_t {
     OP_SPOIL = 3,  // Mxy_a := 0 (transverse anchor reset)
     OP_SHAPE = 4,  // shaped pulse: evaluate, then n_sub sub-steps (eq. 3.23)
     OP_SNAP = 5,   // evaluate and store every spin's M as snapshot aux
+    OP_ADCT = 6,   // n samples at tabulated (k, t): rows u.tab.row ... of the
+                   // trajectory table hold (K + k_s, txy + t_s), absolute
 };
 
 enum OpFlags : uint32_t {
@@ -43,6 +45,7 @@ struct alignas(16) Op {
         float r32[9];                            // RF rotation, FP32 tables
         struct { double mu[3]; double tau; } adc;  // ADC: per-sample moment and
                                                    // dwell
+        struct { uint64_t row; } tab;            // ADCT: first row of its samples
         struct {
             double mu[3];       // per-sub-step moment (same place as adc.mu)
             double tau;         // sub-step duration (same place as adc.tau)

@@ -44,7 +44,7 @@ struct Ctx {
     ps_config cfg{};
     int n_cu = 256;
     std::mutex mu;                 // serialises calls on one context
-    DevBuf ops, rows, partial, state, fin_scratch;
+    DevBuf ops, rows, traj, partial, state, fin_scratch;
     DevBuf batch_tables, batch_records;   // ps_simulate_batch
     HostBuf staging, staging2;
     hipEvent_t done = nullptr;     // completion of the last request's work
@@ -88,6 +88,7 @@ struct Single {
 struct SingleBuffers {
     const void* ops = nullptr;
     const void* rows = nullptr;
+    const void* traj = nullptr;
     void* partial = nullptr;
     void* state = nullptr;
     double* fin_scratch = nullptr;

@@ -60,7 +60,7 @@ def test_count_rejects_invalid_sequences(bad):
     if bad == "inf_m": kw["m"] = (1, math.inf, 0)
     if bad == "nan_alpha": kw["alpha"] = float("nan")
     if bad == "shape_idx": kw["shape"] = 0
-    if bad == "flags": kw["flags"] = 6
+    if bad == "flags": kw["flags"] = 8 | 2
     seq.add(**kw)
     with pytest.raises(ps.PsError) as ei:
         ps.count(seq)

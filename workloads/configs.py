@@ -30,7 +30,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .sequence import Sequence, Shape, SPOIL
+from .sequence import Sequence, Shape, Trajectory, SPOIL
 from .phantom import SpinObject, grid2d, grid3d_two_species
 
 FOV = 0.25
@@ -366,3 +366,26 @@ def table78(kind: str, scale: int = 1) -> Tuple[SpinObject, Sequence]:
     if kind == "epi":
         return obj, epi_2d(n)
     raise ValueError(f"unknown Table 7.8 experiment {kind!r}")
+
+
+def spiral_2d(n_interleaves: int, n_samples: int, fov: float = FOV, res: int = 128, alpha_deg: float = 30.0,
+              tr: float = 20e-3, te: float = 2e-3, dwell: float = 4e-6, name: str = "spiral2d") -> Sequence:
+    """Multi-shot spiral spoiled GRE: each TR a pulse, a wait to TE, then a
+    constant-angular-velocity Archimedean spiral out to k_max = res / (2 fov)
+    sampled on the dwell raster (a per-sample trajectory table), and a
+    spoiled rest.  Interleave i is rotated by 2 pi i / n_interleaves."""
+    seq = Sequence(name)
+    k_max = res / (2.0 * fov)
+    turns = res / (2.0 * n_interleaves)
+    u = (np.arange(n_samples) + 1) / n_samples
+    t = u * n_samples * dwell
+    t_adc = n_samples * dwell + dwell
+    for i in range(n_interleaves):
+        th = 2 * math.pi * turns * u + 2 * math.pi * i / n_interleaves
+        k = np.stack([k_max * u * np.cos(th), k_max * u * np.sin(th), np.zeros(n_samples)], axis=1)
+        j = seq.add_trajectory(Trajectory(k=k, t=t))
+        seq.add(te, alpha=alpha_deg * DEG)
+        seq.add(t_adc, m=tuple(k[-1]), n_adc=n_samples, trajectory=j)
+        seq.add(tr - te - t_adc, flags=SPOIL)
+    seq.meta.update(kind="spiral2d", n_interleaves=n_interleaves, n_samples=n_samples, fov=fov, res=res)
+    return seq

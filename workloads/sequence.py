@@ -166,6 +166,9 @@ class Sequence:
         for s in self.rf_shape:
             if s >= 0:
                 steps += self.shapes[int(s)].n_sub
+        for e, j in enumerate(self.trajectory):       # the piece after a table's last sample
+            if j >= 0 and self.trajectories[int(j)].t[-1] < self.dt[e]:
+                steps += 1
         return steps
 
     def truncated(self, n_events: int) -> "Sequence":
