@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import math
+import platform
 import os
 import sys
 import time
@@ -261,6 +262,12 @@ def cpu_baseline(obj, seq, ctx, target_s: float, rx=None):
     t0 = time.perf_counter()
     ref = oracle.simulate(sub, seq, n_threads=threads, coils=sub_rx(stride))
     dt = time.perf_counter() - t0
+    # one thread on a quarter of the multi-thread run's time
+    stride1 = stride << max(0, int(math.ceil(math.log2(max(threads, 1) * 4))))
+    sub1 = subset(obj, min(stride1, obj.n_spins))
+    t1 = time.perf_counter()
+    oracle.simulate(sub1, seq, n_threads=1, coils=sub_rx(min(stride1, obj.n_spins)))
+    dt1 = time.perf_counter() - t1
     import torch
     got = ctx.simulate(sub, seq, coils=sub_rx(stride))
     torch.cuda.synchronize()
@@ -269,7 +276,20 @@ def cpu_baseline(obj, seq, ctx, target_s: float, rx=None):
             "kind": "oracle",
             "sample": f"every {stride}th spin ({sub.n_spins} spins) through the full sequence "
                       f"({n_steps} steps/spin), {dt:.1f} s",
+            "one_thread": {"value": sub1.n_spins * n_steps / dt1, "spins": sub1.n_spins, "seconds": dt1},
+            "cpu_model": cpu_model(),
             "gpu_rel_l2_on_sample": err}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def copy_calibration(n_bytes: int = 1 << 30, reps: int = 5):

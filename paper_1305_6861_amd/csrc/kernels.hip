@@ -26,12 +26,17 @@
 // per sample, the butterfly cost is shared by that many spins, and no
 // cross-wave reduction or barrier sits inside the sample loop.
 //
+// Inside a chunk the samples are taken in blocks of M = 4: a spin adds p,
+// p z, p z^2, p z^3 (powers from FP64 phases, held in registers) to the
+// lane's four sample sums as complex multiply-accumulates, then steps
+// p <- p z^4.
+//
 // Per-sample superposition (eq. 3.32): each lane first sums its G * S
 // spins, then a butterfly over 32 consecutive samples (64 reals) reduces the
-// 64 lanes with permlane32/16 swaps and DPP, leaving lane l with sample l/2,
-// component l%2, and the wave writes that partial sum into its wave group's
-// row.  A second kernel sums all rows in FP64 in row order.  Every order is
-// fixed, so results are bitwise reproducible for a given tiling.
+// 64 lanes with permlane32/16 swaps and DPP, and the wave writes the partial
+// sum each lane ends with into its wave group's row.  A second kernel sums
+// all rows in FP64 in row order.  Every order is fixed, so results are
+// bitwise reproducible for a given tiling.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -47,6 +52,15 @@ constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kOpChunk = 32;
 constexpr int kT = 32;  // samples per reduction chunk (64 reals -> 64 lanes)
+
+// Samples per readout block.  Inside a block of M samples a spin adds
+// p z^m (m = 0 .. M-1) to the sample sums, with z^m precomputed, and only
+// then steps p <- p z^M: a complex multiply-accumulate is 4 FMAs, so a
+// sample costs 4 + 2 / M instructions per spin instead of 6 (multiply, then
+// add).  The powers take registers, so FP64 keeps the plain recurrence.
+template <typename real> struct ReadoutBlock { static constexpr int M = 4; };
+template <> struct ReadoutBlock<double> { static constexpr int M = 1; };
+static_assert(kT % ReadoutBlock<float>::M == 0, "a chunk holds whole readout blocks");
 
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
@@ -100,8 +114,8 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-template <int CTRL, int BIT, int HALF>
-__device__ __forceinline__ void dpp_stage(float (&v)[64], int lane) {
+template <int CTRL, int BIT, int HALF, int N>
+__device__ __forceinline__ void dpp_stage(float (&v)[N], int lane) {
     const bool upper = (lane & BIT) != 0;
 #pragma unroll
     for (int i = 0; i < HALF; ++i) {
@@ -130,6 +144,73 @@ __device__ __forceinline__ float wave_reduce64(float (&v)[64], int lane) {
     dpp_stage<0x141, 4, 4>(v, lane);  // row_half_mirror: l <-> 7 - l within 8
     dpp_stage<0x4E, 2, 2>(v, lane);   // quad_perm [2,3,0,1]: l <-> l ^ 2
     dpp_stage<0xB1, 1, 1>(v, lane);   // quad_perm [1,0,3,2]: l <-> l ^ 1
+    return v[0];
+}
+
+// Readout form of the same reduction, for a chunk of 32 samples produced
+// as four quarters of 8: each quarter's 16 values (v[2 s + c] = component c
+// of its sample s) are halved twice right away, across lane bits 5 and 4,
+// so that only 4 values per quarter stay live; the 16 values left then go
+// through lane bits 3 .. 0.  Lane l ends with the wave sum of component
+// l & 1 of chunk sample readout_sample_of_lane(l).
+__device__ __forceinline__ int readout_sample_of_lane(int lane) {
+    return ((lane >> 1) & 1) | (((lane >> 4) & 1) << 1) | (((lane >> 5) & 1) << 2) |
+           (((lane >> 2) & 1) << 3) | (((lane >> 3) & 1) << 4);
+}
+
+template <int H>
+__device__ __forceinline__ void perm32_stage(float (&v)[16]) {   // value i vs i + H across lanes l, l ^ 32
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+
+template <int H>
+__device__ __forceinline__ void perm16_stage(float (&v)[16]) {   // value i vs i + H across lanes l, l ^ 16
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+
+__device__ __forceinline__ void quarter_reduce(float (&v)[16], int) {
+    perm32_stage<8>(v);
+    perm16_stage<4>(v);
+}
+
+__device__ __forceinline__ float reduce16(float (&v)[16], int lane) {
+    dpp_stage<0x140, 8, 8>(v, lane);
+    dpp_stage<0x141, 4, 4>(v, lane);
+    dpp_stage<0x4E, 2, 2>(v, lane);
+    dpp_stage<0xB1, 1, 1>(v, lane);
+    return v[0];
+}
+
+// value i vs i + H across lanes l, l ^ D (FP64)
+template <int D, int H, int N>
+__device__ __forceinline__ void xor_stage_h(double (&v)[N], int lane) {
+    const bool upper = (lane & D) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        double send = upper ? v[i] : v[i + H];
+        double keep = upper ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, D, 64);
+    }
+}
+
+__device__ __forceinline__ void quarter_reduce(double (&v)[16], int lane) {
+    xor_stage_h<32, 8>(v, lane);
+    xor_stage_h<16, 4>(v, lane);
+}
+
+__device__ __forceinline__ double reduce16(double (&v)[16], int lane) {
+    xor_stage_h<8, 8>(v, lane);
+    xor_stage_h<4, 4>(v, lane);
+    xor_stage_h<2, 2>(v, lane);
+    xor_stage_h<1, 1>(v, lane);
     return v[0];
 }
 
@@ -179,6 +260,15 @@ struct Spins {
     double r1[S], r2[S];     // 1/T1, 1/T2 (0 for +inf)
     real ar[S], ai[S], az[S];  // anchors: Mxy_a = ar + j ai, Mz_a = az
 };
+
+// A wave-uniform FP64 value (read from LDS into vector registers) moved to
+// scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
 
 // Phase of a spin in revolutions: k.x + (dw / 2 pi) t.
 __device__ __forceinline__ double phase_rev(const double* k, double t, float x, float y, float z,
@@ -252,8 +342,9 @@ __device__ __forceinline__ void step_delta(double c, double tau, double r2, real
 template <typename real, int S>
 constexpr size_t static_lds_bytes() {
     constexpr int G = ReadoutShare<S>::G;
-    return sizeof(Op) * kOpChunk + sizeof(real) * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 8 * 64 +
-           sizeof(real) * S * 6 * kBlock;
+    constexpr int NF = 6 + 2 * (ReadoutBlock<real>::M - 1);
+    return sizeof(Op) * kOpChunk + sizeof(real) * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 2 * 64 +
+           sizeof(real) * S * NF * kBlock;
 }
 
 // Shaped-pulse propagator of every spin of this lane (see ps_ops.h): the
@@ -342,11 +433,14 @@ template <typename real, int S>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, const int rep) {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int R = G * S;                 // spins per lane inside readouts
+    constexpr int M = ReadoutBlock<real>::M;
+    constexpr int NF = 6 + 2 * (M - 1);      // step factors per spin (re, im pairs)
     __shared__ Op s_ops[kOpChunk];
-    __shared__ real s_x[G > 1 ? kWaves : 1][G > 1 ? S : 1][8][64];   // readout anchors
-    // readout step factors (z, z^32, z^(32 G)) of every spin of the tile for
-    // the (mu, tau) of the last ADC operation; each lane reads only its own
-    __shared__ real s_stepf[S][6][kBlock];
+    __shared__ real s_x[G > 1 ? kWaves : 1][G > 1 ? S : 1][2][64];   // readout sample-0 values
+    // readout step factors (z, z^32, z^(32 G), z^2 .. z^M) of every spin of
+    // the tile for the (mu, tau) of the last ADC operation, written by the
+    // spin's own lane and read by the lanes of its wave group
+    __shared__ real s_stepf[S][NF][kBlock];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
     // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
@@ -507,8 +601,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
                 const uint64_t row_u = op.u.tab.row;
-                const int64_t row0 = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(row_u >> 32)) << 32) |
-                                               (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)row_u));
+                const int64_t row0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(row_u >> 32)) << 32) |
+                                               (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)row_u));
                 const double* table = a.traj + 4 * row0;
                 const int n_chunks = (n + kT - 1) / kT;
                 real* red = &s_x[0][0][0][0];         // G x 64 chunk sums (s_x is free here)
@@ -570,7 +664,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 if (a.n_replicas > 1 && (adc_seen++ % a.n_replicas) != rep) continue;
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
-                const double tau = op.u.adc.tau;
+                const double tau = uniform(op.u.adc.tau);
+                const double mu[3] = {uniform(op.u.adc.mu[0]), uniform(op.u.adc.mu[1]), uniform(op.u.adc.mu[2])};
                 // this wave's spins: sample 0 (p0), one sample step (z), one
                 // chunk (Z = z^32) and one group stride (W = z^(32 G)), all
                 // from FP64 phases
@@ -578,13 +673,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 // readouts of a sequence usually share them, so they are kept
                 // (in LDS, off the register budget) from the previous ADC
                 // operation when (mu, tau) is unchanged.
-                const bool same_step = step_valid && op.u.adc.mu[0] == step_mu[0] &&
-                                       op.u.adc.mu[1] == step_mu[1] && op.u.adc.mu[2] == step_mu[2] &&
-                                       tau == step_tau;
-                // z, Z and W of spin s into f[0..5] (re, im pairs)
+                const bool same_step = step_valid && mu[0] == step_mu[0] && mu[1] == step_mu[1] &&
+                                       mu[2] == step_mu[2] && tau == step_tau;
+                // z, Z and W of spin s into f[0..5], z^2 .. z^M into f[6..]
+                // (re, im pairs), each from its own FP64 phase
                 auto step_factors = [&](int s, real* f) {
                     real c, sn;
-                    const double ph = phase_rev(op.u.adc.mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
+                    const double ph = phase_rev(mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
                     real ez = Math<real>::expneg(tau, sp.r2[s]);
                     Math<real>::cis(ph, c, sn);
                     f[0] = ez * c; f[1] = -ez * sn;
@@ -598,16 +693,25 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     } else {
                         f[4] = f[2]; f[5] = f[3];
                     }
+#pragma unroll
+                    for (int m = 2; m <= M; ++m) {
+                        real em = Math<real>::expneg(tau * m, sp.r2[s]);
+                        Math<real>::cis(ph * m, c, sn);
+                        f[6 + 2 * (m - 2)] = em * c; f[7 + 2 * (m - 2)] = -em * sn;
+                    }
                 };
+                // other waves of the group may still read the factors and
+                // sample-0 values of the previous readout
+                if constexpr (G > 1) __syncthreads();
                 if (!same_step) {
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        real f[6];
+                        real f[NF];
                         step_factors(s, f);
 #pragma unroll
-                        for (int k = 0; k < 6; ++k) s_stepf[s][k][tid] = f[k];
+                        for (int k = 0; k < NF; ++k) s_stepf[s][k][tid] = f[k];
                     }
-                    step_mu[0] = op.u.adc.mu[0]; step_mu[1] = op.u.adc.mu[1]; step_mu[2] = op.u.adc.mu[2];
+                    step_mu[0] = mu[0]; step_mu[1] = mu[1]; step_mu[2] = mu[2];
                     step_tau = tau;
                     step_valid = true;
                 }
@@ -626,11 +730,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 // spin; the spins' stepping above is shared by all coils.
                 const int n_passes = a.n_coils > 0 ? a.n_coils : 1;
                 for (int coil = 0; coil < n_passes; ++coil) {
-                real ap[S][8];
+                real ap[S][2];
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) ap[s][2 + k] = s_stepf[s][k][tid];
                     if (a.n_coils > 0) {
                         const int64_t i = base + s * 64 + lane;
                         real sx = 0, sy = 0;
@@ -646,23 +748,32 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     }
                 }
                 real* partial_c = partial + coil * a.coil_stride;
-                // the wave group's G * S spins (LDS exchange when G > 1)
-                real pr[R], pi[R], zr[R], zi[R], Wr[R], Wi[R];
+                // the wave group's G * S spins (LDS exchange when G > 1);
+                // zr/zi[q][m - 1] = z^m of spin q for m = 1 .. M
+                // (W, the stride of G chunks, is read from LDS when it is used
+                // if G > 1, to keep it off the register budget)
+                real pr[R], pi[R], zr[R][M], zi[R][M], Wr[G > 1 ? 1 : R], Wi[G > 1 ? 1 : R];
                 if constexpr (G > 1) {
-                    __syncthreads();             // earlier readers of s_x are done
+                    if (coil > 0) __syncthreads();   // earlier readers of s_x are done
 #pragma unroll
-                    for (int s = 0; s < S; ++s)
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) s_x[wave][s][k][lane] = ap[s][k];
+                    for (int s = 0; s < S; ++s) {
+                        s_x[wave][s][0][lane] = ap[s][0];
+                        s_x[wave][s][1][lane] = ap[s][1];
+                    }
                     __syncthreads();
                     const int w0 = (wave / G) * G;
 #pragma unroll
                     for (int q = 0; q < R; ++q) {
                         const int sw = w0 + q / S, ss = q % S;
+                        const int ln = sw * 64 + lane;
                         real p_r = s_x[sw][ss][0][lane], p_i = s_x[sw][ss][1][lane];
-                        const real Zr_ = s_x[sw][ss][4][lane], Zi_ = s_x[sw][ss][5][lane];
-                        zr[q] = s_x[sw][ss][2][lane]; zi[q] = s_x[sw][ss][3][lane];
-                        Wr[q] = s_x[sw][ss][6][lane]; Wi[q] = s_x[sw][ss][7][lane];
+                        const real Zr_ = s_stepf[ss][2][ln], Zi_ = s_stepf[ss][3][ln];
+                        zr[q][0] = s_stepf[ss][0][ln]; zi[q][0] = s_stepf[ss][1][ln];
+#pragma unroll
+                        for (int m = 1; m < M; ++m) {
+                            zr[q][m] = s_stepf[ss][6 + 2 * (m - 1)][ln];
+                            zi[q][m] = s_stepf[ss][7 + 2 * (m - 1)][ln];
+                        }
                         for (int k = 0; k < wg; ++k) {   // start at chunk wg: p0 Z^wg
                             const real t = p_r * Zr_ - p_i * Zi_;
                             p_i = p_r * Zi_ + p_i * Zr_;
@@ -674,39 +785,79 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 #pragma unroll
                     for (int q = 0; q < R; ++q) {
                         const int s = q % S;
-                        pr[q] = ap[s][0]; pi[q] = ap[s][1]; zr[q] = ap[s][2]; zi[q] = ap[s][3];
-                        Wr[q] = ap[s][6]; Wi[q] = ap[s][7];
+                        pr[q] = ap[s][0]; pi[q] = ap[s][1];
+                        zr[q][0] = s_stepf[s][0][tid]; zi[q][0] = s_stepf[s][1][tid];
+#pragma unroll
+                        for (int m = 1; m < M; ++m) {
+                            zr[q][m] = s_stepf[s][6 + 2 * (m - 1)][tid];
+                            zi[q][m] = s_stepf[s][7 + 2 * (m - 1)][tid];
+                        }
+                        Wr[q] = s_stepf[s][4][tid]; Wi[q] = s_stepf[s][5][tid];
                     }
                 }
                 const int n_chunks = (n + kT - 1) / kT;
+                const int smp_of_lane = readout_sample_of_lane(lane);
                 for (int j = wg; j < n_chunks; j += G) {
                     real qr[R], qi[R];
 #pragma unroll
                     for (int q = 0; q < R; ++q) { qr[q] = pr[q]; qi[q] = pi[q]; }
-                    real acc[2 * kT];
+                    real red[16];
 #pragma unroll
-                    for (int t = 0; t < kT; ++t) {
-                        real sr = qr[0], si = qi[0];
+                    for (int h = 0; h < kT / 8; ++h) {     // quarters of 8 samples
+                        real v[16];
 #pragma unroll
-                        for (int q = 1; q < R; ++q) { sr += qr[q]; si += qi[q]; }
-                        acc[2 * t] = sr; acc[2 * t + 1] = si;
-                        if (t + 1 < kT) {
+                        for (int b = 0; b < 8; b += M) {
+                            // sample t: the sum of the spins; samples t + m:
+                            // the sum of the spins times z^m, as
+                            // multiply-accumulates
+                            const int t = 8 * h + b;
+                            real sr = qr[0], si = qi[0];
 #pragma unroll
-                            for (int q = 0; q < R; ++q) {
-                                const real a_ = qr[q], b_ = qi[q];
-                                qr[q] = a_ * zr[q] - b_ * zi[q];
-                                qi[q] = a_ * zi[q] + b_ * zr[q];
+                            for (int q = 1; q < R; ++q) { sr += qr[q]; si += qi[q]; }
+                            v[2 * b] = sr; v[2 * b + 1] = si;
+#pragma unroll
+                            for (int m = 1; m < M; ++m) {
+                                real ur = qr[0] * zr[0][m - 1], ui = qr[0] * zi[0][m - 1];
+                                ur = fma(-qi[0], zi[0][m - 1], ur);
+                                ui = fma(qi[0], zr[0][m - 1], ui);
+#pragma unroll
+                                for (int q = 1; q < R; ++q) {
+                                    ur = fma(qr[q], zr[q][m - 1], ur);
+                                    ur = fma(-qi[q], zi[q][m - 1], ur);
+                                    ui = fma(qr[q], zi[q][m - 1], ui);
+                                    ui = fma(qi[q], zr[q][m - 1], ui);
+                                }
+                                v[2 * (b + m)] = ur; v[2 * (b + m) + 1] = ui;
+                            }
+                            if (t + M < kT) {
+#pragma unroll
+                                for (int q = 0; q < R; ++q) {
+                                    const real a_ = qr[q], b_ = qi[q];
+                                    qr[q] = a_ * zr[q][M - 1] - b_ * zi[q][M - 1];
+                                    qi[q] = a_ * zi[q][M - 1] + b_ * zr[q][M - 1];
+                                }
                             }
                         }
+                        quarter_reduce(v, lane);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) red[4 * h + i] = v[i];
                     }
 #pragma unroll
                     for (int q = 0; q < R; ++q) {     // advance G chunks from the anchor
+                        real w_r, w_i;
+                        if constexpr (G > 1) {
+                            const int ln = ((wave / G) * G + q / S) * 64 + lane, ss = q % S;
+                            w_r = s_stepf[ss][4][ln]; w_i = s_stepf[ss][5][ln];
+                        } else {
+                            w_r = Wr[q]; w_i = Wi[q];
+                        }
                         const real a_ = pr[q], b_ = pi[q];
-                        pr[q] = a_ * Wr[q] - b_ * Wi[q];
-                        pi[q] = a_ * Wi[q] + b_ * Wr[q];
+                        pr[q] = a_ * w_r - b_ * w_i;
+                        pi[q] = a_ * w_i + b_ * w_r;
                     }
-                    const real v = wave_reduce64(acc, lane);
-                    if (j * kT + (lane >> 1) < n) partial_c[2 * (int64_t)(aux + j * kT) + lane] = v;
+                    const real v = reduce16(red, lane);
+                    if (j * kT + smp_of_lane < n)
+                        partial_c[2 * (int64_t)(aux + j * kT + smp_of_lane) + (lane & 1)] = v;
                 }
                 }   // coil passes
             }
@@ -725,9 +876,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     }
 }
 
+// Waves per SIMD the register allocation is held to: two for FP32 with up
+// to 2 spins per lane (the readout is tuned to fit 256 registers, and a
+// second wave hides the latency of its LDS and transcendental operations),
+// else whatever the code needs.
+template <typename real, int S>
+struct StepOccupancy {
+    static constexpr int kWavesPerEU = (std::is_same<real, float>::value && S <= 2) ? 2 : 1;
+};
+
 // Workgroup b runs tile b % n_tiles as readout replica b / n_tiles.
 template <typename real, int S>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S>::kWavesPerEU)))
+void step_kernel(StepArgs a) {
     const int64_t b = blockIdx.x;
     step_body<real, S>(a, b % a.n_tiles, (int)(b / a.n_tiles));
 }
@@ -739,8 +900,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
 // item writes only its own rows and samples, so which workgroup runs it
 // never changes a result.
 template <typename real, int S>
-__global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req,
-                                                            int64_t total, unsigned long long* counter) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S>::kWavesPerEU)))
+void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_t total,
+                       unsigned long long* counter) {
     __shared__ unsigned long long s_item;
     for (;;) {
         __syncthreads();                     // every wave is done reading s_item
