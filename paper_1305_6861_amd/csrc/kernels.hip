@@ -440,7 +440,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     // readout step factors (z, z^32, z^(32 G), z^2 .. z^M) of every spin of
     // the tile for the (mu, tau) of the last ADC operation, written by the
     // spin's own lane and read by the lanes of its wave group
-    __shared__ real s_stepf[S][NF][kBlock];
+    __shared__ __align__(16) real s_stepf[S][NF][kBlock];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
     // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
@@ -593,10 +593,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
             } else if (kind == OP_ADCT) {
                 // Readout at tabulated instants (non-uniform trajectories):
                 // every sample is evaluated directly from the anchors,
-                //   p_s = Mxy_a E2(t_s) exp(-j 2 pi (k_s . x + dw t_s / 2 pi)),
-                // with the phase in FP64 from the absolute (k_s, t_s) rows.
-                // Each wave sums its own spins over 32-sample chunks; a wave
-                // group's waves add their chunk sums in LDS in wave order.
+                //   p_s = Mxy_a E2(t_s) exp(-j 2 pi (k_s . x + dw t_s / 2 pi)).
+                // FP64 evaluates the phase from the absolute (k_s, t_s) rows.
+                // FP32 splits each 32-sample chunk into blocks of 8: a block's
+                // first row gives every spin an FP64 phase and decay, and
+                // the block's samples add FP32 offsets (k_s - k_b, t_s - t_b)
+                // that the workgroup stages in LDS once per chunk; the
+                // offsets stay small, so FP32 keeps the phase to ~1e-7 of a
+                // revolution.  Each wave sums its own spins over a chunk; a
+                // wave group's waves add their chunk sums in LDS in wave order.
                 if (a.n_replicas > 1 && (adc_seen++ % a.n_replicas) != rep) continue;
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
@@ -606,6 +611,20 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 const double* table = a.traj + 4 * row0;
                 const int n_chunks = (n + kT - 1) / kT;
                 real* red = &s_x[0][0][0][0];         // G x 64 chunk sums (s_x is free here)
+                // FP32 staging of a chunk's rows in the step-factor area, whose
+                // cached factors are then no longer valid
+                constexpr int kTB = 8;                 // samples per FP64-anchored block
+                float4* s_trow = reinterpret_cast<float4*>(&s_stepf[0][0][0]);
+                double* s_tanc = reinterpret_cast<double*>(s_trow + kT);   // [kT / kTB][4]
+                static_assert(sizeof(float4) * kT + sizeof(double) * 4 * (kT / kTB) <= sizeof(s_stepf),
+                              "trajectory staging fits the step-factor area");
+                step_valid = false;
+                float dwf[S], r2l[S];                 // dw / 2 pi and log2(e) / T2 in FP32
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    dwf[s] = (float)((double)sp.dw[s] * kInv2Pi);
+                    r2l[s] = (float)(sp.r2[s] * kLog2e);
+                }
                 const int n_passes = a.n_coils > 0 ? a.n_coils : 1;
                 for (int coil = 0; coil < n_passes; ++coil) {
                     real wr[S], wi[S];               // coil-weighted anchors
@@ -625,26 +644,81 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     }
                     real* partial_c = partial + coil * a.coil_stride;
                     for (int j = 0; j < n_chunks; ++j) {
-                        real acc[2 * kT];
+                        real v;
+                        int smp_lane;                // chunk sample whose component lane & 1 this lane ends with
+                        if constexpr (std::is_same<real, float>::value) {
+                            static_assert(kTB == 8, "a block is one butterfly quarter");
+                            __syncthreads();         // earlier readers of the staging area are done
+                            if (tid < kT) {          // rows past n are never stored
+                                const double* row = table + 4 * min(j * kT + tid, n - 1);
+                                const double* blk_row = table + 4 * min(j * kT + (tid & ~(kTB - 1)), n - 1);
+                                s_trow[tid] = make_float4((float)(row[0] - blk_row[0]), (float)(row[1] - blk_row[1]),
+                                                          (float)(row[2] - blk_row[2]), (float)(row[3] - blk_row[3]));
+                                if ((tid & (kTB - 1)) == 0) {
 #pragma unroll
-                        for (int t = 0; t < kT; ++t) {
-                            const int smp = min(j * kT + t, n - 1);   // rows past n are never stored
-                            const double* row = table + 4 * smp;
-                            const double kx = row[0], ky = row[1], kz = row[2], tt = row[3];
-                            real sr = 0, si = 0;
-#pragma unroll
-                            for (int s = 0; s < S; ++s) {
-                                const double ph = fma(kx, (double)sp.x[s], fma(ky, (double)sp.y[s],
-                                                  fma(kz, (double)sp.z[s], (double)sp.dw[s] * kInv2Pi * tt)));
-                                real c, sn;
-                                Math<real>::cis(ph, c, sn);
-                                const real e2 = Math<real>::expneg(tt, sp.r2[s]);
-                                sr += e2 * fma(wr[s], c, wi[s] * sn);
-                                si += e2 * fma(wi[s], c, -wr[s] * sn);
+                                    for (int c = 0; c < 4; ++c) s_tanc[(tid / kTB) * 4 + c] = blk_row[c];
+                                }
                             }
-                            acc[2 * t] = sr; acc[2 * t + 1] = si;
+                            __syncthreads();
+                            float red16[16];
+#pragma unroll
+                            for (int b = 0; b < kT / kTB; ++b) {
+                                const double kb[3] = {s_tanc[b * 4], s_tanc[b * 4 + 1], s_tanc[b * 4 + 2]};
+                                const double tb = s_tanc[b * 4 + 3];
+                                float c0[S], br[S], bi[S];   // block phase, weighted magnetisation
+#pragma unroll
+                                for (int s = 0; s < S; ++s) {
+                                    const double ph = phase_rev(kb, tb, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
+                                    c0[s] = (float)(ph - rint(ph));
+                                    const float eb = Math<float>::expneg(tb, sp.r2[s]);
+                                    br[s] = eb * wr[s]; bi[s] = eb * wi[s];
+                                }
+                                float q[16];
+#pragma unroll
+                                for (int t = 0; t < kTB; ++t) {
+                                    const float4 d = s_trow[b * kTB + t];
+                                    float sr = 0, si = 0;
+#pragma unroll
+                                    for (int s = 0; s < S; ++s) {
+                                        const float f = c0[s] + fmaf(d.x, sp.x[s], fmaf(d.y, sp.y[s],
+                                                                fmaf(d.z, sp.z[s], dwf[s] * d.w)));
+                                        const float c = __builtin_amdgcn_cosf(f);
+                                        const float sn = __builtin_amdgcn_sinf(f);
+                                        const float ed = __builtin_amdgcn_exp2f(-d.w * r2l[s]);
+                                        sr = fmaf(ed, fmaf(br[s], c, bi[s] * sn), sr);
+                                        si = fmaf(ed, fmaf(bi[s], c, -br[s] * sn), si);
+                                    }
+                                    q[2 * t] = sr; q[2 * t + 1] = si;
+                                }
+                                quarter_reduce(q, lane);
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) red16[4 * b + i] = q[i];
+                            }
+                            v = reduce16(red16, lane);
+                            smp_lane = readout_sample_of_lane(lane);
+                        } else {
+                            real acc[2 * kT];
+#pragma unroll
+                            for (int t = 0; t < kT; ++t) {
+                                const int smp = min(j * kT + t, n - 1);   // rows past n are never stored
+                                const double* row = table + 4 * smp;
+                                const double kx = row[0], ky = row[1], kz = row[2], tt = row[3];
+                                real sr = 0, si = 0;
+#pragma unroll
+                                for (int s = 0; s < S; ++s) {
+                                    const double ph = fma(kx, (double)sp.x[s], fma(ky, (double)sp.y[s],
+                                                      fma(kz, (double)sp.z[s], (double)sp.dw[s] * kInv2Pi * tt)));
+                                    real c, sn;
+                                    Math<real>::cis(ph, c, sn);
+                                    const real e2 = Math<real>::expneg(tt, sp.r2[s]);
+                                    sr += e2 * fma(wr[s], c, wi[s] * sn);
+                                    si += e2 * fma(wi[s], c, -wr[s] * sn);
+                                }
+                                acc[2 * t] = sr; acc[2 * t + 1] = si;
+                            }
+                            v = wave_reduce64(acc, lane);
+                            smp_lane = lane >> 1;
                         }
-                        real v = wave_reduce64(acc, lane);
                         if constexpr (G > 1) {
                             __syncthreads();             // earlier readers of red are done
                             red[wave * 64 + lane] = v;
@@ -655,9 +729,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                 for (int g = 1; g < G; ++g) v += red[(wave + g) * 64 + lane];
                             }
                         }
-                        if (wg == 0 && j * kT + (lane >> 1) < n) partial_c[2 * (int64_t)(aux + j * kT) + lane] = v;
+                        if (wg == 0 && j * kT + smp_lane < n)
+                            partial_c[2 * (int64_t)(aux + j * kT + smp_lane) + (lane & 1)] = v;
                     }
                 }
+                __syncthreads();                     // the staging area is free again
             } else if (kind == OP_ADC) {
                 // A readout changes no spin state, so replicas of this tile
                 // share the slice's readouts round-robin and skip the others.
