@@ -62,6 +62,11 @@ template <typename real> struct ReadoutBlock { static constexpr int M = 4; };
 template <> struct ReadoutBlock<double> { static constexpr int M = 1; };
 static_assert(kT % ReadoutBlock<float>::M == 0, "a chunk holds whole readout blocks");
 
+// 16-byte LDS vectors of the readout step factors
+template <typename real> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int V = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int V = 2; };
+
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 
@@ -245,6 +250,19 @@ struct ReadoutShare {
     static constexpr int G = S <= 2 ? 4 : (S == 4 ? 2 : 1);
 };
 
+// Readout step factors of a spin, as complex numbers c = 0 .. NC - 1:
+// z^(c + 1) for c < M (one sample to a block of M), then z^(32 g) for
+// g = 1 .. G - 1 (the chunk offsets of a wave group), then W = z^(32 G)
+// (the stride of a wave's chunks); NF reals, padded to whole LDS vectors.
+template <typename real, int S>
+struct StepFactors {
+    static constexpr int M = ReadoutBlock<real>::M;
+    static constexpr int G = ReadoutShare<S>::G;
+    static constexpr int V = Vec16<real>::V;
+    static constexpr int kZ = 0, kZg = M, kW = M + G - 1, NC = M + G;
+    static constexpr int NF = (2 * NC + V - 1) / V * V;
+};
+
 int64_t rows_per_block_of(int spins_per_lane) {
     switch (spins_per_lane) {
         case 1: return kWaves / ReadoutShare<1>::G;
@@ -342,8 +360,8 @@ __device__ __forceinline__ void step_delta(double c, double tau, double r2, real
 template <typename real, int S>
 constexpr size_t static_lds_bytes() {
     constexpr int G = ReadoutShare<S>::G;
-    constexpr int NF = 6 + 2 * (ReadoutBlock<real>::M - 1);
-    return sizeof(Op) * kOpChunk + sizeof(real) * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 2 * 64 +
+    constexpr int NF = StepFactors<real, S>::NF;
+    return sizeof(Op) * kOpChunk + sizeof(real) * 2 * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 64 * 2 +
            sizeof(real) * S * NF * kBlock;
 }
 
@@ -433,14 +451,19 @@ template <typename real, int S>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, const int rep) {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int R = G * S;                 // spins per lane inside readouts
-    constexpr int M = ReadoutBlock<real>::M;
-    constexpr int NF = 6 + 2 * (M - 1);      // step factors per spin (re, im pairs)
+    using SF = StepFactors<real, S>;
+    constexpr int M = SF::M;
+    constexpr int NF = SF::NF;               // step factors per spin (re, im pairs)
+    constexpr int V = SF::V;
+    using vec_t = typename Vec16<real>::type;
     __shared__ Op s_ops[kOpChunk];
-    __shared__ real s_x[G > 1 ? kWaves : 1][G > 1 ? S : 1][2][64];   // readout sample-0 values
-    // readout step factors (z, z^32, z^(32 G), z^2 .. z^M) of every spin of
-    // the tile for the (mu, tau) of the last ADC operation, written by the
-    // spin's own lane and read by the lanes of its wave group
-    __shared__ __align__(16) real s_stepf[S][NF][kBlock];
+    // readout sample-0 values (re, im) handed over inside wave groups, in two
+    // buffers used by alternate readout passes
+    __shared__ __align__(16) real s_x[2][G > 1 ? kWaves : 1][G > 1 ? S : 1][64][2];
+    // readout step factors of every spin of the tile for the (mu, tau) of
+    // the last ADC operation (StepFactors), written by the spin's own lane
+    // and read by the lanes of its wave group, one 16-byte vector per lane
+    __shared__ __align__(16) real s_stepf[S][NF / V][kBlock][V];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
     // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
@@ -484,6 +507,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     const int wg = wave % G;                 // position inside the wave group
     double step_mu[3] = {0.0, 0.0, 0.0}, step_tau = 0.0;
     int adc_seen = 0;                        // readouts met so far (replica split)
+    int x_pass = 0;                          // readout passes met so far (s_x buffer)
     bool step_valid = false;
     real* partial = reinterpret_cast<real*>(a.partial) +
                     (blk * (kWaves / G) + wave / G) * a.row_stride;
@@ -610,11 +634,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                                (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)row_u));
                 const double* table = a.traj + 4 * row0;
                 const int n_chunks = (n + kT - 1) / kT;
-                real* red = &s_x[0][0][0][0];         // G x 64 chunk sums (s_x is free here)
+                real* red = &s_x[0][0][0][0][0];      // G x 64 chunk sums (s_x is free here)
                 // FP32 staging of a chunk's rows in the step-factor area, whose
                 // cached factors are then no longer valid
                 constexpr int kTB = 8;                 // samples per FP64-anchored block
-                float4* s_trow = reinterpret_cast<float4*>(&s_stepf[0][0][0]);
+                float4* s_trow = reinterpret_cast<float4*>(&s_stepf[0][0][0][0]);
                 double* s_tanc = reinterpret_cast<double*>(s_trow + kT);   // [kT / kTB][4]
                 static_assert(sizeof(float4) * kT + sizeof(double) * 4 * (kT / kTB) <= sizeof(s_stepf),
                               "trajectory staging fits the step-factor area");
@@ -751,41 +775,44 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 // operation when (mu, tau) is unchanged.
                 const bool same_step = step_valid && mu[0] == step_mu[0] && mu[1] == step_mu[1] &&
                                        mu[2] == step_mu[2] && tau == step_tau;
-                // z, Z and W of spin s into f[0..5], z^2 .. z^M into f[6..]
-                // (re, im pairs), each from its own FP64 phase
+                // the step factors of spin s (StepFactors), each from its own
+                // FP64 phase
                 auto step_factors = [&](int s, real* f) {
-                    real c, sn;
                     const double ph = phase_rev(mu, tau, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]);
-                    real ez = Math<real>::expneg(tau, sp.r2[s]);
-                    Math<real>::cis(ph, c, sn);
-                    f[0] = ez * c; f[1] = -ez * sn;
-                    real eZ = Math<real>::expneg(tau * kT, sp.r2[s]);
-                    Math<real>::cis(ph * kT, c, sn);
-                    f[2] = eZ * c; f[3] = -eZ * sn;
-                    if constexpr (G > 1) {
-                        real eW = Math<real>::expneg(tau * (kT * G), sp.r2[s]);
-                        Math<real>::cis(ph * (kT * G), c, sn);
-                        f[4] = eW * c; f[5] = -eW * sn;
-                    } else {
-                        f[4] = f[2]; f[5] = f[3];
-                    }
+                    auto put = [&](int c, double mult) {
+                        real co, sn;
+                        const real e = Math<real>::expneg(tau * mult, sp.r2[s]);
+                        Math<real>::cis(ph * mult, co, sn);
+                        f[2 * c] = e * co; f[2 * c + 1] = -e * sn;
+                    };
 #pragma unroll
-                    for (int m = 2; m <= M; ++m) {
-                        real em = Math<real>::expneg(tau * m, sp.r2[s]);
-                        Math<real>::cis(ph * m, c, sn);
-                        f[6 + 2 * (m - 2)] = em * c; f[7 + 2 * (m - 2)] = -em * sn;
-                    }
+                    for (int m = 1; m <= M; ++m) put(SF::kZ + m - 1, (double)m);
+#pragma unroll
+                    for (int g = 1; g < G; ++g) put(SF::kZg + g - 1, (double)(kT * g));
+                    put(SF::kW, (double)(kT * G));
+#pragma unroll
+                    for (int k = 2 * SF::NC; k < NF; ++k) f[k] = 0;
                 };
-                // other waves of the group may still read the factors and
-                // sample-0 values of the previous readout
-                if constexpr (G > 1) __syncthreads();
+                // complex factor c of the spin in slot ss of lane ln
+                auto factor = [&](int ss, int ln, int c, real& re, real& im) {
+                    re = s_stepf[ss][(2 * c) / V][ln][(2 * c) % V];
+                    im = s_stepf[ss][(2 * c) / V][ln][(2 * c) % V + 1];
+                };
                 if (!same_step) {
+                    // other waves of the group may still read the factors of
+                    // the previous readout
+                    if constexpr (G > 1) __syncthreads();
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         real f[NF];
                         step_factors(s, f);
 #pragma unroll
-                        for (int k = 0; k < NF; ++k) s_stepf[s][k][tid] = f[k];
+                        for (int v = 0; v < NF / V; ++v) {
+                            vec_t w;
+                            if constexpr (V == 4) w = make_float4(f[4 * v], f[4 * v + 1], f[4 * v + 2], f[4 * v + 3]);
+                            else w = make_double2(f[2 * v], f[2 * v + 1]);
+                            *reinterpret_cast<vec_t*>(&s_stepf[s][v][tid][0]) = w;
+                        }
                     }
                     step_mu[0] = mu[0]; step_mu[1] = mu[1]; step_mu[2] = mu[2];
                     step_tau = tau;
@@ -824,33 +851,33 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     }
                 }
                 real* partial_c = partial + coil * a.coil_stride;
-                // the wave group's G * S spins (LDS exchange when G > 1);
-                // zr/zi[q][m - 1] = z^m of spin q for m = 1 .. M
-                // (W, the stride of G chunks, is read from LDS when it is used
-                // if G > 1, to keep it off the register budget)
-                real pr[R], pi[R], zr[R][M], zi[R][M], Wr[G > 1 ? 1 : R], Wi[G > 1 ? 1 : R];
+                // the wave group's G * S spins (LDS hand-over when G > 1);
+                // zr/zi[q][m - 1] = z^m of spin q for m = 1 .. M (W, the
+                // stride of G chunks, is read from LDS when it is used)
+                real pr[R], pi[R], zr[R][M], zi[R][M];
+                const int w0 = (wave / G) * G;
                 if constexpr (G > 1) {
-                    if (coil > 0) __syncthreads();   // earlier readers of s_x are done
+                    // Two buffers for alternate passes: the writers of this
+                    // pass's buffer have passed the barrier below of the
+                    // previous pass, which every reader of this buffer's
+                    // previous contents had reached after reading it.
+                    const int xb = x_pass++ & 1;
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        s_x[wave][s][0][lane] = ap[s][0];
-                        s_x[wave][s][1][lane] = ap[s][1];
+                        s_x[xb][wave][s][lane][0] = ap[s][0];
+                        s_x[xb][wave][s][lane][1] = ap[s][1];
                     }
                     __syncthreads();
-                    const int w0 = (wave / G) * G;
 #pragma unroll
                     for (int q = 0; q < R; ++q) {
                         const int sw = w0 + q / S, ss = q % S;
                         const int ln = sw * 64 + lane;
-                        real p_r = s_x[sw][ss][0][lane], p_i = s_x[sw][ss][1][lane];
-                        const real Zr_ = s_stepf[ss][2][ln], Zi_ = s_stepf[ss][3][ln];
-                        zr[q][0] = s_stepf[ss][0][ln]; zi[q][0] = s_stepf[ss][1][ln];
+                        real p_r = s_x[xb][sw][ss][lane][0], p_i = s_x[xb][sw][ss][lane][1];
 #pragma unroll
-                        for (int m = 1; m < M; ++m) {
-                            zr[q][m] = s_stepf[ss][6 + 2 * (m - 1)][ln];
-                            zi[q][m] = s_stepf[ss][7 + 2 * (m - 1)][ln];
-                        }
-                        for (int k = 0; k < wg; ++k) {   // start at chunk wg: p0 Z^wg
+                        for (int m = 0; m < M; ++m) factor(ss, ln, SF::kZ + m, zr[q][m], zi[q][m]);
+                        if (wg > 0) {            // start at chunk wg: p0 z^(32 wg)
+                            real Zr_, Zi_;
+                            factor(ss, ln, SF::kZg + wg - 1, Zr_, Zi_);
                             const real t = p_r * Zr_ - p_i * Zi_;
                             p_i = p_r * Zi_ + p_i * Zr_;
                             p_r = t;
@@ -862,13 +889,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     for (int q = 0; q < R; ++q) {
                         const int s = q % S;
                         pr[q] = ap[s][0]; pi[q] = ap[s][1];
-                        zr[q][0] = s_stepf[s][0][tid]; zi[q][0] = s_stepf[s][1][tid];
 #pragma unroll
-                        for (int m = 1; m < M; ++m) {
-                            zr[q][m] = s_stepf[s][6 + 2 * (m - 1)][tid];
-                            zi[q][m] = s_stepf[s][7 + 2 * (m - 1)][tid];
-                        }
-                        Wr[q] = s_stepf[s][4][tid]; Wi[q] = s_stepf[s][5][tid];
+                        for (int m = 0; m < M; ++m) factor(s, tid, SF::kZ + m, zr[q][m], zi[q][m]);
                     }
                 }
                 const int n_chunks = (n + kT - 1) / kT;
@@ -921,12 +943,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 #pragma unroll
                     for (int q = 0; q < R; ++q) {     // advance G chunks from the anchor
                         real w_r, w_i;
-                        if constexpr (G > 1) {
-                            const int ln = ((wave / G) * G + q / S) * 64 + lane, ss = q % S;
-                            w_r = s_stepf[ss][4][ln]; w_i = s_stepf[ss][5][ln];
-                        } else {
-                            w_r = Wr[q]; w_i = Wi[q];
-                        }
+                        factor(q % S, (w0 + q / S) * 64 + lane, SF::kW, w_r, w_i);
                         const real a_ = pr[q], b_ = pi[q];
                         pr[q] = a_ * w_r - b_ * w_i;
                         pi[q] = a_ * w_i + b_ * w_r;
