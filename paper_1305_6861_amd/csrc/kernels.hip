@@ -766,13 +766,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
                 const double tau = uniform(op.u.adc.tau);
                 const double mu[3] = {uniform(op.u.adc.mu[0]), uniform(op.u.adc.mu[1]), uniform(op.u.adc.mu[2])};
-                // this wave's spins: sample 0 (p0), one sample step (z), one
-                // chunk (Z = z^32) and one group stride (W = z^(32 G)), all
-                // from FP64 phases
-                // Step factors depend only on (mu, tau) and the spin; successive
-                // readouts of a sequence usually share them, so they are kept
-                // (in LDS, off the register budget) from the previous ADC
-                // operation when (mu, tau) is unchanged.
+                // Per spin: the sample-0 value p0 and the step factors
+                // (StepFactors), all from FP64 phases.  Step factors depend
+                // only on (mu, tau) and the spin; successive readouts of a
+                // sequence usually share them, so they are kept (in LDS, off
+                // the register budget) from the previous ADC operation when
+                // (mu, tau) is unchanged.
                 const bool same_step = step_valid && mu[0] == step_mu[0] && mu[1] == step_mu[1] &&
                                        mu[2] == step_mu[2] && tau == step_tau;
                 // the step factors of spin s (StepFactors), each from its own
