@@ -67,6 +67,16 @@ template <typename real> struct Vec16;
 template <> struct Vec16<float> { using type = float4; static constexpr int V = 4; };
 template <> struct Vec16<double> { using type = double2; static constexpr int V = 2; };
 
+// A device pointer of StepArgs as a pointer into global memory.  The batched
+// kernel reads its arguments from a request record, and the compiler cannot
+// tell where such pointers point: without this it accesses them with flat
+// instructions, and an outstanding flat store also holds up every later wait
+// for LDS data.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 
@@ -362,7 +372,7 @@ constexpr size_t static_lds_bytes() {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int NF = StepFactors<real, S>::NF;
     return sizeof(Op) * kOpChunk + sizeof(real) * 2 * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 64 * 2 +
-           sizeof(real) * S * NF * kBlock;
+           sizeof(real) * S * NF * kBlock + sizeof(real) * (G > 1 ? kWaves : 1) * 64;
 }
 
 // Shaped-pulse propagator of every spin of this lane (see ps_ops.h): the
@@ -464,6 +474,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     // the last ADC operation (StepFactors), written by the spin's own lane
     // and read by the lanes of its wave group, one 16-byte vector per lane
     __shared__ __align__(16) real s_stepf[S][NF / V][kBlock][V];
+    __shared__ real s_red[G > 1 ? kWaves : 1][64];   // chunk sums of waves sharing a chunk
     extern __shared__ __align__(16) unsigned char s_dyn[];
     double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
     // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
@@ -481,12 +492,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     for (int s = 0; s < S; ++s) {
         const int64_t i = base + s * 64 + lane;
         if (i < a.n_spins) {
-            sp.x[s] = a.x[i]; sp.y[s] = a.y[i]; sp.z[s] = a.z[i];
-            sp.m0[s] = a.m0[i]; sp.dw[s] = a.dw[i];
-            sp.r1[s] = 1.0 / (double)a.t1[i];
-            sp.r2[s] = 1.0 / (double)a.t2[i];
+            sp.x[s] = gmem(a.x)[i]; sp.y[s] = gmem(a.y)[i]; sp.z[s] = gmem(a.z)[i];
+            sp.m0[s] = gmem(a.m0)[i]; sp.dw[s] = gmem(a.dw)[i];
+            sp.r1[s] = 1.0 / (double)gmem(a.t1)[i];
+            sp.r2[s] = 1.0 / (double)gmem(a.t2)[i];
             if (a.load_state) {
-                const real* st = reinterpret_cast<const real*>(a.state);
+                const auto st = gmem(reinterpret_cast<const real*>(a.state));
                 sp.ar[s] = st[i]; sp.ai[s] = st[a.n_spins + i]; sp.az[s] = st[2 * a.n_spins + i];
             } else {
                 sp.ar[s] = 0; sp.ai[s] = 0; sp.az[s] = (real)sp.m0[s];
@@ -500,7 +511,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 
     // shaped-pulse rotation rows -> LDS (made visible by the first barrier below)
     {
-        const double* rows = reinterpret_cast<const double*>(a.rows);
+        const auto rows = gmem(reinterpret_cast<const double*>(a.rows));
         for (int i = tid; i < a.n_shape_rows * 9; i += kBlock) s_rows[i] = rows[i];
     }
 
@@ -509,16 +520,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     int adc_seen = 0;                        // readouts met so far (replica split)
     int x_pass = 0;                          // readout passes met so far (s_x buffer)
     bool step_valid = false;
-    real* partial = reinterpret_cast<real*>(a.partial) +
+    const auto partial = gmem(reinterpret_cast<real*>(a.partial)) +
                     (blk * (kWaves / G) + wave / G) * a.row_stride;
 
     for (int c0 = 0; c0 < a.n_ops; c0 += kOpChunk) {
         const int cn = min(kOpChunk, a.n_ops - c0);
         __syncthreads();
         {
-            const uint4* src = reinterpret_cast<const uint4*>(a.ops + c0);
+            const auto src = gmem(reinterpret_cast<const uint32_t*>(a.ops + c0));
             uint4* dst = reinterpret_cast<uint4*>(s_ops);
-            for (int i = tid; i < cn * 8; i += kBlock) dst[i] = src[i];
+            for (int i = tid; i < cn * 8; i += kBlock)
+                dst[i] = make_uint4(src[4 * i], src[4 * i + 1], src[4 * i + 2], src[4 * i + 3]);
         }
         __syncthreads();
 
@@ -542,7 +554,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 if (rep != 0) continue;
                 real mx[S], my[S], mz[S];
                 evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
-                real* out = reinterpret_cast<real*>(a.snaps) +
+                const auto out = gmem(reinterpret_cast<real*>(a.snaps)) +
                             (int64_t)__builtin_amdgcn_readfirstlane(op.aux) * 3 * a.n_spins;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -632,7 +644,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 const uint64_t row_u = op.u.tab.row;
                 const int64_t row0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(row_u >> 32)) << 32) |
                                                (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)row_u));
-                const double* table = a.traj + 4 * row0;
+                const auto table = gmem(a.traj) + 4 * row0;
                 const int n_chunks = (n + kT - 1) / kT;
                 real* red = &s_x[0][0][0][0][0];      // G x 64 chunk sums (s_x is free here)
                 // FP32 staging of a chunk's rows in the step-factor area, whose
@@ -659,14 +671,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                             const int64_t i = base + s * 64 + lane;
                             real sx = 0, sy = 0;
                             if (i < a.n_spins) {
-                                sx = (real)a.s_x[coil * a.n_spins + i];
-                                sy = (real)a.s_y[coil * a.n_spins + i];
+                                sx = (real)gmem(a.s_x)[coil * a.n_spins + i];
+                                sy = (real)gmem(a.s_y)[coil * a.n_spins + i];
                             }
                             wr[s] = fma(sx, sp.ar[s], sy * sp.ai[s]);
                             wi[s] = fma(sx, sp.ai[s], -sy * sp.ar[s]);
                         }
                     }
-                    real* partial_c = partial + coil * a.coil_stride;
+                    const auto partial_c = partial + coil * a.coil_stride;
                     for (int j = 0; j < n_chunks; ++j) {
                         real v;
                         int smp_lane;                // chunk sample whose component lane & 1 this lane ends with
@@ -674,8 +686,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                             static_assert(kTB == 8, "a block is one butterfly quarter");
                             __syncthreads();         // earlier readers of the staging area are done
                             if (tid < kT) {          // rows past n are never stored
-                                const double* row = table + 4 * min(j * kT + tid, n - 1);
-                                const double* blk_row = table + 4 * min(j * kT + (tid & ~(kTB - 1)), n - 1);
+                                const auto row = table + 4 * min(j * kT + tid, n - 1);
+                                const auto blk_row = table + 4 * min(j * kT + (tid & ~(kTB - 1)), n - 1);
                                 s_trow[tid] = make_float4((float)(row[0] - blk_row[0]), (float)(row[1] - blk_row[1]),
                                                           (float)(row[2] - blk_row[2]), (float)(row[3] - blk_row[3]));
                                 if ((tid & (kTB - 1)) == 0) {
@@ -725,7 +737,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 #pragma unroll
                             for (int t = 0; t < kT; ++t) {
                                 const int smp = min(j * kT + t, n - 1);   // rows past n are never stored
-                                const double* row = table + 4 * smp;
+                                const auto row = table + 4 * smp;
                                 const double kx = row[0], ky = row[1], kz = row[2], tt = row[3];
                                 real sr = 0, si = 0;
 #pragma unroll
@@ -839,8 +851,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         const int64_t i = base + s * 64 + lane;
                         real sx = 0, sy = 0;
                         if (i < a.n_spins) {
-                            sx = (real)a.s_x[coil * a.n_spins + i];
-                            sy = (real)a.s_y[coil * a.n_spins + i];
+                            sx = (real)gmem(a.s_x)[coil * a.n_spins + i];
+                            sy = (real)gmem(a.s_y)[coil * a.n_spins + i];
                         }
                         ap[s][0] = fma(sx, p0r[s], sy * p0i[s]);
                         ap[s][1] = fma(sx, p0i[s], -sy * p0r[s]);
@@ -849,107 +861,139 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         ap[s][1] = p0i[s];
                     }
                 }
-                real* partial_c = partial + coil * a.coil_stride;
-                // the wave group's G * S spins (LDS hand-over when G > 1);
-                // zr/zi[q][m - 1] = z^m of spin q for m = 1 .. M (W, the
-                // stride of G chunks, is read from LDS when it is used)
-                real pr[R], pi[R], zr[R][M], zi[R][M];
+                const auto partial_c = partial + coil * a.coil_stride;
+                // the wave group's G * S spins (LDS hand-over when G > 1)
                 const int w0 = (wave / G) * G;
+                const int n_chunks = (n + kT - 1) / kT;
+                const int smp_of_lane = readout_sample_of_lane(lane);
+                int xb = 0;
                 if constexpr (G > 1) {
                     // Two buffers for alternate passes: the writers of this
                     // pass's buffer have passed the barrier below of the
                     // previous pass, which every reader of this buffer's
                     // previous contents had reached after reading it.
-                    const int xb = x_pass++ & 1;
+                    xb = x_pass++ & 1;
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         s_x[xb][wave][s][lane][0] = ap[s][0];
                         s_x[xb][wave][s][lane][1] = ap[s][1];
                     }
                     __syncthreads();
+                }
+                // A readout of fewer chunks than the group has waves would
+                // leave waves idle: then n_share = G / n_chunks waves share
+                // each chunk, each taking 1 / n_share of the group's spins,
+                // and add their chunk sums in LDS in wave order (one chunk
+                // per wave).
+                int n_share = 1;
+                if constexpr (G > 1) {
+                    if (4 * n_chunks <= G) n_share = 4;
+                    else if (2 * n_chunks <= G) n_share = 2;
+                }
+                auto run = [&](auto p_c) {
+                    constexpr int P = decltype(p_c)::value;     // waves per chunk
+                    constexpr int RS = R / P;                    // spins per lane in this readout
+                    const int sub = wg % P;                      // which RS of the group's spins
+                    const int j0 = wg / P;                       // first chunk
+                    // zr/zi[q][m - 1] = z^m of spin q for m = 1 .. M (W, the
+                    // stride of G chunks, is read from LDS when it is used)
+                    real pr[RS], pi[RS], zr[RS][M], zi[RS][M];
 #pragma unroll
-                    for (int q = 0; q < R; ++q) {
-                        const int sw = w0 + q / S, ss = q % S;
+                    for (int q = 0; q < RS; ++q) {
+                        const int qq = sub * RS + q;
+                        const int sw = w0 + qq / S, ss = qq % S;
                         const int ln = sw * 64 + lane;
-                        real p_r = s_x[xb][sw][ss][lane][0], p_i = s_x[xb][sw][ss][lane][1];
+                        real p_r, p_i;
+                        if constexpr (G > 1) {
+                            p_r = s_x[xb][sw][ss][lane][0]; p_i = s_x[xb][sw][ss][lane][1];
+                        } else {
+                            p_r = ap[ss][0]; p_i = ap[ss][1];
+                        }
 #pragma unroll
                         for (int m = 0; m < M; ++m) factor(ss, ln, SF::kZ + m, zr[q][m], zi[q][m]);
-                        if (wg > 0) {            // start at chunk wg: p0 z^(32 wg)
+                        if (j0 > 0) {            // start at chunk j0: p0 z^(32 j0)
                             real Zr_, Zi_;
-                            factor(ss, ln, SF::kZg + wg - 1, Zr_, Zi_);
+                            factor(ss, ln, SF::kZg + j0 - 1, Zr_, Zi_);
                             const real t = p_r * Zr_ - p_i * Zi_;
                             p_i = p_r * Zi_ + p_i * Zr_;
                             p_r = t;
                         }
                         pr[q] = p_r; pi[q] = p_i;
                     }
-                } else {
+                    for (int j = j0; j < n_chunks; j += G / P) {
+                        real qr[RS], qi[RS];
 #pragma unroll
-                    for (int q = 0; q < R; ++q) {
-                        const int s = q % S;
-                        pr[q] = ap[s][0]; pi[q] = ap[s][1];
+                        for (int q = 0; q < RS; ++q) { qr[q] = pr[q]; qi[q] = pi[q]; }
+                        real red[16];
 #pragma unroll
-                        for (int m = 0; m < M; ++m) factor(s, tid, SF::kZ + m, zr[q][m], zi[q][m]);
-                    }
-                }
-                const int n_chunks = (n + kT - 1) / kT;
-                const int smp_of_lane = readout_sample_of_lane(lane);
-                for (int j = wg; j < n_chunks; j += G) {
-                    real qr[R], qi[R];
+                        for (int h = 0; h < kT / 8; ++h) {     // quarters of 8 samples
+                            real v[16];
 #pragma unroll
-                    for (int q = 0; q < R; ++q) { qr[q] = pr[q]; qi[q] = pi[q]; }
-                    real red[16];
+                            for (int b = 0; b < 8; b += M) {
+                                // sample t: the sum of the spins; samples
+                                // t + m: the sum of the spins times z^m, as
+                                // multiply-accumulates
+                                const int t = 8 * h + b;
+                                real sr = qr[0], si = qi[0];
 #pragma unroll
-                    for (int h = 0; h < kT / 8; ++h) {     // quarters of 8 samples
-                        real v[16];
+                                for (int q = 1; q < RS; ++q) { sr += qr[q]; si += qi[q]; }
+                                v[2 * b] = sr; v[2 * b + 1] = si;
 #pragma unroll
-                        for (int b = 0; b < 8; b += M) {
-                            // sample t: the sum of the spins; samples t + m:
-                            // the sum of the spins times z^m, as
-                            // multiply-accumulates
-                            const int t = 8 * h + b;
-                            real sr = qr[0], si = qi[0];
+                                for (int m = 1; m < M; ++m) {
+                                    real ur = qr[0] * zr[0][m - 1], ui = qr[0] * zi[0][m - 1];
+                                    ur = fma(-qi[0], zi[0][m - 1], ur);
+                                    ui = fma(qi[0], zr[0][m - 1], ui);
 #pragma unroll
-                            for (int q = 1; q < R; ++q) { sr += qr[q]; si += qi[q]; }
-                            v[2 * b] = sr; v[2 * b + 1] = si;
-#pragma unroll
-                            for (int m = 1; m < M; ++m) {
-                                real ur = qr[0] * zr[0][m - 1], ui = qr[0] * zi[0][m - 1];
-                                ur = fma(-qi[0], zi[0][m - 1], ur);
-                                ui = fma(qi[0], zr[0][m - 1], ui);
-#pragma unroll
-                                for (int q = 1; q < R; ++q) {
-                                    ur = fma(qr[q], zr[q][m - 1], ur);
-                                    ur = fma(-qi[q], zi[q][m - 1], ur);
-                                    ui = fma(qr[q], zi[q][m - 1], ui);
-                                    ui = fma(qi[q], zr[q][m - 1], ui);
+                                    for (int q = 1; q < RS; ++q) {
+                                        ur = fma(qr[q], zr[q][m - 1], ur);
+                                        ur = fma(-qi[q], zi[q][m - 1], ur);
+                                        ui = fma(qr[q], zi[q][m - 1], ui);
+                                        ui = fma(qi[q], zr[q][m - 1], ui);
+                                    }
+                                    v[2 * (b + m)] = ur; v[2 * (b + m) + 1] = ui;
                                 }
-                                v[2 * (b + m)] = ur; v[2 * (b + m) + 1] = ui;
+                                if (t + M < kT) {
+#pragma unroll
+                                    for (int q = 0; q < RS; ++q) {
+                                        const real a_ = qr[q], b_ = qi[q];
+                                        qr[q] = a_ * zr[q][M - 1] - b_ * zi[q][M - 1];
+                                        qi[q] = a_ * zi[q][M - 1] + b_ * zr[q][M - 1];
+                                    }
+                                }
                             }
-                            if (t + M < kT) {
+                            quarter_reduce(v, lane);
 #pragma unroll
-                                for (int q = 0; q < R; ++q) {
-                                    const real a_ = qr[q], b_ = qi[q];
-                                    qr[q] = a_ * zr[q][M - 1] - b_ * zi[q][M - 1];
-                                    qi[q] = a_ * zi[q][M - 1] + b_ * zr[q][M - 1];
-                                }
+                            for (int i = 0; i < 4; ++i) red[4 * h + i] = v[i];
+                        }
+                        if constexpr (P == 1) {
+#pragma unroll
+                            for (int q = 0; q < RS; ++q) {     // advance G chunks from the anchor
+                                real w_r, w_i;
+                                factor(q % S, (w0 + q / S) * 64 + lane, SF::kW, w_r, w_i);
+                                const real a_ = pr[q], b_ = pi[q];
+                                pr[q] = a_ * w_r - b_ * w_i;
+                                pi[q] = a_ * w_i + b_ * w_r;
                             }
                         }
-                        quarter_reduce(v, lane);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) red[4 * h + i] = v[i];
+                        real v = reduce16(red, lane);
+                        if constexpr (P > 1) {
+                            // every wave of the group runs exactly this one
+                            // chunk; the readers of s_red below are done
+                            // before they reach the next readout's barrier
+                            s_red[wave][lane] = v;
+                            __syncthreads();
+                            if (sub == 0)
+                                for (int k = 1; k < P; ++k) v += s_red[wave + k][lane];
+                        }
+                        if (sub == 0 && j * kT + smp_of_lane < n)
+                            partial_c[2 * (int64_t)(aux + j * kT + smp_of_lane) + (lane & 1)] = v;
                     }
-#pragma unroll
-                    for (int q = 0; q < R; ++q) {     // advance G chunks from the anchor
-                        real w_r, w_i;
-                        factor(q % S, (w0 + q / S) * 64 + lane, SF::kW, w_r, w_i);
-                        const real a_ = pr[q], b_ = pi[q];
-                        pr[q] = a_ * w_r - b_ * w_i;
-                        pi[q] = a_ * w_i + b_ * w_r;
-                    }
-                    const real v = reduce16(red, lane);
-                    if (j * kT + smp_of_lane < n)
-                        partial_c[2 * (int64_t)(aux + j * kT + smp_of_lane) + (lane & 1)] = v;
+                };
+                if (__builtin_expect(n_share == 1, 1)) {
+                    run(std::integral_constant<int, 1>());
+                } else if constexpr (G >= 2) {
+                    if (n_share == 2) run(std::integral_constant<int, 2>());
+                    else if constexpr (G >= 4) run(std::integral_constant<int, 4>());
                 }
                 }   // coil passes
             }
@@ -957,7 +1001,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     }
 
     if (a.save_state && rep == 0) {
-        real* st = reinterpret_cast<real*>(a.state);
+        const auto st = gmem(reinterpret_cast<real*>(a.state));
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t i = base + s * 64 + lane;
@@ -1059,11 +1103,11 @@ __global__ void batch_finalize_pass1(const FinDesc* __restrict__ d, int32_t n) {
     const int64_t g = local / jt;
     const int64_t j = (local % jt) * 256 + threadIdx.x;
     if (j >= f.n_vals) return;
-    const real* partial = reinterpret_cast<const real*>(f.partial);
+    const auto partial = gmem(reinterpret_cast<const real*>(f.partial));
     const int64_t r0 = g * kRowGroup, r1 = min(f.n_rows, r0 + kRowGroup);
     double s = 0.0;
     for (int64_t r = r0; r < r1; ++r) s += (double)partial[r * f.row_stride + j];
-    if (f.n_groups > 1) f.mid[g * f.n_vals + j] = s; else f.out[j] = s;
+    if (f.n_groups > 1) gmem(f.mid)[g * f.n_vals + j] = s; else gmem(f.out)[j] = s;
 }
 
 __global__ void batch_finalize_pass2(const FinDesc* __restrict__ d, int32_t n) {
@@ -1071,9 +1115,10 @@ __global__ void batch_finalize_pass2(const FinDesc* __restrict__ d, int32_t n) {
     const FinDesc& f = d[find_desc(d, n, t, true)];
     const int64_t j = (t - f.tile_begin2) * 256 + threadIdx.x;
     if (f.n_groups <= 1 || j >= f.n_vals) return;
+    const auto mid = gmem(f.mid);
     double s = 0.0;
-    for (int64_t g = 0; g < f.n_groups; ++g) s += f.mid[g * f.n_vals + j];
-    f.out[j] = s;
+    for (int64_t g = 0; g < f.n_groups; ++g) s += mid[g * f.n_vals + j];
+    gmem(f.out)[j] = s;
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
