@@ -148,6 +148,20 @@ def test_ragged_sample_counts(ctx32, ctx64, n_adc):
     check(ctx64, obj, seq, TOL64, ref=ref, label=f"adc{n_adc}/fp64")
 
 
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+def test_short_readouts_every_tiling(ps, S):
+    """Readouts of 1, 2 and 3 chunks of 32 samples (one chunk ragged): with
+    fewer chunks than a wave group has waves, the waves share each chunk's
+    spins and add their sums in LDS; wave groups of 4, 4, 2 and 1 waves."""
+    obj = random_spins(1500, seed=5)
+    seq = Sequence("short")
+    for n_adc in (20, 64, 70):
+        seq.add(1e-3, m=(-n_adc / 2, 3, 0), alpha=0.6, phase=0.2)
+        seq.add(n_adc * 1e-5, m=(n_adc * 1.1, 0, 0), n_adc=n_adc, flags=SPOIL)
+    with ps.Context(precision=32, spins_per_lane=S) as ctx:
+        check(ctx, obj, seq, TOL32, label=f"short readouts S={S}")
+
+
 def test_long_readout_and_time_slicing(ps):
     """A 5000-sample readout forced through many time slices (small partial
     buffer).  A slice boundary inside a readout re-anchors the recurrence from
