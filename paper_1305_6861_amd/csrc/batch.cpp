@@ -12,9 +12,11 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/parspin.h"
@@ -100,14 +102,23 @@ size_t ReqPlan::footprint() const {
     return device_bytes() + (size_t)obj.n_spins * 7 * sizeof(float) + (size_t)prog.n_samples * 2 * sizeof(double);
 }
 
+size_t ReqPlan::table_bytes() const { return bytes_ops + bytes_rows + bytes_traj; }
+
+void ReqPlan::bind_work(unsigned char* w) {
+    d_partial = w; w += bytes_partial;
+    d_state = bytes_state ? w : nullptr; w += bytes_state;
+    d_mid = bytes_mid ? reinterpret_cast<double*>(w) : nullptr;
+}
+
+void ReqPlan::bind_tables(unsigned char* t) {
+    d_ops = reinterpret_cast<Op*>(t); t += bytes_ops;
+    d_rows = reinterpret_cast<double*>(t); t += bytes_rows;
+    d_traj = reinterpret_cast<double*>(t);
+}
+
 void ReqPlan::bind(unsigned char* base) {
-    unsigned char* q = base;
-    d_partial = q; q += bytes_partial;
-    d_state = bytes_state ? q : nullptr; q += bytes_state;
-    d_mid = bytes_mid ? reinterpret_cast<double*>(q) : nullptr; q += bytes_mid;
-    d_ops = reinterpret_cast<Op*>(q); q += bytes_ops;
-    d_rows = reinterpret_cast<double*>(q); q += bytes_rows;
-    d_traj = reinterpret_cast<double*>(q); q += bytes_traj;
+    bind_work(base);
+    bind_tables(base + bytes_partial + bytes_state + bytes_mid);
 }
 
 StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
@@ -298,6 +309,28 @@ ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t s
     return PS_OK;
 }
 
+ps_status upload_tables_contiguous(std::vector<ReqPlan*>& plans, void* dev, HostBuf& staging, hipStream_t stream) {
+    size_t need = 0;
+    for (ReqPlan* p : plans) need += p->table_bytes();
+    if (need == 0) return PS_OK;
+    ps_status st;
+    if ((st = staging.reserve(need)) != PS_OK) return st;
+    unsigned char* h0 = reinterpret_cast<unsigned char*>(staging.ptr);
+    unsigned char* h = h0;
+    for (ReqPlan* p : plans) {
+        // the host image mirrors bind_tables: ops, rows, trajectories, each
+        // in its 256-byte aligned slot
+        if (!p->prog.ops.empty()) std::memcpy(h, p->prog.ops.data(), p->prog.ops.size() * sizeof(Op));
+        if (!p->prog.rows.empty())
+            std::memcpy(h + p->bytes_ops, p->prog.rows.data(), p->prog.rows.size() * sizeof(double));
+        if (!p->prog.traj.empty())
+            std::memcpy(h + p->bytes_ops + p->bytes_rows, p->prog.traj.data(), p->prog.traj.size() * sizeof(double));
+        h += p->table_bytes();
+    }
+    hipError_t e = hipMemcpyAsync(dev, h0, need, hipMemcpyHostToDevice, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "hipMemcpyAsync(tables)");
+}
+
 }  // namespace ps
 
 using namespace ps;
@@ -315,21 +348,52 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
     DeviceGuard g(ctx->cfg.device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
     std::vector<ReqPlan> plans((size_t)n_requests);
-    for (int32_t i = 0; i < n_requests; ++i) {
-        ps_status st = plan_request(ctx, &objs[i], &seqs[i], n_samples[i], signals[i], 0, &plans[i]);
-        if (st != PS_OK) return fail(st, "request " + std::to_string(i) + ": " + ps_last_error());
+    {
+        // Compiling the requests' sequences is independent host work: spread
+        // it over a few threads (errors are thread-local, so each request's
+        // message is kept and reported from this thread).
+        std::vector<ps_status> sts((size_t)n_requests, PS_OK);
+        std::vector<std::string> errs((size_t)n_requests);
+        std::atomic<int32_t> next{0};
+        auto work = [&]() {
+            for (int32_t i; (i = next.fetch_add(1)) < n_requests;) {
+                sts[i] = plan_request(ctx, &objs[i], &seqs[i], n_samples[i], signals[i], 0, &plans[i]);
+                if (sts[i] != PS_OK) errs[i] = ps_last_error();
+            }
+        };
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const int n_threads = (int)std::min<unsigned>(std::min<unsigned>(hw, 8u), (unsigned)((n_requests + 7) / 8));
+        std::vector<std::thread> pool;
+        try {
+            for (int t = 1; t < n_threads; ++t) pool.emplace_back(work);
+        } catch (...) {
+            // no more threads: the calling thread does the rest
+        }
+        work();
+        for (std::thread& t : pool) t.join();
+        for (int32_t i = 0; i < n_requests; ++i)
+            if (sts[i] != PS_OK) return fail(sts[i], "request " + std::to_string(i) + ": " + errs[i]);
     }
     ps_status st;
     if ((st = wait_previous(ctx)) != PS_OK) return st;
-    size_t total = 0;
-    for (ReqPlan& p : plans) total += p.device_bytes();
+    // all requests' tables first (one upload), then their work buffers
+    size_t tables = 0, total = 0;
+    for (ReqPlan& p : plans) {
+        tables += p.table_bytes();
+        total += p.device_bytes();
+    }
     if ((st = ctx->batch_tables.reserve(std::max<size_t>(total, 256))) != PS_OK) return st;
-    unsigned char* base = reinterpret_cast<unsigned char*>(ctx->batch_tables.ptr);
+    unsigned char* tbase = reinterpret_cast<unsigned char*>(ctx->batch_tables.ptr);
+    unsigned char* base = tbase + tables;
     std::vector<ReqPlan*> ptrs;
+    std::vector<ReqPlan*> with_tables;
     std::vector<size_t> first, count;
     for (ReqPlan& p : plans) {
-        p.bind(base);
-        base += p.device_bytes();
+        p.bind_tables(tbase);
+        tbase += p.table_bytes();
+        p.bind_work(base);
+        base += p.device_bytes() - p.table_bytes();
+        with_tables.push_back(&p);
         if (p.prog.n_samples == 0) continue;
         if (p.obj.n_spins == 0) {
             hipError_t e = launch_fill_zero(p.signal, 2 * p.prog.n_samples, stream);
@@ -341,8 +405,8 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
         count.push_back(p.prog.slices.size());
     }
     if (ptrs.empty()) return PS_OK;
-    // records first in the staging buffer, tables after them
-    if ((st = upload_tables(ptrs, ctx->staging, 0, stream)) != PS_OK) return st;
+    if ((st = upload_tables_contiguous(with_tables, ctx->batch_tables.ptr, ctx->staging, stream)) != PS_OK)
+        return st;
     if ((st = run_rounds(ctx, ptrs, first, count, stream, ctx->batch_records, ctx->staging2, nullptr)) != PS_OK)
         return st;
     hipError_t e = hipEventRecord(ctx->done, stream);

@@ -29,8 +29,11 @@ struct ReqPlan {
     double* d_traj = nullptr;
 
     size_t device_bytes() const;       // library buffers of this request
+    size_t table_bytes() const;        // op, rotation and trajectory tables (uploaded)
     size_t footprint() const;          // + object arrays + output (admission)
     void bind(unsigned char* base);    // place the buffers at base (256-aligned)
+    void bind_tables(unsigned char* t);   // the tables alone at t (256-aligned)
+    void bind_work(unsigned char* w);     // partial rows, slice state, finalize scratch at w
     StepArgs args_for_slice(size_t k, int n_replicas = 1) const;
 };
 
@@ -41,6 +44,9 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
 
 // Stream-ordered upload of the requests' op and rotation tables.
 ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t staging_off, hipStream_t stream);
+// The same for requests whose tables were bound back to back (bind_tables)
+// from device address dev: one host image, one copy.
+ps_status upload_tables_contiguous(std::vector<ReqPlan*>& plans, void* dev, HostBuf& staging, hipStream_t stream);
 
 struct RoundImage;
 // Run slices first[i] .. first[i] + count[i] - 1 of every plan, one slice per
