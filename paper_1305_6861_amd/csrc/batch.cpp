@@ -163,6 +163,20 @@ struct RoundImage {
     int64_t tiles1 = 0, tiles2 = 0;
 };
 
+// Rough work per spin of one slice of a request: one unit per sample and
+// sub-step, a few for every other operation.
+static int64_t slice_cost(const ReqPlan& p, size_t k) {
+    const Slice& sl = p.prog.slices[k];
+    int64_t c = 0;
+    for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
+        const Op& op = p.prog.ops[i];
+        const bool counted = op.kind == OP_ADC || op.kind == OP_ADCT ||
+                             (op.kind == OP_SHAPE && op.u.shape.mode != SHAPE_APPLY);
+        c += counted ? (int64_t)op.n : 8;
+    }
+    return c;
+}
+
 ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first_slice,
                      const std::vector<size_t>& n_slices_this_call, hipStream_t stream, DevBuf& arena,
                      HostBuf& staging, std::vector<RoundImage>* rounds_out) {
@@ -185,6 +199,14 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
         for (size_t i = 0; i < plans.size(); ++i)
             if (k < n_slices_this_call[i] && plans[i]->obj.n_spins > 0) by_S[plans[i]->S].push_back(i);
         for (auto& kv : by_S) {
+            // Longest tiles first: workgroups take items in record order, so
+            // the requests whose tiles take longest start first and short
+            // ones fill the end of the launch (which workgroup runs an item
+            // never changes a result).
+            std::vector<int64_t> cost(plans.size(), 0);
+            for (size_t i : kv.second) cost[i] = slice_cost(*plans[i], first_slice[i] + k);
+            std::stable_sort(kv.second.begin(), kv.second.end(),
+                             [&](size_t a, size_t b) { return cost[a] > cost[b]; });
             RoundImage::Class c;
             c.S = kv.first;
             c.n_req = (int32_t)kv.second.size();
