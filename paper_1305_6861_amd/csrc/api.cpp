@@ -242,7 +242,9 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
     r->partial_bytes = (size_t)(r->n_rows * r->row_stride * real_bytes);
     r->fin_bytes = (size_t)finalize_scratch_doubles(r->n_rows, r->row_stride) * sizeof(double);
-    r->state_bytes = prog.slices.size() > 1 ? (size_t)(3 * obj->n_spins * real_bytes) : 0;
+    r->state_bytes = prog.slices.size() > 1
+                         ? (size_t)((3 + (int64_t)kShapeCacheReals * prog.n_state_slots) * obj->n_spins * real_bytes)
+                         : 0;
     r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out));
     return PS_OK;
 }
@@ -261,7 +263,7 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
     const int precision = ctx->cfg.precision;
     const int64_t real_bytes = precision == 64 ? 8 : 4;
     const Program& prog = r.prog;
-    StepArgs a;
+    StepArgs a{};
     a.x = r.obj.x; a.y = r.obj.y; a.z = r.obj.z; a.m0 = r.obj.m0; a.t1 = r.obj.t1; a.t2 = r.obj.t2;
     a.dw = r.obj.dw;
     a.n_spins = r.obj.n_spins;
@@ -286,6 +288,8 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
         a.load_state = i > 0;
         a.save_state = i + 1 < prog.slices.size();
         a.n_cache_slots = sl.n_cache_slots;
+        a.cache_load = sl.cache_load;
+        a.cache_save = sl.cache_save;
         hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
         if (timing_ctx) {
             t0 = timing_event(timing_ctx); t1 = timing_event(timing_ctx); t2 = timing_event(timing_ctx);

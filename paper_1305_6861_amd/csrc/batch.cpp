@@ -86,7 +86,9 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
     p->n_groups = (p->n_rows + row_group_size() - 1) / row_group_size();
     const size_t rb = ctx->cfg.precision == 64 ? 8 : 4;
     p->bytes_partial = align_up((size_t)(p->n_rows * p->row_stride) * rb);
-    p->bytes_state = p->prog.slices.size() > 1 ? align_up((size_t)(3 * obj->n_spins) * rb) : 0;
+    p->bytes_state = p->prog.slices.size() > 1
+                         ? align_up((size_t)((3 + (int64_t)kShapeCacheReals * p->prog.n_state_slots) * obj->n_spins) * rb)
+                         : 0;
     p->bytes_mid = p->n_groups > 1 ? align_up((size_t)(p->n_groups * p->row_stride) * sizeof(double)) : 0;
     p->bytes_ops = align_up(p->prog.ops.size() * sizeof(Op));
     p->bytes_rows = align_up(p->prog.rows.size() * sizeof(double));
@@ -123,7 +125,7 @@ void ReqPlan::bind(unsigned char* base) {
 
 StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     const Slice& sl = prog.slices[k];
-    StepArgs a;
+    StepArgs a{};
     a.x = obj.x; a.y = obj.y; a.z = obj.z; a.m0 = obj.m0; a.t1 = obj.t1; a.t2 = obj.t2; a.dw = obj.dw;
     a.n_spins = obj.n_spins;
     a.ops = d_ops + sl.op_begin;
@@ -137,6 +139,8 @@ StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     a.load_state = k > 0;
     a.save_state = k + 1 < prog.slices.size();
     a.n_cache_slots = sl.n_cache_slots;
+    a.cache_load = sl.cache_load;
+    a.cache_save = sl.cache_save;
     a.n_coils = 0;
     a.s_x = nullptr;
     a.s_y = nullptr;

@@ -283,25 +283,28 @@ constexpr int64_t kMinShapeRepeats = 5;
 
 void assign_shape_slots(Program* p, int max_slots) {
     max_slots = std::max(0, std::min(max_slots, kShapeSlots));
-    for (Slice& sl : p->slices) {
-        // shapes that recur often enough in the slice, most frequent first
-        std::map<int32_t, int64_t> count;
-        std::vector<int32_t> order;
-        for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
-            const Op& op = p->ops[i];
-            if (op.kind != OP_SHAPE) continue;
-            if (count[op.u.shape.shape_id]++ == 0) order.push_back(op.u.shape.shape_id);
+    // shapes that recur often enough in the program, most frequent first
+    std::map<int32_t, int64_t> count;
+    std::vector<int32_t> order;
+    for (const Op& op : p->ops) {
+        if (op.kind != OP_SHAPE) continue;
+        if (count[op.u.shape.shape_id]++ == 0) order.push_back(op.u.shape.shape_id);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return count[a] > count[b]; });
+    std::map<int32_t, int32_t> slot_of;
+    for (int32_t id : order)
+        if (count[id] >= kMinShapeRepeats && (int)slot_of.size() < max_slots) {
+            const int32_t slot = (int32_t)slot_of.size();
+            slot_of[id] = slot;
         }
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return count[a] > count[b]; });
-        std::map<int32_t, int32_t> slot_of;
-        for (int32_t id : order)
-            if (count[id] >= kMinShapeRepeats && (int)slot_of.size() < max_slots) {
-                const int32_t slot = (int32_t)slot_of.size();
-                slot_of[id] = slot;
-            }
-        sl.n_cache_slots = (int32_t)slot_of.size();
-        std::vector<bool> filled(kShapeSlots, false);
+    // fill or apply, slice by slice; a slot filled in an earlier slice is
+    // read back from the slice state instead of filled again
+    uint32_t in_state = 0;                       // slots filled in earlier slices
+    std::vector<uint32_t> filled(p->slices.size(), 0);
+    for (size_t k = 0; k < p->slices.size(); ++k) {
+        Slice& sl = p->slices[k];
+        uint32_t here = 0, loaded = 0;
+        int32_t top = -1;
         for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
             Op& op = p->ops[i];
             if (op.kind != OP_SHAPE) continue;
@@ -309,9 +312,34 @@ void assign_shape_slots(Program* p, int max_slots) {
             auto it = slot_of.find(sh.shape_id);
             if (it == slot_of.end()) { sh.slot = -1; sh.mode = SHAPE_DIRECT; continue; }
             sh.slot = it->second;
-            sh.mode = filled[sh.slot] ? SHAPE_APPLY : SHAPE_FILL;
-            filled[sh.slot] = true;
+            top = std::max(top, sh.slot);
+            const uint32_t bit = 1u << sh.slot;
+            if (here & bit) {
+                sh.mode = SHAPE_APPLY;
+            } else if (in_state & bit) {
+                sh.mode = SHAPE_APPLY;
+                loaded |= bit;
+                here |= bit;
+            } else {
+                sh.mode = SHAPE_FILL;
+                here |= bit;
+                filled[k] |= bit;
+            }
         }
+        sl.n_cache_slots = top + 1;
+        sl.cache_load = loaded;
+        sl.cache_save = 0;
+        in_state |= here;
+    }
+    // a slot filled in slice k is saved at its end when a later slice loads it
+    uint32_t later_loads = 0;
+    p->n_state_slots = 0;
+    for (size_t k = p->slices.size(); k-- > 0;) {
+        Slice& sl = p->slices[k];
+        sl.cache_save = filled[k] & later_loads;
+        later_loads |= sl.cache_load;
+        for (int32_t s = 0; s < kShapeSlots; ++s)
+            if ((sl.cache_save | sl.cache_load) & (1u << s)) p->n_state_slots = std::max(p->n_state_slots, s + 1);
     }
 }
 

@@ -15,6 +15,8 @@ struct Slice {
     int64_t sample_begin = 0;          // index of the slice's first sample
     int64_t n_samples = 0;
     int32_t n_cache_slots = 0;         // shaped-pulse propagator slots its ops use
+    uint32_t cache_load = 0;           // slots whose propagators it reads from the slice state
+    uint32_t cache_save = 0;           // slots whose propagators it writes to the slice state
 };
 
 struct Program {
@@ -25,6 +27,7 @@ struct Program {
     int64_t n_steps = 0;               // intervals per spin (see ps_count)
     int64_t n_rf = 0, n_shape_substeps = 0, n_adc_ops = 0;
     int64_t n_snapshots = 0;           // events flagged PS_EV_SNAPSHOT
+    int32_t n_state_slots = 0;         // propagator slots kept in the slice state between slices
     std::vector<Slice> slices;
 };
 
@@ -45,11 +48,15 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
 // op's offset inside its slice.  max_samples >= 1.
 void plan_slices(Program* p, int64_t max_samples);
 
-// Give every shape that occurs often (at least five times) in a time slice a
-// propagator cache slot (at most max_slots <= kShapeSlots per slice, the
-// most frequent shapes first): its first occurrence in the slice fills the
-// slot, later ones apply it.  Other SHAPE ops (all of them when max_slots is
-// 0) step their sub-steps directly.  Run after the slices are final.
+// Give every shape that occurs often (at least five times) in the program a
+// propagator cache slot (at most max_slots <= kShapeSlots, the most frequent
+// shapes first): its first occurrence fills the slot, later ones apply it.
+// A slot filled in one time slice and used in a later one is written to the
+// slice state at the end of the slice that filled it and read back by the
+// slices that use it (Slice::cache_save / cache_load), so a shape is stepped
+// sub-step by sub-step once per request.  Other SHAPE ops (all of them when
+// max_slots is 0) step their sub-steps directly.  Run after the slices are
+// final.
 void assign_shape_slots(Program* p, int max_slots);
 
 // Copy of the ops with rotations narrowed to FP32 (precision 32 tables).

@@ -509,6 +509,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
         }
     }
 
+    // Propagators filled in an earlier time slice: back from the state into
+    // this lane's own cache entries (each lane reads only what it wrote).
+    if (a.cache_load) {
+        const auto st = gmem(reinterpret_cast<const real*>(a.state));
+        for (int slot = 0; slot < kShapeSlots; ++slot) {
+            if (!((a.cache_load >> slot) & 1u)) continue;
+            real* cache = s_cache + slot * (kShapeCacheReals * S * kBlock) + tid;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int64_t i = base + s * 64 + lane;
+#pragma unroll
+                for (int e = 0; e < kShapeCacheReals; ++e)
+                    cache[(e * S + s) * kBlock] =
+                        i < a.n_spins ? st[(3 + kShapeCacheReals * slot + e) * a.n_spins + i] : (real)0;
+            }
+        }
+    }
+
     // shaped-pulse rotation rows -> LDS (made visible by the first barrier below)
     {
         const auto rows = gmem(reinterpret_cast<const double*>(a.rows));
@@ -1007,6 +1025,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
             const int64_t i = base + s * 64 + lane;
             if (i < a.n_spins) {
                 st[i] = sp.ar[s]; st[a.n_spins + i] = sp.ai[s]; st[2 * a.n_spins + i] = sp.az[s];
+            }
+        }
+        for (int slot = 0; slot < kShapeSlots; ++slot) {
+            if (!((a.cache_save >> slot) & 1u)) continue;
+            const real* cache = s_cache + slot * (kShapeCacheReals * S * kBlock) + tid;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int64_t i = base + s * 64 + lane;
+                if (i < a.n_spins) {
+#pragma unroll
+                    for (int e = 0; e < kShapeCacheReals; ++e)
+                        st[(3 + kShapeCacheReals * slot + e) * a.n_spins + i] = cache[(e * S + s) * kBlock];
+                }
             }
         }
     }

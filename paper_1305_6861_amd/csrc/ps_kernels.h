@@ -16,10 +16,13 @@ struct StepArgs {
     const void* rows;        // device, n_shape_rows * 9 doubles (rotation deltas)
     void* partial;           // device, gridDim.x * rows_per_block rows of row_stride reals
     int64_t row_stride;      // reals per workgroup row (2 per sample of the slice)
-    void* state;             // device, 3 * n_spins reals (Mxy_a re, im, Mz_a), SoA
+    void* state;             // device, (3 + 12 * slots) * n_spins reals, SoA: Mxy_a re, im,
+                             // Mz_a, then kShapeCacheReals entries per kept propagator slot
     int32_t load_state;      // resume from state instead of equilibrium
     int32_t save_state;      // write the anchors back at the end
     int32_t n_cache_slots;   // shaped-pulse propagator slots the slice's ops use
+    uint32_t cache_load;     // slots read from the state at the start (bit per slot)
+    uint32_t cache_save;     // slots written to the state at the end (bit per slot)
     int32_t n_coils;         // receive coils (0: one homogeneous coil, no weights)
     const float *s_x, *s_y;  // device, n_coils * n_spins transverse sensitivities
     int64_t coil_stride;     // reals between coils' sample blocks inside a row
