@@ -59,9 +59,10 @@ typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
  * HIP events on its stream so that ps_kernel_times() can report durations. */
 #define PS_CFG_KERNEL_TIMING 1u
 /* ps_config.flags: step every shaped pulse sub-step by sub-step.  By default a
- * shaped pulse that recurs within a time slice is stepped once per spin into
- * the affine map it applies (every sub-step of eq. 3.23 is affine in M), and
- * later occurrences apply that map, rotated by their RF phase offset.  Both
+ * shaped pulse that recurs in a request is stepped once per spin into the
+ * affine map it applies (every sub-step of eq. 3.23 is affine in M; the map
+ * is kept across time slices), and later occurrences apply that map,
+ * rotated by their RF phase offset.  Both
  * give the same signal within FP32 rounding; this flag exists to measure and
  * test the sub-step path on sequences with repeated shapes. */
 #define PS_CFG_NO_SHAPE_CACHE 2u
