@@ -697,6 +697,115 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         }
                     }
                     const auto partial_c = partial + coil * a.coil_stride;
+                    if constexpr (std::is_same<real, float>::value && G > 1) {
+                        // The wave group shares its G * S spins, as in the
+                        // Cartesian readout: wave wg of the group evaluates
+                        // chunk round * G + wg for all of them, so each lane
+                        // sums 8 spins per sample, the butterfly is shared by
+                        // them and no chunk sums are added across waves.
+                        // Every spin's parameters and weighted anchor go
+                        // through LDS once per pass; rows of G chunks are
+                        // staged per round.
+                        constexpr int RT = G * S;
+                        float4* g_row = s_trow;                                        // [G * kT]
+                        double* g_anc = reinterpret_cast<double*>(g_row + G * kT);      // [G * kT / kTB][4]
+                        float* g_par = reinterpret_cast<float*>(g_anc + 4 * (G * kT / kTB));   // [kWaves][S][8][64]
+                        static_assert(sizeof(float4) * G * kT + sizeof(double) * 4 * (G * kT / kTB) +
+                                          sizeof(float) * kWaves * S * 8 * 64 <= sizeof(s_stepf),
+                                      "shared trajectory staging fits the step-factor area");
+                        __syncthreads();     // earlier readers of these areas are done
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            float* q = g_par + ((wave * S + s) * 8) * 64 + lane;
+                            const double r2 = sp.r2[s];
+                            const uint64_t r2b = (uint64_t)__double_as_longlong(r2);
+                            q[0 * 64] = sp.x[s]; q[1 * 64] = sp.y[s]; q[2 * 64] = sp.z[s]; q[3 * 64] = sp.dw[s];
+                            q[4 * 64] = __uint_as_float((uint32_t)r2b);
+                            q[5 * 64] = __uint_as_float((uint32_t)(r2b >> 32));
+                            q[6 * 64] = wr[s]; q[7 * 64] = wi[s];
+                        }
+                        const int w0 = (wave / G) * G;
+                        const int smp_lane = readout_sample_of_lane(lane);
+                        const int n_rounds = (n_chunks + G - 1) / G;
+                        for (int round = 0; round < n_rounds; ++round) {
+                            __syncthreads();     // parameters visible; previous round's rows read
+                            if (tid < G * kT) {  // rows past n are never stored
+                                const int c = tid / kT, t = tid % kT;
+                                const int j = round * G + c;
+                                const auto row = table + 4 * min(j * kT + t, n - 1);
+                                const auto blk_row = table + 4 * min(j * kT + (t & ~(kTB - 1)), n - 1);
+                                g_row[tid] = make_float4((float)(row[0] - blk_row[0]), (float)(row[1] - blk_row[1]),
+                                                         (float)(row[2] - blk_row[2]), (float)(row[3] - blk_row[3]));
+                                if ((t & (kTB - 1)) == 0) {
+#pragma unroll
+                                    for (int k = 0; k < 4; ++k) g_anc[(tid / kTB) * 4 + k] = blk_row[k];
+                                }
+                            }
+                            __syncthreads();
+                            const int j = round * G + wg;
+                            if (j >= n_chunks) continue;
+                            // the group's spins: x, y, z, dw and log2(e) / T2 for
+                            // the samples; 1 / T2 and the anchor are read again
+                            // per block (fewer live registers)
+                            auto par = [&](int q) {
+                                return g_par + (((w0 + q / S) * S + q % S) * 8) * 64 + lane;
+                            };
+                            auto rate = [&](const float* src) {
+                                return __longlong_as_double((long long)(((uint64_t)__float_as_uint(src[5 * 64]) << 32) |
+                                                                        (uint64_t)__float_as_uint(src[4 * 64])));
+                            };
+                            float px[RT], py[RT], pz[RT], pdw[RT], pr2l[RT];
+#pragma unroll
+                            for (int q = 0; q < RT; ++q) {
+                                const float* src = par(q);
+                                px[q] = src[0 * 64]; py[q] = src[1 * 64]; pz[q] = src[2 * 64]; pdw[q] = src[3 * 64];
+                                pr2l[q] = (float)(rate(src) * kLog2e);
+                            }
+                            float red16[16];
+#pragma unroll
+                            for (int b = 0; b < kT / kTB; ++b) {
+                                // keep the blocks apart: interleaving them
+                                // would keep several blocks' anchors live
+                                __builtin_amdgcn_sched_barrier(0);
+                                const double* anc = g_anc + (wg * (kT / kTB) + b) * 4;
+                                const double kb[3] = {anc[0], anc[1], anc[2]};
+                                const double tb = anc[3];
+                                float c0[RT], br[RT], bi[RT];
+#pragma unroll
+                                for (int q = 0; q < RT; ++q) {
+                                    const float* src = par(q);
+                                    const double ph = phase_rev(kb, tb, px[q], py[q], pz[q], pdw[q]);
+                                    c0[q] = (float)(ph - rint(ph));
+                                    const float eb = Math<float>::expneg(tb, rate(src));
+                                    br[q] = eb * src[6 * 64]; bi[q] = eb * src[7 * 64];
+                                }
+                                float vq[16];
+#pragma unroll
+                                for (int t = 0; t < kTB; ++t) {
+                                    const float4 d = g_row[wg * kT + b * kTB + t];
+                                    const float dt_rev = d.w * (float)kInv2Pi;   // dw dt / 2 pi = dw * dt_rev
+                                    float sr = 0, si = 0;
+#pragma unroll
+                                    for (int q = 0; q < RT; ++q) {
+                                        const float f = c0[q] + fmaf(d.x, px[q], fmaf(d.y, py[q], fmaf(d.z, pz[q], pdw[q] * dt_rev)));
+                                        const float c = __builtin_amdgcn_cosf(f);
+                                        const float sn = __builtin_amdgcn_sinf(f);
+                                        const float ed = __builtin_amdgcn_exp2f(-d.w * pr2l[q]);
+                                        sr = fmaf(ed, fmaf(br[q], c, bi[q] * sn), sr);
+                                        si = fmaf(ed, fmaf(bi[q], c, -br[q] * sn), si);
+                                    }
+                                    vq[2 * t] = sr; vq[2 * t + 1] = si;
+                                }
+                                quarter_reduce(vq, lane);
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) red16[4 * b + i] = vq[i];
+                            }
+                            const float v = reduce16(red16, lane);
+                            if (j * kT + smp_lane < n)
+                                partial_c[2 * (int64_t)(aux + j * kT + smp_lane) + (lane & 1)] = v;
+                        }
+                        continue;
+                    }
                     for (int j = 0; j < n_chunks; ++j) {
                         real v;
                         int smp_lane;                // chunk sample whose component lane & 1 this lane ends with
