@@ -654,7 +654,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 // the block's samples add FP32 offsets (k_s - k_b, t_s - t_b)
                 // that the workgroup stages in LDS once per chunk; the
                 // offsets stay small, so FP32 keeps the phase to ~1e-7 of a
-                // revolution.  Each wave sums its own spins over a chunk; a
+                // revolution.  FP32 wave groups share their spins (below);
+                // otherwise each wave sums its own spins over a chunk and a
                 // wave group's waves add their chunk sums in LDS in wave order.
                 if (a.n_replicas > 1 && (adc_seen++ % a.n_replicas) != rep) continue;
                 const int n = (int)__builtin_amdgcn_readfirstlane(op.n);
