@@ -118,18 +118,27 @@ def test_more_recurring_shapes_than_slots(ps):
     assert report("three shapes cached/fp64", oracle.rel_l2(run(ps, obj, seq, precision=64), ref)) <= TOL64
 
 
-def test_cache_refilled_in_every_time_slice(ps):
+def test_cache_kept_across_time_slices(ps):
     """A small partial-sum buffer cuts the sequence into slices of a few
-    repetitions; every slice refills its slot from its own first occurrence
-    (whose phase differs from slice to slice)."""
+    repetitions; the propagator filled in the first slice is written to the
+    slice state and read back by every later slice, whose first occurrence
+    has another RF phase (applied by conjugation)."""
     obj = random_spins(1500, seed=23, dw_sigma_hz=100.0)
     seq = rf_spoiled_sinc(40, n_adc=24)
     ref = oracle.simulate(obj, seq)
     n_rows = 6                                           # 1500 spins at S = 1: 6 workgroups x 1 row
-    sliced = run(ps, obj, seq, spins_per_lane=1, max_partial_bytes=n_rows * 2 * 4 * 24 * 6)
+    small = n_rows * 2 * 4 * 24 * 6
+    sliced = run(ps, obj, seq, spins_per_lane=1, max_partial_bytes=small)
     whole = run(ps, obj, seq, spins_per_lane=1)
     assert report("sliced cached", oracle.rel_l2(sliced, ref)) <= TOL32
     assert report("sliced vs whole", oracle.rel_l2(sliced, whole)) <= CACHE_VS_DIRECT32
+    sliced64 = run(ps, obj, seq, spins_per_lane=1, precision=64, max_partial_bytes=2 * small)
+    assert report("sliced cached/fp64", oracle.rel_l2(sliced64, ref)) <= TOL64
+    # three recurring shapes, two slots, slices of 64 samples (4 repetitions)
+    seq3 = three_shapes(12)
+    ref3 = oracle.simulate(obj, seq3)
+    assert report("three shapes sliced", oracle.rel_l2(
+        run(ps, obj, seq3, spins_per_lane=1, max_partial_bytes=n_rows * 2 * 4 * 64), ref3)) <= TOL32
 
 
 @pytest.mark.parametrize("S", [1, 2])
