@@ -95,10 +95,24 @@ template <> struct Math<float> {
         float f = (float)(a - i);
         return ldexpf(__builtin_amdgcn_exp2f(f), (int)i);
     }
-    // 1 - exp(-t r), formed without cancellation (for t r << 1 the FP32
-    // difference 1 - exp(-t r) would keep only a few significant bits).
+    // 1 - exp(-x), x = t r >= 0, formed without cancellation (for x << 1 the
+    // FP32 difference 1 - exp(-x) would keep only a few significant bits):
+    // below 1/2 the Taylor series of 1 - e^-x to x^8 (truncation below
+    // 1.5e-8 relative), above it 1 - 2^(-x log2 e) from the hardware exp2
+    // (e^-x <= 0.61 there, so its error stays relative).  Both are cheaper
+    // than the library expm1f, which handles the whole range.
     static __device__ __forceinline__ float one_minus_expneg(double t, double r) {
-        return -expm1f((float)(-t * r));
+        const float x = (float)(t * r);
+        float p = fmaf(x, -1.0f / 40320.0f, 1.0f / 5040.0f);
+        p = fmaf(x, -p, 1.0f / 720.0f);
+        p = fmaf(x, -p, 1.0f / 120.0f);
+        p = fmaf(x, -p, 1.0f / 24.0f);
+        p = fmaf(x, -p, 1.0f / 6.0f);
+        p = fmaf(x, -p, 0.5f);
+        p = fmaf(x, -p, 1.0f);
+        p *= x;
+        const float q = 1.0f - __builtin_amdgcn_exp2f(-x * (float)kLog2e);
+        return x < 0.5f ? p : q;
     }
     // cos and sin of 2 pi c for a phase c in revolutions (FP64), reduced to
     // [-1/2, 1/2] in FP64 before rounding to FP32, then evaluated by the
@@ -560,7 +574,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
             if (kind == OP_RF) {
                 real mx[S], my[S], mz[S];
                 evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
-                rotate<real, S>(rot_of<real>(op), mx, my, mz);
+                const real* D = rot_of<real>(op);
+                if (mxy_zero) {              // (0, 0, Mz): only the third column of D acts
+                    const real d02 = D[2], d12 = D[5], d22 = D[8];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        sp.ar[s] = d02 * mz[s]; sp.ai[s] = d12 * mz[s]; sp.az[s] = fma(d22, mz[s], mz[s]);
+                    }
+                    continue;
+                }
+                rotate<real, S>(D, mx, my, mz);
 #pragma unroll
                 for (int s = 0; s < S; ++s) { sp.ar[s] = mx[s]; sp.ai[s] = my[s]; sp.az[s] = mz[s]; }
             } else if (kind == OP_SPOIL) {
