@@ -138,9 +138,12 @@ template <> struct Math<double> {
 // wave-wide transpose-reduce of 64 values per lane -> 1 value per lane
 // (lane l ends with the sum over all 64 lanes of input value l)
 // ---------------------------------------------------------------------------
+// The patterns used here (row mirrors, quad permutes) read a valid lane for
+// every lane, so bound_ctrl changes no value; set, it lets the compiler fold
+// the move into the consuming add (one v_add_f32 with a DPP source).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int CTRL, int BIT, int HALF, int N>
@@ -1071,7 +1074,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         }
                         pr[q] = p_r; pi[q] = p_i;
                     }
-                    for (int j = j0; j < n_chunks; j += G / P) {
+                    // With P > 1, P n_chunks == G: each sub-group has exactly
+                    // the one chunk j0.  Saying so lets the compiler drop the
+                    // loop; otherwise it hoists the (loop-invariant) products
+                    // out of it and copies them before every in-place lane
+                    // swap of the reduction.
+                    const int j_end = P == 1 ? n_chunks : j0 + 1;
+                    for (int j = j0; j < j_end; j += G / P) {
                         real qr[RS], qi[RS];
 #pragma unroll
                         for (int q = 0; q < RS; ++q) { qr[q] = pr[q]; qi[q] = pi[q]; }
