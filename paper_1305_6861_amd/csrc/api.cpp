@@ -84,7 +84,8 @@ int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins) {
     // lane-sum + butterfly reduction.  Readouts run 8 spins per lane from
     // S = 2 on (wave groups of 4 at S = 2, of 2 at S = 4), and S = 4 no longer
     // fits two waves per SIMD in registers, nor its propagator slots in LDS,
-    // so the automatic choice stops at 2.
+    // so the automatic choice stops at 2.  (S = 1 runs three waves per SIMD,
+    // so objects between the thresholds still fill the chip in one pass.)
     const int64_t target_waves = 2 * 4 * (int64_t)std::max(ctx->n_cu, 1);
     const int maxS = 2;
     int S = 1;

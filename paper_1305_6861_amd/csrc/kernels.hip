@@ -1185,13 +1185,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     }
 }
 
-// Waves per SIMD the register allocation is held to: two for FP32 with up
-// to 2 spins per lane (the readout is tuned to fit 256 registers, and a
-// second wave hides the latency of its LDS and transcendental operations),
-// else whatever the code needs.
+// Waves per SIMD the register allocation is held to: for FP32, three at 1
+// spin per lane (its readout of 4 spins per lane fits 168 registers; the
+// spills left are on cold paths: the prologue and the shaped-pulse set-up)
+// and two at 2 (the readout is tuned to fit 256 registers, and a second
+// wave hides the latency of its LDS and transcendental operations); else
+// whatever the code needs.  Three waves per SIMD give objects of 2 to 3
+// waves per SIMD at S = 1 a single pass over the chip instead of a full
+// pass and a partial one.
 template <typename real, int S>
 struct StepOccupancy {
-    static constexpr int kWavesPerEU = (std::is_same<real, float>::value && S <= 2) ? 2 : 1;
+    static constexpr int kWavesPerEU = !std::is_same<real, float>::value ? 1 : S == 1 ? 3 : S == 2 ? 2 : 1;
 };
 
 // Workgroup b runs tile b % n_tiles as readout replica b / n_tiles.
