@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import coils, configs as C
+from workloads import SPOIL, Sequence, coils, configs as C
 from workloads.phantom import random_spins
 
 pytestmark = pytest.mark.gpu
@@ -79,6 +79,22 @@ def test_coils_on_every_tiling(ps, S):
     seq = C.spin_echo_2d(24, 5)
     rx = coils.loop_ring(obj, 2, ring_radius=0.25, coil_radius=0.1)
     per_coil(f"S={S} 2 loops", run(ps, obj, seq, rx, spins_per_lane=S), oracle.simulate(obj, seq, coils=rx), TOL32)
+
+
+@pytest.mark.parametrize("S", [1, 2, 4])
+def test_coils_on_short_readouts(ps, S):
+    """Readouts of 1, 2 and 3 chunks of 32 samples (the last ragged) with
+    three coils: where a readout has fewer chunks than the wave group has
+    waves, the waves split the group's spins and add their sums in LDS, once
+    per coil pass."""
+    obj = random_spins(1700, seed=50 + S, dw_sigma_hz=25.0)
+    seq = Sequence("short")
+    for n_adc in (20, 64, 70):
+        seq.add(1e-3, m=(-n_adc / 2, 2, 0), alpha=0.7, phase=0.3)
+        seq.add(n_adc * 1e-5, m=(n_adc * 1.1, 0, 0), n_adc=n_adc, flags=SPOIL)
+    rx = coils.loop_ring(obj, 3, ring_radius=0.2, coil_radius=0.08)
+    per_coil(f"short readouts S={S} 3 loops", run(ps, obj, seq, rx, spins_per_lane=S),
+             oracle.simulate(obj, seq, coils=rx), TOL32)
 
 
 def test_many_coils_and_time_slices(ps):

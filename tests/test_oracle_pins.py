@@ -264,6 +264,65 @@ def test_spoiled_gre_ernst_approach_to_steady_state():
     np.testing.assert_allclose(sig, ref, rtol=0, atol=1e-12)
 
 
+def _widen(obj):
+    return tuple(np.asarray(a, dtype=float) for a in (obj.x, obj.y, obj.m0, obj.t1, obj.t2, obj.dw))
+
+
+def test_whole_c1_output_closed_form():
+    """Every sample of the c1 workload (64^2 spins, 64 spoiled-GRE
+    repetitions of 64 samples) in closed form: before pulse m,
+    Mz_{m+1} = m0 + (cos a Mz_m - m0) E1(TR) (spoiled, so Mxy starts at zero);
+    sample n of repetition m is j sin a Mz_m E2(t_n) e^{-j(2 pi k.x + dw t_n)}
+    with t_n = TE + (n - N/2) dwell and k = ((n - N/2) / FOV, (m - M/2) / FOV)
+    (eq. 3.19 as a rotation by -a about x, eq. 3.5 / 3.14 / 3.33).  Built from
+    the recipe's parameters, not from its event list."""
+    obj, seq = C.c1()
+    md = seq.meta
+    n_ro, n_pe, fov, tr, te, dwell, a = (md["n_read"], md["n_pe"], md["fov"], md["tr"], md["te"],
+                                         md["dwell"], md["alpha"])
+    x, y, m0, t1, t2, dw = _widen(obj)
+    sig = oracle.simulate(obj, seq).reshape(n_pe, n_ro)
+    t = te + (np.arange(n_ro) - n_ro // 2) * dwell
+    kx = (np.arange(n_ro) - n_ro // 2) / fov
+    e2 = np.exp(-t[:, None] / t2[None, :])
+    mz = m0.copy()
+    worst = 0.0
+    for m in range(n_pe):
+        ky = (m - n_pe // 2) / fov
+        ph = 2 * np.pi * (kx[:, None] * x[None, :] + ky * y[None, :]) + dw[None, :] * t[:, None]
+        ref = (1j * math.sin(a) * mz[None, :] * e2 * np.exp(-1j * ph)).sum(axis=1)
+        worst = max(worst, np.abs(sig[m] - ref).max() / np.abs(ref).max())
+        mz = m0 + (math.cos(a) * mz - m0) * np.exp(-tr / t1)
+    assert worst < EXACT, worst
+
+
+def test_whole_c2_recipe_output_closed_form():
+    """Every sample of the c2 recipe at 64^2 x 4 jittered isochromats with
+    off-resonance: 90x makes j Mz_m; TE/2 of free precession; 180y turns
+    Mxy into -conj(Mxy), so Mxy = j Mz_m E2(TE/2) e^{+j dw TE/2}; sample n
+    then lies t_n = TE/2 + (n - N/2) dwell after the 180 with
+    k = ((n - N/2) / FOV, (m - M/2) / FOV).  Mz before the 90 is m0 for the
+    first repetition and m0 [1 - 2 E1(TR - TE/2) + E1(TR)] after it."""
+    obj, seq = C.c2(64)
+    md = seq.meta
+    n_ro, n_pe, fov, tr, te, dwell = (md["n_read"], md["n_pe"], md["fov"], md["tr"], md["te"], md["dwell"])
+    x, y, m0, t1, t2, dw = _widen(obj)
+    sig = oracle.simulate(obj, seq).reshape(n_pe, n_ro)
+    t = te / 2 + (np.arange(n_ro) - n_ro // 2) * dwell
+    kx = (np.arange(n_ro) - n_ro // 2) / fov
+    before = np.exp(-(te / 2) / t2) * np.exp(1j * dw * te / 2)
+    decay = np.exp(-t[:, None] / t2[None, :])
+    mz_ss = m0 * (1 - 2 * np.exp(-(tr - te / 2) / t1) + np.exp(-tr / t1))
+    worst = 0.0
+    for m in range(n_pe):
+        mz = m0 if m == 0 else mz_ss
+        ky = (m - n_pe // 2) / fov
+        ph = 2 * np.pi * (kx[:, None] * x[None, :] + ky * y[None, :]) + dw[None, :] * t[:, None]
+        ref = (1j * (mz * before)[None, :] * decay * np.exp(-1j * ph)).sum(axis=1)
+        worst = max(worst, np.abs(sig[m] - ref).max() / np.abs(ref).max())
+    assert worst < EXACT, worst
+
+
 def test_inversion_recovery_null_at_t1_ln2():
     t1 = 0.9
     for ti, expect in [(t1 * math.log(2), 0.0), (0.3, None), (2.0, None)]:
