@@ -238,7 +238,7 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->snaps = r->any_snaps ? snaps : nullptr;
     int64_t max_slice = 0;
     for (const Slice& sl : prog.slices) max_slice = std::max(max_slice, sl.n_samples);
-    r->coil_stride = 2 * max_slice;      // one block of samples per coil in every row
+    r->coil_stride = pad_fin(2 * max_slice);   // one block of samples per coil in every row
     r->row_stride = r->coil_stride * r->n_out;
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
     r->partial_bytes = (size_t)(r->n_rows * r->row_stride * real_bytes);

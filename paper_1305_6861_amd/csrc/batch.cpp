@@ -82,7 +82,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
     if (n_samples > 0 && !signal) return fail(PS_E_INVALID_ARG, "signal is NULL");
     int64_t max_slice = 0;
     for (const Slice& s : p->prog.slices) max_slice = std::max(max_slice, s.n_samples);
-    p->row_stride = 2 * max_slice;
+    p->row_stride = pad_fin(2 * max_slice);
     p->n_groups = (p->n_rows + row_group_size() - 1) / row_group_size();
     const size_t rb = ctx->cfg.precision == 64 ? 8 : 4;
     p->bytes_partial = align_up((size_t)(p->n_rows * p->row_stride) * rb);
@@ -256,21 +256,19 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
             f.n_groups = p->n_groups;
             f.out = p->signal + 2 * sl.sample_begin;
             f.mid = p->d_mid;
-            const int64_t jt = (f.n_vals + 255) / 256;
             f.tile_begin1 = t1;
             f.tile_begin2 = t2;
-            t1 += std::max<int64_t>(f.n_groups, 1) * jt;
-            if (f.n_groups > 1) t2 += jt;
+            t1 += std::max<int64_t>(f.n_groups, 1) * finalize_tiles(f.n_vals);   // kFinVals values a thread
+            if (f.n_groups > 1) t2 += (f.n_vals + 255) / 256;                   // one value a thread
             if (p->obj.n_spins == 0) continue;   // zero-filled separately
             fd.push_back(f);
         }
         // recompute the prefix sums over the records kept
         t1 = 0; t2 = 0;
         for (FinDesc& f : fd) {
-            const int64_t jt = (f.n_vals + 255) / 256;
             f.tile_begin1 = t1; f.tile_begin2 = t2;
-            t1 += std::max<int64_t>(f.n_groups, 1) * jt;
-            if (f.n_groups > 1) t2 += jt;
+            t1 += std::max<int64_t>(f.n_groups, 1) * finalize_tiles(f.n_vals);
+            if (f.n_groups > 1) t2 += (f.n_vals + 255) / 256;
         }
         R.n_fin = (int32_t)fd.size();
         R.tiles1 = t1; R.tiles2 = t2;

@@ -1239,16 +1239,59 @@ void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_
 // (pass 2); with at most kRowGroup rows pass 1 writes the output directly.
 constexpr int64_t kRowGroup = 64;
 
+// A pass-1 thread sums kFinVals consecutive values of its row group with
+// one 16-byte (FP32) or two 16-byte (FP64) loads per row: the host pads
+// row_stride and every coil block to a multiple of kFinVals values, so the
+// loads are aligned and stay inside the rows (values past n_vals in the
+// padding are read but never stored).  Each value is still summed over the
+// rows in row order.
+
+__device__ __forceinline__ void load_fin(const float* p, double (&v)[kFinVals]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ __forceinline__ void load_fin(const double* p, double (&v)[kFinVals]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+// Sum of rows r0 .. r1 - 1 at values j .. j + kFinVals - 1 into out[j ..],
+// the values below n_vals only.
+template <typename real>
+__device__ __forceinline__ void sum_rows(const real* partial, int64_t r0, int64_t r1, int64_t row_stride, int64_t j,
+                                         int64_t n_vals, double* out) {
+    double s[kFinVals] = {0.0, 0.0, 0.0, 0.0};
+    // eight rows' loads in flight before their adds (still in row order)
+    constexpr int kU = 8;
+    int64_t r = r0;
+    for (; r + kU <= r1; r += kU) {
+        double v[kU][kFinVals];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) load_fin(partial + (r + u) * row_stride + j, v[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int k = 0; k < kFinVals; ++k) s[k] += v[u][k];
+    }
+    for (; r < r1; ++r) {
+        double v[kFinVals];
+        load_fin(partial + r * row_stride + j, v);
+#pragma unroll
+        for (int k = 0; k < kFinVals; ++k) s[k] += v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kFinVals; ++k)
+        if (j + k < n_vals) out[j + k] = s[k];
+}
+
 template <typename real>
 __global__ void finalize_rows_kernel(const real* __restrict__ partial, int64_t n_rows, int64_t row_stride,
                                      int64_t n_vals, double* __restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kFinVals;
     if (j >= n_vals) return;
     const int64_t r0 = (int64_t)blockIdx.y * kRowGroup;
     const int64_t r1 = min(n_rows, r0 + kRowGroup);
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) s += (double)partial[r * row_stride + j];
-    out[(int64_t)blockIdx.y * n_vals + j] = s;
+    sum_rows(partial, r0, r1, row_stride, j, n_vals, out + (int64_t)blockIdx.y * n_vals);
 }
 
 __global__ void finalize_groups_kernel(const double* __restrict__ mid, int64_t n_groups, int64_t n_vals,
@@ -1275,16 +1318,14 @@ template <typename real>
 __global__ void batch_finalize_pass1(const FinDesc* __restrict__ d, int32_t n) {
     const int64_t t = blockIdx.x;
     const FinDesc& f = d[find_desc(d, n, t, false)];
-    const int64_t jt = (f.n_vals + 255) / 256;
+    const int64_t jt = finalize_tiles(f.n_vals);
     const int64_t local = t - f.tile_begin1;
     const int64_t g = local / jt;
-    const int64_t j = (local % jt) * 256 + threadIdx.x;
+    const int64_t j = ((local % jt) * 256 + threadIdx.x) * kFinVals;
     if (j >= f.n_vals) return;
-    const auto partial = gmem(reinterpret_cast<const real*>(f.partial));
     const int64_t r0 = g * kRowGroup, r1 = min(f.n_rows, r0 + kRowGroup);
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) s += (double)partial[r * f.row_stride + j];
-    if (f.n_groups > 1) gmem(f.mid)[g * f.n_vals + j] = s; else gmem(f.out)[j] = s;
+    sum_rows(reinterpret_cast<const real*>(f.partial), r0, r1, f.row_stride, j, f.n_vals,
+             f.n_groups > 1 ? f.mid + g * f.n_vals : f.out);
 }
 
 __global__ void batch_finalize_pass2(const FinDesc* __restrict__ d, int32_t n) {
@@ -1434,7 +1475,8 @@ hipError_t launch_finalize(const void* partial, int precision, int64_t n_rows, i
                            int64_t n_vals, double* out, double* scratch, hipStream_t st) {
     if (n_vals <= 0) return hipSuccess;
     const int threads = 256;
-    const int64_t gx = (n_vals + threads - 1) / threads;
+    if (row_stride % kFinVals != 0 || reinterpret_cast<uintptr_t>(partial) % 16 != 0) return hipErrorInvalidValue;
+    const int64_t gx = finalize_tiles(n_vals);
     const int64_t groups = (n_rows + kRowGroup - 1) / kRowGroup;
     double* dst = groups > 1 ? scratch : out;
     if (groups > 1 && !scratch) return hipErrorInvalidValue;
@@ -1447,8 +1489,8 @@ hipError_t launch_finalize(const void* partial, int precision, int64_t n_rows, i
                            reinterpret_cast<const float*>(partial), n_rows, row_stride, n_vals, dst);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || groups <= 1) return e;
-    hipLaunchKernelGGL(finalize_groups_kernel, dim3((unsigned)gx), dim3(threads), 0, st, scratch, groups,
-                       n_vals, out);
+    hipLaunchKernelGGL(finalize_groups_kernel, dim3((unsigned)((n_vals + threads - 1) / threads)), dim3(threads), 0,
+                       st, scratch, groups, n_vals, out);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ struct alignas(16) FinDesc {
     int64_t n_groups;        // row groups (pass 2 needed when > 1)
     double* out;             // n_vals doubles
     double* mid;             // n_groups * n_vals doubles when n_groups > 1
-    int64_t tile_begin1;     // first pass-1 block (n_groups * ceil(n_vals/256) blocks)
+    int64_t tile_begin1;     // first pass-1 block (n_groups * finalize_tiles(n_vals) blocks)
     int64_t tile_begin2;     // first pass-2 block (ceil(n_vals/256) blocks if n_groups > 1, else 0)
 };
 
@@ -65,8 +65,15 @@ size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_row
 // Propagator slots (at most kShapeSlots) that fit a step workgroup's LDS
 // budget next to n_shape_rows shaped-pulse rows.
 int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows);
+// Finalize pass 1: each thread sums kFinVals consecutive values, so partial
+// rows and the coil blocks inside them are padded to a multiple of kFinVals
+// values; finalize_tiles(n) workgroups of 256 threads cover n values.
+constexpr int64_t kFinVals = 4;
+constexpr int64_t finalize_tiles(int64_t n_vals) { return (n_vals + 256 * kFinVals - 1) / (256 * kFinVals); }
+constexpr int64_t pad_fin(int64_t n_vals) { return (n_vals + kFinVals - 1) / kFinVals * kFinVals; }
 // Doubles of scratch launch_finalize needs for n_rows rows of n_vals values.
 int64_t finalize_scratch_doubles(int64_t n_rows, int64_t n_vals);
+// row_stride and the partial base must be multiples of kFinVals values.
 hipError_t launch_finalize(const void* partial, int precision, int64_t n_rows, int64_t row_stride,
                            int64_t n_vals, double* out, double* scratch, hipStream_t st);
 hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t st);
