@@ -1366,8 +1366,11 @@ size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_row
 
 int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows) {
     // FP32: keep a workgroup's LDS within half of a CU's 160 KiB so that two
-    // workgroups (8 waves, the register-bound occupancy) stay resident per
-    // CU; FP64 kernels run one workgroup per CU anyway
+    // workgroups (8 waves, the register-bound occupancy at S = 2) stay
+    // resident per CU.  At S = 1 registers allow three; slots that push a
+    // workgroup past a third of the LDS trade the third for fewer sub-step
+    // evaluations, which cost far more.  FP64 kernels run one workgroup per
+    // CU anyway.
     const size_t kBudget = (precision == 64 ? 160 : 80) * 1024;
     size_t fixed;
     if (precision == 64) fixed = spins_per_lane == 1 ? static_lds_bytes<double, 1>() : static_lds_bytes<double, 2>();

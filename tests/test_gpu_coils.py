@@ -97,6 +97,37 @@ def test_coils_on_short_readouts(ps, S):
              oracle.simulate(obj, seq, coils=rx), TOL32)
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+def test_odd_sample_counts_row_groups_coils_and_slices(ps, precision):
+    """Odd sample counts (rows and coil blocks padded for the finalize's
+    four-value loads), more than one row group of partial rows (the
+    two-pass cross-workgroup sum), three coils and several time slices, for
+    one call and for the batched path."""
+    import torch
+    obj = random_spins(20000, seed=60, dw_sigma_hz=30.0)     # 79 workgroups at S = 1: two row groups
+    seq = Sequence("odd")
+    for i in range(5):
+        n_adc = 21 + 2 * i
+        seq.add(2e-3, m=(-n_adc / 2, i - 2, 0), alpha=0.5 + 0.1 * i, phase=0.2 * i)
+        seq.add(n_adc * 1e-5, m=(n_adc * 1.1, 0, 0), n_adc=n_adc, flags=SPOIL)
+    rx = coils.loop_ring(obj, 3, ring_radius=0.2, coil_radius=0.08)
+    ref = oracle.simulate(obj, seq, coils=rx)
+    tol = TOL32 if precision == 32 else TOL64
+    # 79 rows x 3 coils x 2 x 64 samples per slice: the 125 samples take two slices
+    sliced = run(ps, obj, seq, rx, precision=precision, spins_per_lane=1,
+                 max_partial_bytes=79 * 3 * 2 * (precision // 8) * 64)
+    whole = run(ps, obj, seq, rx, precision=precision, spins_per_lane=1)
+    per_coil(f"odd samples sliced fp{precision}", sliced, ref, tol)
+    per_coil(f"odd samples whole fp{precision}", whole, ref, tol)
+    plain_ref = oracle.simulate(obj, seq)
+    with ps.Context(precision=precision, spins_per_lane=1) as ctx:
+        batched = ctx.simulate_batch([obj, obj.take(np.arange(777))], [seq, seq])
+        torch.cuda.synchronize()
+        b0, b1 = (t.cpu().numpy() for t in batched)
+    assert oracle.rel_l2(b0, plain_ref) <= tol
+    assert oracle.rel_l2(b1, oracle.simulate(obj.take(np.arange(777)), seq)) <= tol
+
+
 def test_many_coils_and_time_slices(ps):
     """16 coils and a partial buffer small enough to force several slices:
     every coil keeps its own block of samples in each row."""
