@@ -174,6 +174,17 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
             op.n = (uint32_t)n;
             op.flags = mxy_zero ? OPF_MXY_ZERO : 0u;
             op.u.tab.row = p.traj.size() / 4;
+            // instants on a regular raster (spirals and other trajectories
+            // sampled at a fixed dwell) let the kernel step the T2 decay from
+            // sample to sample by one factor instead of evaluating it at
+            // each sample
+            if (n >= 2) {
+                const double d = (tr->t[n - 1] - tr->t[0]) / (double)(n - 1);
+                bool even = d > 0.0;
+                for (int64_t q = 1; even && q < n; ++q)
+                    even = std::fabs(tr->t[q] - tr->t[0] - (double)q * d) <= 1e-9 * d;
+                if (even) { op.flags |= OPF_EVEN_T; op.u.tab.dt = d; }
+            }
             for (int64_t q = 0; q < n; ++q) {
                 p.traj.push_back(K[0] + tr->k[3 * q]);
                 p.traj.push_back(K[1] + tr->k[3 * q + 1]);

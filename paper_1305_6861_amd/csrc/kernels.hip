@@ -724,15 +724,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         }
                     }
                     const auto partial_c = partial + coil * a.coil_stride;
-                    if constexpr (std::is_same<real, float>::value && G > 1) {
-                        // The wave group shares its G * S spins, as in the
-                        // Cartesian readout: wave wg of the group evaluates
-                        // chunk round * G + wg for all of them, so each lane
-                        // sums 8 spins per sample, the butterfly is shared by
-                        // them and no chunk sums are added across waves.
-                        // Every spin's parameters and weighted anchor go
-                        // through LDS once per pass; rows of G chunks are
-                        // staged per round.
+                    if (std::is_same<real, float>::value && G > 1 &&
+                        (__builtin_amdgcn_readfirstlane(op.flags) & OPF_EVEN_T) != 0) {
+                        // Instants on a regular raster (every fixed-dwell
+                        // readout): the wave group shares its G * S spins, as
+                        // in the Cartesian readout: wave wg of the group
+                        // evaluates chunk round * G + wg for all of them, so
+                        // each lane sums 8 spins per sample, the butterfly is
+                        // shared by them and no chunk sums are added across
+                        // waves.  Every spin's parameters and weighted anchor
+                        // go through LDS once per pass; rows of G chunks are
+                        // staged per round.  The T2 decay inside a block of 8
+                        // samples is stepped by one factor per sample.
+                        // Uneven instants take the per-wave path below.
                         constexpr int RT = G * S;
                         float4* g_row = s_trow;                                        // [G * kT]
                         double* g_anc = reinterpret_cast<double*>(g_row + G * kT);      // [G * kT / kTB][4]
@@ -754,6 +758,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         const int w0 = (wave / G) * G;
                         const int smp_lane = readout_sample_of_lane(lane);
                         const int n_rounds = (n_chunks + G - 1) / G;
+                        const float dt_even = (float)uniform(op.u.tab.dt);
                         for (int round = 0; round < n_rounds; ++round) {
                             __syncthreads();     // parameters visible; previous round's rows read
                             if (tid < G * kT) {  // rows past n are never stored
@@ -781,12 +786,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                 return __longlong_as_double((long long)(((uint64_t)__float_as_uint(src[5 * 64]) << 32) |
                                                                         (uint64_t)__float_as_uint(src[4 * 64])));
                             };
-                            float px[RT], py[RT], pz[RT], pdw[RT], pr2l[RT];
+                            // pdec: the decay over one spacing, 2^(-dt log2(e) / T2)
+                            float px[RT], py[RT], pz[RT], pdw[RT], pdec[RT];
 #pragma unroll
                             for (int q = 0; q < RT; ++q) {
                                 const float* src = par(q);
                                 px[q] = src[0 * 64]; py[q] = src[1 * 64]; pz[q] = src[2 * 64]; pdw[q] = src[3 * 64];
-                                pr2l[q] = (float)(rate(src) * kLog2e);
+                                pdec[q] = __builtin_amdgcn_exp2f(-dt_even * (float)(rate(src) * kLog2e));
                             }
                             float red16[16];
 #pragma unroll
@@ -807,6 +813,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                     br[q] = eb * src[6 * 64]; bi[q] = eb * src[7 * 64];
                                 }
                                 float vq[16];
+                                // the block's decay E2(t - t_b) is pdec^(sample),
+                                // stepped by one product per sample folded into
+                                // (br, bi)
 #pragma unroll
                                 for (int t = 0; t < kTB; ++t) {
                                     const float4 d = g_row[wg * kT + b * kTB + t];
@@ -817,9 +826,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                         const float f = c0[q] + fmaf(d.x, px[q], fmaf(d.y, py[q], fmaf(d.z, pz[q], pdw[q] * dt_rev)));
                                         const float c = __builtin_amdgcn_cosf(f);
                                         const float sn = __builtin_amdgcn_sinf(f);
-                                        const float ed = __builtin_amdgcn_exp2f(-d.w * pr2l[q]);
-                                        sr = fmaf(ed, fmaf(br[q], c, bi[q] * sn), sr);
-                                        si = fmaf(ed, fmaf(bi[q], c, -br[q] * sn), si);
+                                        sr = fmaf(br[q], c, fmaf(bi[q], sn, sr));
+                                        si = fmaf(bi[q], c, fmaf(-br[q], sn, si));
+                                        br[q] *= pdec[q]; bi[q] *= pdec[q];
                                     }
                                     vq[2 * t] = sr; vq[2 * t + 1] = si;
                                 }

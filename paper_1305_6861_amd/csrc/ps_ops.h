@@ -32,6 +32,7 @@ enum OpKind : uint32_t {
 
 enum OpFlags : uint32_t {
     OPF_MXY_ZERO = 1u,  // Mxy_a is known to be 0 for every spin (after init/spoil)
+    OPF_EVEN_T = 2u,    // ADCT: sample instants equally spaced by u.tab.dt
 };
 
 // 128-byte operation record.
@@ -45,7 +46,8 @@ struct alignas(16) Op {
         float r32[9];                            // RF rotation, FP32 tables
         struct { double mu[3]; double tau; } adc;  // ADC: per-sample moment and
                                                    // dwell
-        struct { uint64_t row; } tab;            // ADCT: first row of its samples
+        struct { uint64_t row; double dt; } tab; // ADCT: first row of its samples;
+                                                 // spacing of the instants (OPF_EVEN_T)
         struct {
             double mu[3];       // per-sub-step moment (same place as adc.mu)
             double tau;         // sub-step duration (same place as adc.tau)

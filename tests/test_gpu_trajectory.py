@@ -102,6 +102,32 @@ def test_every_tiling(ps, S):
     check(f"spiral S={S}", run(ps, obj, seq, spins_per_lane=S), oracle.simulate(obj, seq), TOL32)
 
 
+def _spiral_table(n, t_end, power):
+    """A spiral whose instants are t_end (s / n)^power: an equal raster for
+    power 1, uneven (variable density) otherwise."""
+    u = (np.arange(n) + 1) / n
+    th = 2 * np.pi * 6 * u
+    k = np.stack([300 * u * np.cos(th), 300 * u * np.sin(th), 20 * u], axis=1)
+    return Trajectory(k=k, t=t_end * u ** power)
+
+
+@pytest.mark.parametrize("S", [1, 2, 4])
+@pytest.mark.parametrize("power", [1.0, 1.3])
+def test_even_and_uneven_instants_with_fast_decay(ps, S, power):
+    """Instants on an equal raster (the decay stepped by one factor per
+    sample) and uneven instants (the decay evaluated at every sample), with
+    T2 down to 1.5 ms so that the decay inside an 8-sample block matters,
+    on the tilings whose wave groups share their spins."""
+    obj = random_spins(2300, seed=80 + S, dw_sigma_hz=40.0)
+    obj.t2[:] = obj.t2 / 20.0
+    seq = Sequence("even" if power == 1.0 else "uneven")
+    for i in range(3):
+        j = seq.add_trajectory(_spiral_table(150 + 13 * i, 1.5e-3, power))
+        seq.add(1e-3, alpha=0.6 + 0.2 * i, phase=0.4 * i)
+        seq.add(2e-3, m=(3.0, -2.0, 1.0), n_adc=150 + 13 * i, trajectory=j)
+    check(f"instants^{power} S={S}", run(ps, obj, seq, spins_per_lane=S), oracle.simulate(obj, seq), TOL32)
+
+
 def test_split_batch_and_serve_bitwise(ps):
     import torch
     obj = random_spins(900, seed=70, dw_sigma_hz=40.0)
