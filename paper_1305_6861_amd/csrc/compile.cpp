@@ -267,7 +267,8 @@ void plan_slices(Program* p, int64_t max_samples) {
         while (done < n) {
             int64_t room = max_samples - (sample - cur.sample_begin);
             if (room <= 0) { close_slice(); room = max_samples; }
-            const int64_t take = std::min<int64_t>(room, n - done);
+            int64_t take = std::min<int64_t>(room, n - done);
+            if (op0.kind == OP_ADC) take = std::min<int64_t>(take, kAdcRun);
             Op op = op0;
             if (op0.kind == OP_ADCT) {
                 op.u.tab.row = op0.u.tab.row + (uint64_t)done;

@@ -45,7 +45,12 @@ ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* er
 
 // Cut the program into time slices of at most max_samples samples each
 // (ADC operations longer than that are split exactly), setting every ADC
-// op's offset inside its slice.  max_samples >= 1.
+// op's offset inside its slice.  max_samples >= 1.  A Cartesian readout is
+// also cut into runs of at most kAdcRun samples: each run starts from its
+// own FP64 phase, which bounds the FP32 recurrence a readout accumulates
+// (its anchor advances one multiply per wave group's 32 G samples, and the
+// rounding of that factor adds up linearly along the run).
+constexpr int64_t kAdcRun = 8192;
 void plan_slices(Program* p, int64_t max_samples);
 
 // Give every shape that occurs often (at least five times) in the program a

@@ -185,6 +185,38 @@ def test_long_readout_and_time_slicing(ps):
     assert oracle.rel_l2(b, ref) <= TOL32
 
 
+def test_readout_of_a_million_samples(ctx32, ctx64):
+    """One readout of 2^20 samples (1 us dwell) on spins without relaxation,
+    so the last samples weigh as much as the first: the recurrence is cut
+    into runs that each start from their own FP64 phase, so its rounding
+    does not build up along the readout (one unbroken FP32 run was 2.4e-4
+    off here).  The FP32 signal is checked against the oracle; the FP64 one
+    against the closed form j m0 exp(-j (2 pi k_n.x + dw t_n)) at the first
+    and last 4096 samples, since the oracle's own 2^20 sequential FP64
+    sub-steps carry ~1e-11 of rounding."""
+    obj = random_spins(600, seed=9, dw_sigma_hz=30.0, t_inf_frac=1.0)
+    n, tau, pre = 1 << 20, 1e-6, 1e-3
+    m = np.array([0.01, -0.004, 0.002]) * n
+    seq = Sequence("long1M")
+    seq.add(pre, alpha=np.pi / 2)
+    seq.add(n * tau, m=tuple(m), n_adc=n)
+    ref = oracle.simulate(obj, seq)
+    idx = np.r_[0:4096, n - 4096:n]
+    pos = np.stack([obj.x, obj.y, obj.z]).astype(np.float64)
+    k = np.outer(idx + 1, m / n)                                        # cycles/m at sample idx
+    t = pre + (idx + 1) * tau
+    ph = 2 * np.pi * (k @ pos) + t[:, None] * obj.dw.astype(np.float64)[None, :]
+    closed = (1j * obj.m0.astype(np.float64)[None, :] * np.exp(-1j * ph)).sum(axis=1)
+    got32 = gpu(ctx32, obj, seq)
+    got64 = gpu(ctx64, obj, seq)
+    e32, t32 = oracle.rel_l2(got32, ref), oracle.rel_l2(got32[-4096:], ref[-4096:])
+    e64 = oracle.rel_l2(got64[idx], closed)
+    print(f"[parity] 2^20-sample readout fp32 rel_l2={e32:.3e} (last 4096: {t32:.3e}); fp64 vs closed form "
+          f"{e64:.3e}; oracle vs closed form {oracle.rel_l2(ref[idx], closed):.3e}", flush=True)
+    assert e32 <= TOL32 and t32 <= TOL32
+    assert e64 <= TOL64
+
+
 def test_shaped_pulses_with_phase_offsets_and_hard_pulse(ctx32, ctx64):
     obj = random_spins(900, seed=5, dw_sigma_hz=200.0)
     rng = np.random.default_rng(5)
