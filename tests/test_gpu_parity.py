@@ -162,6 +162,24 @@ def test_short_readouts_every_tiling(ps, S):
         check(ctx, obj, seq, TOL32, label=f"short readouts S={S}")
 
 
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+def test_readouts_with_a_partial_last_round(ps, S):
+    """Readouts of 5, 6, 7 and 10 chunks of 32 samples (the last ragged):
+    the waves of a wave group run different numbers of chunks, each from its
+    own anchor advanced by W = z^(32 G) per round; FP64 on the tilings it
+    has."""
+    obj = random_spins(2100, seed=6 + S, dw_sigma_hz=35.0)
+    seq = Sequence("rounds")
+    for n_adc in (150, 180, 220, 300):
+        seq.add(1e-3, m=(-n_adc / 3, 2, 1), alpha=0.8, phase=0.1)
+        seq.add(n_adc * 1e-5, m=(n_adc * 0.9, 0, 0.2), n_adc=n_adc, flags=SPOIL)
+    with ps.Context(precision=32, spins_per_lane=S) as ctx:
+        check(ctx, obj, seq, TOL32, label=f"partial last round S={S}")
+    if S <= 2:
+        with ps.Context(precision=64, spins_per_lane=S) as ctx:
+            check(ctx, obj, seq, TOL64, label=f"partial last round fp64 S={S}")
+
+
 def test_long_readout_and_time_slicing(ps):
     """A 5000-sample readout forced through many time slices (small partial
     buffer).  A slice boundary inside a readout re-anchors the recurrence from
