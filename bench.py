@@ -298,6 +298,17 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def valu_calibration():
+    """The vector FMA rate the library's code generation attains (FP32 with
+    packed FP32 disabled, and FP64) next to MI355X's published vector peaks."""
+    import paper_1305_6861_amd as ps
+    with ps.Context() as ctx:
+        f32, f64 = ctx.valu_peak(32), ctx.valu_peak(64)
+    print(json.dumps({"fma_tflops_fp32": f32, "fma_tflops_fp64": f64, "published_peak_fp32": PEAK_FP32_TFLOPS,
+                      "published_peak_fp64": 78.6, "fraction_fp32": f32 / PEAK_FP32_TFLOPS,
+                      "fraction_fp64": f64 / 78.6}), flush=True)
+
+
 def copy_calibration(n_bytes: int = 1 << 30, reps: int = 5):
     """A plain copy of n_bytes (read n_bytes, write n_bytes) per launch."""
     import torch
@@ -334,9 +345,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="instead of the workload, run a plain 1 GiB device-to-device copy 5 times "
                          "(reference kernel for scaling HBM byte counters)")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="instead of the workload, measure the attainable vector FMA rate (FP32 and FP64)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.valu_calibration:
+        valu_calibration()
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

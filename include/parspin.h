@@ -329,6 +329,16 @@ ps_status ps_tile(ps_ctx *ctx, int64_t n_spins, int32_t *spins_per_lane, int64_t
 ps_status ps_kernel_times(ps_ctx *ctx, double *step_ms, int64_t capacity, int64_t *n_step,
                           double *finalize_ms);
 
+/* The vector FMA rate, in TFLOP/s (an FMA counted as 2 flops), that code
+ * built like this library's kernels attains on the context's device:
+ * 8,192 workgroups of 256 lanes run 8 independent FMA chains of 4,096 steps
+ * per lane in FP32 (precision 32; packed FP32 disabled, as for the kernels)
+ * or FP64 (precision 64); the best of 5 timed launches after one warm-up.
+ * Allocates 16 bytes of device memory for the call; synchronous.
+ * PS_E_INVALID_ARG for a NULL argument or another precision, PS_E_DEVICE on
+ * a HIP error.  Measurement support, not part of the simulation. */
+ps_status ps_valu_peak(ps_ctx *ctx, int32_t precision, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -206,6 +206,14 @@ class Context:
         _b.check(_b.lib.ps_kernel_times(self._h, buf, capacity, ctypes.byref(n), ctypes.byref(fin)))
         return [buf[i] for i in range(min(n.value, capacity))], float(fin.value)
 
+    def valu_peak(self, precision: int = 32) -> float:
+        """TFLOP/s of vector FMAs that code built like the kernels attains on
+        this context's device (FP32 with packed FP32 disabled, or FP64):
+        measurement support for the roofline, not part of the simulation."""
+        out = ctypes.c_double()
+        _b.check(_b.lib.ps_valu_peak(self._h, int(precision), ctypes.byref(out)))
+        return float(out.value)
+
     def simulate_batch(self, objs, seqs, stream=None):
         """Signals of several requests computed together (one persistent
         launch per spins-per-lane class and time-slice round); each equals,

@@ -112,6 +112,7 @@ SIGNATURES = {
     "ps_request_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ps_request_info)]),
     "ps_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "ps_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_server_stats_t)]),
+    "ps_valu_peak": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "ps_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int64)]),
     "ps_simulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -13,6 +14,7 @@
 #include "../../include/parspin.h"
 #include "compile.h"
 #include "ps_kernels.h"
+#include "calib.h"
 #include "ps_runtime.h"
 
 static_assert(sizeof(ps_event) == 64, "ps_event ABI size");
@@ -473,6 +475,47 @@ ps_status ps_tile(ps_ctx* handle, int64_t n_spins, int32_t* spins_per_lane, int6
     const int S = choose_spins_per_lane(ctx, n_spins);
     if (spins_per_lane) *spins_per_lane = S;
     if (spins_per_block) *spins_per_block = spins_per_block_of(S);
+    return PS_OK;
+}
+
+ps_status ps_valu_peak(ps_ctx* handle, int32_t precision, double* tflops) {
+    clear_error();
+    if (!handle || !tflops) return fail(PS_E_INVALID_ARG, "ctx or tflops is NULL");
+    if (precision != 32 && precision != 64) return fail(PS_E_INVALID_ARG, "precision must be 32 or 64");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    constexpr int64_t kBlocks = 8192;
+    constexpr int32_t kIters = 4096;
+    void* sink = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&sink, 16);
+    if (e == hipSuccess) e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    if (e == hipSuccess) e = launch_fma_chain(precision, kBlocks, kIters, nan, sink, st);    // warm-up
+    float best = 0.f;
+    for (int rep = 0; rep < 5 && e == hipSuccess; ++rep) {
+        float ms = 0.f;
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = launch_fma_chain(precision, kBlocks, kIters, nan, sink, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (rep == 0 || ms < best)) best = ms;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const hipError_t first = e;
+    if (e1) hipEventDestroy(e1);
+    if (e0) hipEventDestroy(e0);
+    if (st) hipStreamDestroy(st);
+    if (sink) hipFree(sink);
+    if (first != hipSuccess) return hip_fail(first, "FMA rate measurement");
+    if (!(best > 0.f)) return fail(PS_E_DEVICE, "FMA rate measurement: no elapsed time");
+    const double flops = 2.0 * 8.0 * (double)kIters * (double)kBlocks * 256.0;
+    *tflops = flops / ((double)best * 1e-3) / 1e12;
     return PS_OK;
 }
 
