@@ -178,32 +178,37 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj) {
     return PS_OK;
 }
 
-// Largest useful number of readout replicas of one tile of a program: at
-// most one per readout of its busiest slice, and few enough that the
-// repeated RF / shaped-pulse work of the replicas stays below the readout
-// work they share (per-spin estimates in VALU instructions: ~6 per sample
-// and coil, ~80 per hard pulse or snapshot, ~30 per shaped-pulse sub-step).
-int replica_bound(const Program& p, int n_out) {
+// Readout replicas of one tile of a program (ReplicaBound): the work bound
+// weighs per-spin estimates in VALU instructions, ~6 per sample and coil
+// against ~80 per hard pulse or snapshot and ~30 per shaped-pulse sub-step.
+ReplicaBound replica_bound(const Program& p, int n_out) {
     int64_t max_adc = 0;
     for (const Slice& sl : p.slices) {
         int64_t c = 0;
         for (int64_t i = sl.op_begin; i < sl.op_end; ++i) c += p.ops[i].kind == OP_ADC || p.ops[i].kind == OP_ADCT;
         max_adc = std::max(max_adc, c);
     }
-    int64_t R = std::min<int64_t>(max_adc, 64);
+    ReplicaBound b;
+    b.hard = (int)std::max<int64_t>(1, std::min<int64_t>(max_adc, 64));
+    b.work = b.hard;
     const double readout = 6.0 * (double)p.n_samples * std::max(n_out, 1);
     const double other = 80.0 * (double)(p.n_rf + p.n_snapshots) + 30.0 * (double)p.n_shape_substeps;
-    if (other > 0) R = std::min<int64_t>(R, std::max<int64_t>(1, (int64_t)(readout / other)));
-    return (int)std::max<int64_t>(R, 1);
+    if (other > 0) b.work = (int)std::max<int64_t>(1, std::min<int64_t>(b.hard, (int64_t)(readout / other)));
+    return b;
 }
 
 // Readout replicas for a launch of n_tiles workgroup tiles: none when the
-// tiles alone give every CU a workgroup, else enough for about two per CU.
-int replicas_for_load(const Ctx* ctx, int64_t n_tiles, int bound) {
+// tiles alone give every CU a workgroup.  Otherwise replicas that each get
+// a CU of their own only shorten the launch, whatever stepping they repeat
+// (up to n_CU / n_tiles of them); beyond that, about two workgroups per CU
+// while the repeated stepping stays below the readout work it splits.
+int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound) {
     if (ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) return 1;
-    const int64_t want = 2 * (int64_t)std::max(ctx->n_cu, 1);
+    const int64_t n_cu = std::max(ctx->n_cu, 1), want = 2 * n_cu;
     if (n_tiles <= 0 || n_tiles * 2 > want) return 1;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((want + n_tiles - 1) / n_tiles, bound));
+    const int64_t own = n_cu / n_tiles;
+    const int64_t shared = std::min<int64_t>((want + n_tiles - 1) / n_tiles, bound.work);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(bound.hard, std::max(own, shared)));
 }
 
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,

@@ -17,7 +17,7 @@ struct ReqPlan {
     double* signal = nullptr;
     Program prog;
     int S = 1;
-    int max_replicas = 1;              // readout replicas one tile can use
+    ReplicaBound max_replicas;         // readout replicas one tile can use
     int64_t n_blocks = 0, n_rows = 0, row_stride = 0, n_groups = 0;
     size_t bytes_partial = 0, bytes_state = 0, bytes_mid = 0, bytes_ops = 0, bytes_rows = 0, bytes_traj = 0;
     // device placement (bind)

@@ -64,10 +64,17 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S,
 int shape_cache_slots(const Ctx* ctx, int S, const Program& prog);
 ps_status wait_previous(Ctx* ctx);
 ps_status validate_receive(const ps_receive* rx, const ps_object* obj);
-// Readout replicas (see the step kernel): the useful maximum for one tile of
-// a program, and the number to launch for n_tiles tiles under that bound.
-int replica_bound(const Program& p, int n_out);
-int replicas_for_load(const Ctx* ctx, int64_t n_tiles, int bound);
+// Readout replicas (see the step kernel) a tile of a program can use: at
+// most `hard` (one per readout of its busiest slice, at most 64); replicas
+// that share a CU with others are worth it only up to `work`, where their
+// repeated RF and shaped-pulse stepping reaches the readout work they
+// split.  replicas_for_load gives the number to launch for n_tiles tiles.
+struct ReplicaBound {
+    int hard = 1;
+    int work = 1;
+};
+ReplicaBound replica_bound(const Program& p, int n_out);
+int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound);
 
 // One request compiled for a context: program, tiling and buffer sizes.
 struct Single {
