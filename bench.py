@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak (published)
+PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector peak (published)
 FLOPS_ADC_SAMPLE = 8          # p <- p z (complex multiply) and accumulate
 FLOPS_HARD_RF = 15            # 3x3 rotation of (Mx, My, Mz), eq. 3.19
 FLOPS_SHAPE_SUBSTEP = 23      # rotation + complex precession/decay + Mz recovery
@@ -305,8 +306,8 @@ def valu_calibration():
     with ps.Context() as ctx:
         f32, f64 = ctx.valu_peak(32), ctx.valu_peak(64)
     print(json.dumps({"fma_tflops_fp32": f32, "fma_tflops_fp64": f64, "published_peak_fp32": PEAK_FP32_TFLOPS,
-                      "published_peak_fp64": 78.6, "fraction_fp32": f32 / PEAK_FP32_TFLOPS,
-                      "fraction_fp64": f64 / 78.6}), flush=True)
+                      "published_peak_fp64": PEAK_FP64_TFLOPS, "fraction_fp32": f32 / PEAK_FP32_TFLOPS,
+                      "fraction_fp64": f64 / PEAK_FP64_TFLOPS}), flush=True)
 
 
 def copy_calibration(n_bytes: int = 1 << 30, reps: int = 5):
@@ -345,6 +346,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="instead of the workload, run a plain 1 GiB device-to-device copy 5 times "
                          "(reference kernel for scaling HBM byte counters)")
+    ap.add_argument("--precision", type=int, choices=(32, 64), default=32,
+                    help="32: FP32 stepping with FP64 phases and sums (default); 64: FP64 throughout")
     ap.add_argument("--valu-calibration", action="store_true",
                     help="instead of the workload, measure the attainable vector FMA rate (FP32 and FP64)")
     args = ap.parse_args()
@@ -373,7 +376,10 @@ def main():
     obj, seq = load_workload(args.workload)
     dev = ps.to_device(obj)
     cache = not args.no_shape_cache
-    ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache)
+    ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache,
+                     precision=args.precision)
+    fp64 = args.precision == 64
+    peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
     packed = ps.pack_sequence(seq)
     n_samples, n_steps = packed.count()
     rx, rx_np = None, None
@@ -426,17 +432,20 @@ def main():
     launches = len(step_ms) // max(args.steps, 1)
     k_ms = sum(step_ms) / max(args.steps, 1)
     achieved = flops / (k_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic_from_profiles(spl) if args.workload == "c2" and args.coils == 0 else None,
-            "kernel": "step_kernel<float,%d>" % spl, "kernel_ms": k_ms, "launches_per_step": launches,
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": (traffic_from_profiles(spl) if args.workload == "c2" and args.coils == 0 and not fp64
+                        else None),
+            "kernel": "step_kernel<%s,%d>" % ("double" if fp64 else "float", spl), "kernel_ms": k_ms,
+            "launches_per_step": launches,
             "kernel_ms_per_launch": k_ms / max(launches, 1),
             "flops_per_step": flops, "flops_per_launch": flops / max(launches, 1),
             "finalize_ms_per_step": fin_ms / max(args.steps, 1)}
     if args.workload == "spiral":
         roof["flops_basis"] = ("8 per spin-sample, the unit of the recurrence readout; tabulated samples are "
                                "evaluated directly (FP32 offset phase from an FP64 anchor per 8 samples, "
-                               "hardware cos/sin/exp2) at several times that cost")
+                               "hardware cos/sin, the decay stepped by one multiply per sample on the "
+                               "regular raster) at several times that cost")
     if args.plan:
         roof["kernel"] += " + finalize (one graph replay per step)"
         roof["timing"] = "HIP events around each graph replay on its stream"
@@ -446,16 +455,17 @@ def main():
         roof["flops_basis"] = "effective (sub-step path flops; shaped pulses applied from cached propagators)"
         executed = algorithmic_flops(seq, obj.n_spins, args.coils, cached_shapes=True)
         roof["executed"] = {"flops_per_step": executed, "achieved": executed / (k_ms * 1e-3) / 1e12,
-                            "frac": executed / (k_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                            "frac": executed / (k_ms * 1e-3) / 1e12 / peak,
                             "basis": "shaped pulses counted as one cached affine map (%d flops) each"
                                      % FLOPS_SHAPE_APPLY}
     rec = {"metric": "spin-steps/s", "value": value, "unit": "spin-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if fp64 else "f32",
            "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
-                      "n_samples": n_samples, "spins_per_lane": spl, "precision": "fp32 stepping, "
-                      "fp64 phases and cross-block sums", "shape_cache": cache,
+                      "n_samples": n_samples, "spins_per_lane": spl,
+                      "precision": "fp64 throughout" if fp64 else "fp32 stepping, fp64 phases and cross-block sums",
+                      "shape_cache": cache,
                       "receive_coils": args.coils or "one homogeneous coil",
                       "step": "plan replay (HIP graph)" if args.plan else "full call: compile, upload, kernels"},
            "eta_spins_per_s": obj.n_spins / (ms_per_step * 1e-3),
