@@ -59,7 +59,7 @@ constexpr int kT = 32;  // samples per reduction chunk (64 reals -> 64 lanes)
 // sample costs 4 + 2 / M instructions per spin instead of 6 (multiply, then
 // add).  The powers take registers, so FP64 keeps the plain recurrence.
 template <typename real> struct ReadoutBlock { static constexpr int M = 4; };
-template <> struct ReadoutBlock<double> { static constexpr int M = 1; };
+template <> struct ReadoutBlock<double> { static constexpr int M = 2; };
 static_assert(kT % ReadoutBlock<float>::M == 0, "a chunk holds whole readout blocks");
 
 // 16-byte LDS vectors of the readout step factors
