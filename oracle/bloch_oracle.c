@@ -4,7 +4,7 @@
  * can check the GPU library against an independent, plain, slow and
  * obviously correct implementation.  Nothing in the product path may load it.
  *
- * What it computes (section 5.1.1, "Ablauf einer spinbasierten Simulation"):
+ * What it computes (section 5.1.1, the course of a spin-based simulation):
  * every spin starts at thermal equilibrium M = (0, 0, M0).  The elementary
  * sequences are applied in order (eq. 4.1): a hard RF rotation at the start
  * of the interval (eq. 3.19), then precession about z by the gradient phase
