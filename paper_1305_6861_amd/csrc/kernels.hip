@@ -233,16 +233,64 @@ __device__ __forceinline__ void xor_stage_h(double (&v)[N], int lane) {
     }
 }
 
-__device__ __forceinline__ void quarter_reduce(double (&v)[16], int lane) {
-    xor_stage_h<32, 8>(v, lane);
-    xor_stage_h<16, 4>(v, lane);
+// The FP64 readout butterfly takes the same lane exchanges as the FP32 one,
+// each applied to the two 32-bit halves of a value (lane swaps and DPP
+// moves are pure data movement), so lane l ends with the same sample.
+__device__ __forceinline__ double join_halves(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint64_t)lo));
+}
+
+template <int H>
+__device__ __forceinline__ void perm32_stage(double (&v)[16]) {   // value i vs i + H across lanes l, l ^ 32
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const uint64_t a = (uint64_t)__double_as_longlong(v[i]), b = (uint64_t)__double_as_longlong(v[i + H]);
+        auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+        auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+        v[i] = join_halves(lo[0], hi[0]) + join_halves(lo[1], hi[1]);
+    }
+}
+
+template <int H>
+__device__ __forceinline__ void perm16_stage(double (&v)[16]) {   // value i vs i + H across lanes l, l ^ 16
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const uint64_t a = (uint64_t)__double_as_longlong(v[i]), b = (uint64_t)__double_as_longlong(v[i + H]);
+        auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+        auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+        v[i] = join_halves(lo[0], hi[0]) + join_halves(lo[1], hi[1]);
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return join_halves(lo, hi);
+}
+
+template <int CTRL, int BIT, int HALF>
+__device__ __forceinline__ void dpp_stage(double (&v)[16], int lane) {
+    const bool upper = (lane & BIT) != 0;
+#pragma unroll
+    for (int i = 0; i < HALF; ++i) {
+        const double lo = v[i] + dpp<CTRL>(v[i]);
+        const double hi = v[i + HALF] + dpp<CTRL>(v[i + HALF]);
+        v[i] = upper ? hi : lo;
+    }
+}
+
+__device__ __forceinline__ void quarter_reduce(double (&v)[16], int) {
+    perm32_stage<8>(v);
+    perm16_stage<4>(v);
 }
 
 __device__ __forceinline__ double reduce16(double (&v)[16], int lane) {
-    xor_stage_h<8, 8>(v, lane);
-    xor_stage_h<4, 4>(v, lane);
-    xor_stage_h<2, 2>(v, lane);
-    xor_stage_h<1, 1>(v, lane);
+    dpp_stage<0x140, 8, 8>(v, lane);
+    dpp_stage<0x141, 4, 4>(v, lane);
+    dpp_stage<0x4E, 2, 2>(v, lane);
+    dpp_stage<0xB1, 1, 1>(v, lane);
     return v[0];
 }
 
