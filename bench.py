@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the GPU spin stepper: spin-steps/s on one MI355X.
 
-Workload: the 2-D 256 x 256 spin-echo configuration -- 262,144 spins
-(4 jittered isochromats per voxel, dw ~ N(0, (2 pi 20 Hz)^2)), 90x/180y
-with TE 20 ms and TR 500 ms, 256 phase encodes x 256 samples: 66,304
-elementary intervals per spin, 65,536 complex samples.  One step is one
-complete simulation of that request through the C ABI (sequence compile +
-upload, step kernel, FP64 finalize) with the object already resident in
-HBM.  Prints one JSON line.
+Default workload: the 3-D configuration -- a 128^3 grid of two co-located
+species (water 0.8 rho, fat 0.2 rho at -440 Hz; 4,194,304 spins) in a
+quadratic B0 map of +-50 Hz, a spoiled GRE with a 128-sub-step TBW-4 sinc
+excitation (30 deg), TE 5 ms, TR 10 ms, 128 x 128 phase encodes (kz outer)
+x 128 samples: 4,227,072 elementary intervals per spin, 2,097,152 complex
+samples.  One step is one complete simulation of that request through the
+C ABI (sequence compile + upload, step kernels over the time slices, FP64
+finalize) with the object already resident in HBM.  Prints one JSON line.
+--workload c2 selects the 2-D 256 x 256 spin-echo configuration instead.
 
-Also reported: the step kernel's roofline position (algorithmic FP32 flops
-per launch / its mean HIP-event duration, against the FP32 vector peak),
-and the FP64 CPU oracle timed on the host on a bounded spin subset of the
-same workload (with the GPU's error against it on that subset).
+Also reported: the step kernel's roofline position (the FP32 flops it
+executes per launch / its mean HIP-event duration, against the FP32 vector
+peak; a shaped pulse applied from its cached propagator counts as that
+affine map), the FP64 CPU oracle timed on the host on a bounded spin subset
+of the same workload (with the GPU's error against it on that subset), and
+served vs one-request-per-launch latency on a prefix of the Poisson request
+stream.
 """
 from __future__ import annotations
 
@@ -89,11 +94,26 @@ def bench_c4(args):
 def bench_c5(args):
     """Poisson stream: served (continuous batching) vs FIFO one launch per
     request, both replaying the same arrival schedule in real time."""
+    rec = c5_replay(args.c5_requests)
+    print(json.dumps(rec), flush=True)
+
+
+def latency_block(n_requests: int) -> dict:
+    """Served vs FIFO one-launch-per-request latency on the first n_requests
+    of the c5 arrival schedule (Poisson, 50 requests/s)."""
+    rec = c5_replay(n_requests)
+    out = {"requests": n_requests, "arrivals": "c5 Poisson stream prefix, 50 requests/s, seed 5000",
+           "served": rec["served"], "fifo_one_per_launch": rec["fifo_one_per_launch"],
+           "served_spin_steps_per_s": rec["value"], "workload": rec["config"]["workload"]}
+    return out
+
+
+def c5_replay(n_requests: int) -> dict:
     import numpy as np
     import torch
     import paper_1305_6861_amd as ps
     from workloads import configs as C
-    sched = C.c5_stream(n_requests=args.c5_requests)
+    sched = C.c5_stream(n_requests=n_requests)
     reqs = [C.c5_request(kind, param) for _, kind, param in sched]
     devs = [ps.to_device(o) for o, _ in reqs]
     packs = [ps.pack_sequence(s) for _, s in reqs]
@@ -117,12 +137,16 @@ def bench_c5(args):
     ctx = ps.Context()
     def s_submit(i, t):
         return (t, ctx.submit(devs[i], packs[i]))
+    kernel_s, queue_s = [], []
+
     def s_finish(handles, t0):
         lat = []
         for t_sub, h in handles:
             h.wait(-1.0)
-            inf = h.info()
-            lat.append(inf["t_done"] - inf["t_submit"])
+            st = h.stats()
+            lat.append(st["t_e2e"])
+            kernel_s.append(st["t_kernel"])
+            queue_s.append(st["t_queue"])
         return np.array(lat)
     lat_s, wall_s = replay(s_submit, s_finish)
     served_iters = ctx.server_stats()["iterations"]
@@ -169,11 +193,13 @@ def bench_c5(args):
            "served": {"wall_s": wall_s, "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
                       "p50_2d_ms": pct(lat_s[~is3d], 50), "p99_2d_ms": pct(lat_s[~is3d], 99),
                       "p50_3d_ms": pct(lat_s[is3d], 50) if is3d.any() else None,
+                      "p50_queue_ms": pct(np.array(queue_s), 50),
+                      "p50_kernel_ms": pct(np.array(kernel_s), 50),
                       "iterations": served_iters},
            "fifo_one_per_launch": {"wall_s": wall_f, "p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
                                    "p50_2d_ms": pct(lat_f[~is3d], 50), "p99_2d_ms": pct(lat_f[~is3d], 99)},
            "roofline": None, "cpu_baseline": None}
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 WORKLOADS = {
@@ -215,11 +241,23 @@ def load_workload(name: str):
 
 def algorithmic_flops(seq, n_spins: int, n_coils: int = 1, cached_shapes: bool = False) -> float:
     """Each receive coil has its own readout pass over every spin-sample.
-    cached_shapes: count each shaped pulse as the application of its cached
-    affine propagator (FLOPS_SHAPE_APPLY) instead of its sub-steps."""
+    cached_shapes: count each shaped pulse that recurs (five times or more,
+    the library's rule for a propagator slot) as the application of its
+    cached affine propagator (FLOPS_SHAPE_APPLY), plus filling the slot once:
+    the three columns of the identity and the offset vector stepped through
+    its sub-steps (4 x FLOPS_SHAPE_SUBSTEP per sub-step)."""
     n_rf = int(sum(1 for a in seq.rf_alpha if a != 0.0))
-    shaped = [seq.shapes[int(s)].n_sub for s in seq.rf_shape if s >= 0]
-    shape_flops = FLOPS_SHAPE_APPLY * len(shaped) if cached_shapes else FLOPS_SHAPE_SUBSTEP * int(sum(shaped))
+    uses = {}
+    for sh in seq.rf_shape:
+        if sh >= 0:
+            uses[int(sh)] = uses.get(int(sh), 0) + 1
+    shape_flops = 0.0
+    for sid, n_use in uses.items():
+        n_sub = seq.shapes[sid].n_sub
+        if cached_shapes and n_use >= 5:
+            shape_flops += 4 * FLOPS_SHAPE_SUBSTEP * n_sub + FLOPS_SHAPE_APPLY * n_use
+        else:
+            shape_flops += FLOPS_SHAPE_SUBSTEP * n_sub * n_use
     return float(n_spins) * (FLOPS_ADC_SAMPLE * seq.n_samples * max(n_coils, 1) + FLOPS_HARD_RF * n_rf
                              + shape_flops)
 
@@ -232,10 +270,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(spl: int):
+def traffic_from_profiles(workload: str, spl: int):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source and tiling."""
-    p = os.path.join(ROOT, "profiles", "step_kernel_c2_traffic.json")
+    p = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_traffic.json")
     try:
         with open(p) as f:
             rec = json.load(f)
@@ -331,10 +369,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--spins-per-lane", type=int, default=0, help="0 = autotuned")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5"], default="c2",
-                    help="c2 (default, the reported workload), c3 (3-D shaped-pulse configuration), "
-                         "c4 (batched vs one launch per request), c5 (served stream vs FIFO)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5"], default="c3",
+                    help="c3 (default, the reported workload: 3-D shaped-pulse configuration), "
+                         "c2 (2-D spin echo), c4 (batched vs one launch per request), "
+                         "c5 (served stream vs FIFO)")
     ap.add_argument("--c5-requests", type=int, default=2000)
+    ap.add_argument("--latency-requests", type=int, default=300,
+                    help="requests of the c5 stream prefix replayed served and FIFO for the latency block "
+                         "of the default run (0: leave the block out)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", action="store_true",
@@ -426,7 +468,10 @@ def main():
     spin_steps = float(obj.n_spins) * n_steps
     ms_per_step = 1e3 * elapsed / args.steps
     value = spin_steps * args.steps / elapsed
-    flops = algorithmic_flops(seq, obj.n_spins, args.coils)
+    shaped = any(int(x) >= 0 for x in seq.rf_shape)
+    # the flops the kernel executes: a recurring shaped pulse is applied from
+    # its cached propagator (when the cache is on)
+    flops = algorithmic_flops(seq, obj.n_spins, args.coils, cached_shapes=cache)
     # a long sequence runs as several time slices (launches) per step: the
     # step's kernel time is the sum over its launches
     launches = len(step_ms) // max(args.steps, 1)
@@ -434,12 +479,14 @@ def main():
     achieved = flops / (k_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": (traffic_from_profiles(spl) if args.workload == "c2" and args.coils == 0 and not fp64
-                        else None),
+            "traffic": (traffic_from_profiles(args.workload, spl) if args.coils == 0 and not fp64 else None),
             "kernel": "step_kernel<%s,%d>" % ("double" if fp64 else "float", spl), "kernel_ms": k_ms,
             "launches_per_step": launches,
             "kernel_ms_per_launch": k_ms / max(launches, 1),
             "flops_per_step": flops, "flops_per_launch": flops / max(launches, 1),
+            "flops_basis": ("executed: 8 per ADC spin-sample, 15 per hard pulse, 23 per shaped-pulse sub-step "
+                            "stepped" + (", 18 per shaped pulse applied from its cached propagator plus the "
+                                         "fill (4 x 23 per sub-step, once)" if cache and shaped else "")),
             "finalize_ms_per_step": fin_ms / max(args.steps, 1)}
     if args.workload == "spiral":
         roof["flops_basis"] = ("8 per spin-sample, the unit of the recurrence readout; tabulated samples are "
@@ -449,15 +496,14 @@ def main():
     if args.plan:
         roof["kernel"] += " + finalize (one graph replay per step)"
         roof["timing"] = "HIP events around each graph replay on its stream"
-    if cache and any(int(x) >= 0 for x in seq.rf_shape):
-        # recurring shaped pulses applied from per-spin propagators: the flop
-        # basis is the sub-step path's, so achieved and frac are effective
-        roof["flops_basis"] = "effective (sub-step path flops; shaped pulses applied from cached propagators)"
-        executed = algorithmic_flops(seq, obj.n_spins, args.coils, cached_shapes=True)
-        roof["executed"] = {"flops_per_step": executed, "achieved": executed / (k_ms * 1e-3) / 1e12,
-                            "frac": executed / (k_ms * 1e-3) / 1e12 / peak,
-                            "basis": "shaped pulses counted as one cached affine map (%d flops) each"
-                                     % FLOPS_SHAPE_APPLY}
+    if cache and shaped:
+        # side figure: the sub-step path's flops over the same time (what the
+        # cache saves), not a roofline position
+        effective = algorithmic_flops(seq, obj.n_spins, args.coils, cached_shapes=False)
+        roof["effective"] = {"flops_per_step": effective, "tflops": effective / (k_ms * 1e-3) / 1e12,
+                             "basis": "every shaped pulse counted as its %d-flop sub-steps, which the cached "
+                                      "propagator replaces; a rate, not a fraction of the peak"
+                                      % FLOPS_SHAPE_SUBSTEP}
     rec = {"metric": "spin-steps/s", "value": value, "unit": "spin-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if fp64 else "f32",
@@ -479,6 +525,11 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(obj, seq, ctx, args.cpu_seconds, rx_np)
     else:
         rec["cpu_baseline"] = None
+    ctx.close()
+    if args.latency_requests > 0 and not args.plan and args.coils == 0 and not fp64:
+        del dev
+        torch.cuda.empty_cache()
+        rec["latency"] = latency_block(args.latency_requests)
     print(json.dumps(rec), flush=True)
 
 

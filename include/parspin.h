@@ -82,6 +82,10 @@ typedef struct ps_config {
     int64_t max_partial_bytes;   /* bound on the per-block partial-sum buffer; longer
                                     sequences run in time slices (0 = default 2 GiB)   */
     int64_t max_footprint_bytes; /* admission cap for served requests (0 = 64 GiB)     */
+    int64_t max_slice_steps;     /* served requests: at most this many elementary
+                                    intervals per spin in one scheduler iteration, so
+                                    that long requests yield the device regularly and
+                                    new ones join between their slices (0 = 65,536)    */
 } ps_config;
 
 /* Spins as structure-of-arrays, n_spins entries each, FP32, DEVICE memory
@@ -161,8 +165,12 @@ const char *ps_last_error(void);
 
 /* Number of ADC samples (the signal length) and the number of elementary
  * intervals each spin is stepped through after cutting ADC intervals into
- * their samples and shaped pulses into their sub-pulses.  Validates the
- * sequence; needs no device. */
+ * their samples and shaped pulses into their sub-pulses (section 5.1.1: an
+ * ADC elementary sequence is divided into as many steps as it has samples;
+ * eq. 3.23: a shaped pulse is a list of hard-pulse elementary sequences).
+ * Validates the sequence (PS_E_INVALID_ARG with the offending event or
+ * shape named by ps_last_error()); needs no device.  Either output pointer
+ * may be NULL. */
 ps_status ps_count(const ps_sequence *seq, int64_t *n_samples, int64_t *n_steps_per_spin);
 
 /* Simulate one request, stream-ordered on `stream`.
@@ -227,11 +235,18 @@ ps_status ps_simulate_ex(ps_ctx *ctx, const ps_object *obj, const ps_sequence *s
  *                   the grey-value step, e.g. 1/256);
  * k_max in cycles/m, and dx_max[d] = 1 / (2 k_max[d]) m, the largest spin
  * spacing free of aliasing (eq. 5.2 with k in cycles/m; +inf where k_max is
- * 0).  *n_configs_peak (may be NULL): the most transverse configurations
- * populated at once.  PS_E_INVALID_ARG for a moment off the lattice or an
- * invalid sequence, PS_E_TOO_LARGE past 2^22 configurations. */
+ * 0).  extent (HOST, may be NULL): the object's size per axis in m (0 on an
+ * axis it does not span); then *n_spins_min receives the isochromats one
+ * tissue class needs to cover it at that spacing, the product over the axes
+ * with extent > 0 and a finite dx_max of ceil(extent / dx_max) (1 when no
+ * axis counts).  n_spins_min may be NULL, and must be when extent is.
+ * *n_configs_peak (may be NULL): the most transverse configurations
+ * populated at once.  PS_E_INVALID_ARG for a moment off the lattice, an
+ * invalid sequence or a negative / non-finite extent; PS_E_TOO_LARGE past
+ * 2^22 configurations or a spin count beyond 2^62. */
 ps_status ps_kt_extent(const ps_sequence *seq, const double dk[3], double t1, double t2, double grey_step,
-                       double k_max[3], double dx_max[3], int64_t *n_configs_peak);
+                       const double extent[3], double k_max[3], double dx_max[3], int64_t *n_spins_min,
+                       int64_t *n_configs_peak);
 
 /* Compiled plans: one request compiled once and its kernel launches captured
  * in a HIP graph, for callers that simulate the same (object layout,
@@ -288,6 +303,8 @@ typedef struct ps_request_info_t {
     int64_t n_slices;            /* time slices the request runs as                    */
     int64_t footprint_bytes;     /* counted against the admission cap                  */
     int64_t n_spins, n_steps_per_spin;
+    double  t_kernel;            /* s of device time of the iterations it ran in (see
+                                    ps_stats)                                          */
 } ps_request_info_t;
 
 typedef struct ps_server_stats_t {
@@ -310,6 +327,19 @@ ps_status ps_wait(ps_ctx *ctx, uint64_t ticket, double timeout_s);
 ps_status ps_cancel(ps_ctx *ctx, uint64_t ticket);
 /* State, status and timing of a request. */
 ps_status ps_request_info(ps_ctx *ctx, uint64_t ticket, ps_request_info_t *out);
+/* Timing of a served request (the bookkeeping of the paper's master, section
+ * 6.3, and the simulation time of eq. 7.1), in seconds:
+ *   t_queue  from ps_submit to admission (waiting for the footprint cap or
+ *            for a large request ahead of it);
+ *   t_kernel device time of the scheduler iterations the request ran in:
+ *            for each, the span from the start of its first kernel to the end
+ *            of its last one, measured with HIP events.  Requests admitted
+ *            together share an iteration's kernels, so each is charged the
+ *            whole span (the time the device spent with it in flight);
+ *   t_e2e    from ps_submit to completion.
+ * Values not known yet (a request still queued or running) are -1; any
+ * output pointer may be NULL.  PS_E_INVALID_ARG for an unknown ticket. */
+ps_status ps_stats(ps_ctx *ctx, uint64_t ticket, double *t_queue, double *t_kernel, double *t_e2e);
 /* Forget a finished request's record (PS_E_NOT_READY while in flight). */
 ps_status ps_release(ps_ctx *ctx, uint64_t ticket);
 /* Scheduler counters (all zero before the first ps_submit). */

@@ -213,14 +213,16 @@ def stoerabstand_db(test, ref) -> float:
     return float(20.0 * np.log10(r)) if r > 0 else float("-inf")
 
 
-def count_over_threshold(test, ref, rel_threshold: float, eps_scale: float = 1e3) -> int:
+def count_over_threshold(test, ref, rel_threshold: float, eps_scale: float = 1e3, eps: Optional[float] = None) -> int:
     """Number of sample components whose relative error exceeds rel_threshold,
     skipping components whose reference magnitude lies within
-    eps_scale * machine-eps of the largest (section 5.4.2)."""
+    eps_scale * eps of the largest (section 5.4.2); eps is the machine
+    epsilon of the arithmetic under test (default FP64)."""
     t = np.asarray(test); r = np.asarray(ref)
     comps_t = np.concatenate([t.real.ravel(), t.imag.ravel()])
     comps_r = np.concatenate([r.real.ravel(), r.imag.ravel()])
-    floor = eps_scale * np.finfo(np.float64).eps * max(np.max(np.abs(comps_r)), 1e-300)
+    eps = float(np.finfo(np.float64).eps) if eps is None else float(eps)
+    floor = eps_scale * eps * max(np.max(np.abs(comps_r)), 1e-300)
     sel = np.abs(comps_r) > floor
     rel = np.abs(comps_t[sel] - comps_r[sel]) / np.abs(comps_r[sel])
     return int(np.count_nonzero(rel > rel_threshold))

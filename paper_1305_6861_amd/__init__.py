@@ -29,7 +29,7 @@ from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT, PS_EV_TRAJECTORY
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
 __all__ = ["Context", "Plan", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence",
-           "to_device", "kt_extent", "min_spins", "FIELDS"]
+           "to_device", "kt_extent", "FIELDS"]
 
 
 class PackedSequence:
@@ -105,29 +105,26 @@ def count(seq):
     return pack_sequence(seq).count()
 
 
-def kt_extent(seq, dk, t1: float, t2: float, grey_step: float = 0.0) -> dict:
+def kt_extent(seq, dk, t1: float, t2: float, grey_step: float = 0.0, extent=None) -> dict:
     """Spin spacing the sequence needs (ps_kt_extent, section 5.2): k_max and
     dx_max per axis (cycles/m, m) for lattice steps dk (cycles/m per axis)
     and the reference tissue (t1, t2); grey_step > 0 leaves out outer
-    configurations too weak to show at that grey-value step (eq. 5.4 / 5.5)."""
+    configurations too weak to show at that grey-value step (eq. 5.4 / 5.5).
+    With the object's extent (m per axis) also n_spins_min, the isochromats
+    one tissue class needs at that spacing (eq. 5.2)."""
     ps = pack_sequence(seq)
     dkv = (ctypes.c_double * 3)(*[float(v) for v in dk])
+    ext = None if extent is None else (ctypes.c_double * 3)(*[float(v) for v in extent])
     km = (ctypes.c_double * 3)()
     dx = (ctypes.c_double * 3)()
+    n_min = ctypes.c_int64()
     peak = ctypes.c_int64()
-    _b.check(_b.lib.ps_kt_extent(ctypes.byref(ps.struct), dkv, float(t1), float(t2), float(grey_step), km, dx,
-                                 ctypes.byref(peak)))
-    return {"k_max": np.array(km[:]), "dx_max": np.array(dx[:]), "n_configs_peak": int(peak.value)}
-
-
-def min_spins(extent_m, dx_max) -> int:
-    """Spins needed to cover an object of the given extent (m per axis) at
-    the spacing dx_max per axis (eq. 5.2): prod ceil(extent / dx_max)."""
-    n = 1
-    for e, d in zip(extent_m, dx_max):
-        if e > 0 and np.isfinite(d):
-            n *= int(np.ceil(e / d))
-    return n
+    _b.check(_b.lib.ps_kt_extent(ctypes.byref(ps.struct), dkv, float(t1), float(t2), float(grey_step), ext, km, dx,
+                                 ctypes.byref(n_min) if ext is not None else None, ctypes.byref(peak)))
+    out = {"k_max": np.array(km[:]), "dx_max": np.array(dx[:]), "n_configs_peak": int(peak.value)}
+    if ext is not None:
+        out["n_spins_min"] = int(n_min.value)
+    return out
 
 
 def to_device(obj, device="cuda"):
@@ -155,7 +152,7 @@ class Context:
 
     def __init__(self, device: int = 0, precision: int = 32, spins_per_lane: int = 0,
                  max_partial_bytes: int = 0, max_footprint_bytes: int = 0, kernel_timing: bool = False,
-                 shape_cache: bool = True, readout_split: bool = True):
+                 shape_cache: bool = True, readout_split: bool = True, max_slice_steps: int = 0):
         cfg = _b.ps_config()
         _b.check(_b.lib.ps_config_default(ctypes.byref(cfg)))
         cfg.device = device
@@ -168,6 +165,8 @@ class Context:
             cfg.max_partial_bytes = max_partial_bytes
         if max_footprint_bytes:
             cfg.max_footprint_bytes = max_footprint_bytes
+        if max_slice_steps:
+            cfg.max_slice_steps = max_slice_steps
         h = ctypes.c_void_p()
         _b.check(_b.lib.ps_create(ctypes.byref(h), ctypes.byref(cfg)))
         self._h = h
@@ -431,6 +430,12 @@ class Ticket:
         d = {f: getattr(i, f) for f, _ in i._fields_}
         d["state"] = _b.REQ_STATES.get(d["state"], d["state"])
         return d
+
+    def stats(self) -> dict:
+        """(ps_stats) t_queue, t_kernel and t_e2e in seconds; -1 where not known yet."""
+        q, k, e = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _b.check(_b.lib.ps_stats(self.ctx._h, self.ticket, ctypes.byref(q), ctypes.byref(k), ctypes.byref(e)))
+        return {"t_queue": q.value, "t_kernel": k.value, "t_e2e": e.value}
 
     def release(self):
         _b.check(_b.lib.ps_release(self.ctx._h, self.ticket))

@@ -32,7 +32,8 @@ class PsError(RuntimeError):
 class ps_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("spins_per_lane", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("max_partial_bytes", ctypes.c_int64), ("max_footprint_bytes", ctypes.c_int64)]
+                ("max_partial_bytes", ctypes.c_int64), ("max_footprint_bytes", ctypes.c_int64),
+                ("max_slice_steps", ctypes.c_int64)]
 
 
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -75,13 +76,13 @@ assert ctypes.sizeof(ps_event) == 64
 assert ctypes.sizeof(ps_trajectory) == 24
 assert ctypes.sizeof(ps_sequence) == 40
 assert ctypes.sizeof(ps_rf_shape) == 56
-assert ctypes.sizeof(ps_config) == 32
+assert ctypes.sizeof(ps_config) == 40
 
 class ps_request_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("n_slices", ctypes.c_int64),
                 ("footprint_bytes", ctypes.c_int64), ("n_spins", ctypes.c_int64),
-                ("n_steps_per_spin", ctypes.c_int64)]
+                ("n_steps_per_spin", ctypes.c_int64), ("t_kernel", ctypes.c_double)]
 
 
 class ps_server_stats_t(ctypes.Structure):
@@ -127,7 +128,10 @@ SIGNATURES = {
     "ps_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "ps_kt_extent": (ctypes.c_int, [ctypes.POINTER(ps_sequence), ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
-                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "ps_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "ps_plan_destroy": (None, [ctypes.c_void_p]),
     "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                       ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,

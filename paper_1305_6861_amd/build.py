@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libparspin.so")
-SOURCES = ["kernels.hip", "calib.hip", "compile.cpp", "api.cpp", "batch.cpp", "server.cpp", "plan.cpp", "kt.cpp"]
+SOURCES = ["kernels.hip", "calib.hip", "compile.cpp", "api.cpp", "batch.cpp", "server.cpp",
+           "plan.cpp", "kt.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

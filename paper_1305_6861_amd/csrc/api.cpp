@@ -19,7 +19,7 @@
 
 static_assert(sizeof(ps_event) == 64, "ps_event ABI size");
 static_assert(sizeof(ps_rf_shape) == 56, "ps_rf_shape ABI size");
-static_assert(sizeof(ps_config) == 32, "ps_config ABI size");
+static_assert(sizeof(ps_config) == 40, "ps_config ABI size");
 static_assert(sizeof(ps_object) == 64, "ps_object ABI size");
 static_assert(sizeof(ps_sequence) == 40, "ps_sequence ABI size");
 static_assert(sizeof(ps_trajectory) == 24, "ps_trajectory ABI size");
@@ -122,13 +122,14 @@ int shape_cache_slots(const Ctx* ctx, int S, const Program& prog) {
 // Compile + slice a request for a given number of partial-sum rows, spins
 // per lane and receive coils (every coil has its own samples in each row).
 ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils,
-                  bool snapshots) {
+                  bool snapshots, int64_t max_partial_bytes) {
     std::string err;
     ps_status st = compile_sequence(seq, prog, &err, snapshots);
     if (st != PS_OK) return fail(st, err);
     const int64_t real_bytes = ctx->cfg.precision == 64 ? 8 : 4;
     const int64_t per_sample = std::max<int64_t>(n_rows, 1) * 2 * real_bytes * std::max(n_coils, 1);
-    int64_t max_samples = ctx->cfg.max_partial_bytes / per_sample;
+    const int64_t budget = max_partial_bytes > 0 ? max_partial_bytes : ctx->cfg.max_partial_bytes;
+    int64_t max_samples = budget / per_sample;
     if (max_samples < 64) max_samples = 64;
     plan_slices(prog, max_samples);
     assign_shape_slots(prog, shape_cache_slots(ctx, S, *prog));
@@ -136,36 +137,65 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S,
     return PS_OK;
 }
 
-// Upload program tables into the context's buffers (stream-ordered).
-ps_status upload(Ctx* ctx, const Program& prog, hipStream_t stream) {
+// Upload program tables into a buffer set (stream-ordered).
+static ps_status upload(BufSet* b, const Program& prog, hipStream_t stream) {
     const size_t ops_bytes = prog.ops.size() * sizeof(Op);
     const size_t rows_bytes = prog.rows.size() * sizeof(double);
     const size_t traj_bytes = prog.traj.size() * sizeof(double);
     ps_status st;
-    if ((st = ctx->ops.reserve(ops_bytes)) != PS_OK) return st;
-    if ((st = ctx->rows.reserve(rows_bytes)) != PS_OK) return st;
-    if ((st = ctx->traj.reserve(traj_bytes)) != PS_OK) return st;
-    if ((st = ctx->staging.reserve(ops_bytes + rows_bytes + traj_bytes)) != PS_OK) return st;
-    unsigned char* h = reinterpret_cast<unsigned char*>(ctx->staging.ptr);
+    if ((st = b->ops.reserve(ops_bytes)) != PS_OK) return st;
+    if ((st = b->rows.reserve(rows_bytes)) != PS_OK) return st;
+    if ((st = b->traj.reserve(traj_bytes)) != PS_OK) return st;
+    if ((st = b->staging.reserve(ops_bytes + rows_bytes + traj_bytes)) != PS_OK) return st;
+    unsigned char* h = reinterpret_cast<unsigned char*>(b->staging.ptr);
     if (ops_bytes) std::memcpy(h, prog.ops.data(), ops_bytes);
     if (rows_bytes) std::memcpy(h + ops_bytes, prog.rows.data(), rows_bytes);
     if (traj_bytes) std::memcpy(h + ops_bytes + rows_bytes, prog.traj.data(), traj_bytes);
     hipError_t e;
-    if (ops_bytes && (e = hipMemcpyAsync(ctx->ops.ptr, h, ops_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    if (ops_bytes && (e = hipMemcpyAsync(b->ops.ptr, h, ops_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ops)");
-    if (rows_bytes && (e = hipMemcpyAsync(ctx->rows.ptr, h + ops_bytes, rows_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    if (rows_bytes && (e = hipMemcpyAsync(b->rows.ptr, h + ops_bytes, rows_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(rows)");
-    if (traj_bytes && (e = hipMemcpyAsync(ctx->traj.ptr, h + ops_bytes + rows_bytes, traj_bytes,
+    if (traj_bytes && (e = hipMemcpyAsync(b->traj.ptr, h + ops_bytes + rows_bytes, traj_bytes,
                                           hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(trajectories)");
     return PS_OK;
 }
 
-ps_status wait_previous(Ctx* ctx) {
-    if (!ctx->pending) return PS_OK;
-    hipError_t e = hipEventSynchronize(ctx->done);
-    ctx->pending = false;
+void BufSet::release() {
+    ops.release(); rows.release(); traj.release(); partial.release(); state.release(); fin_scratch.release();
+    batch_tables.release(); batch_records.release();
+    staging.release(); staging2.release();
+}
+
+ps_status acquire_set(Ctx* ctx, BufSet** out) {
+    for (int k = 0; k < kBufSets; ++k) {
+        const int idx = (ctx->next_set + k) % kBufSets;
+        BufSet& b = ctx->sets[idx];
+        if (b.pending) {
+            const hipError_t q = hipEventQuery(b.done);
+            if (q == hipErrorNotReady) continue;
+            b.pending = false;
+            if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+        }
+        ctx->next_set = (idx + 1) % kBufSets;
+        *out = &b;
+        return PS_OK;
+    }
+    // every set is in use: wait for the oldest
+    BufSet& b = ctx->sets[ctx->next_set];
+    const hipError_t e = hipEventSynchronize(b.done);
+    b.pending = false;
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    ctx->next_set = (ctx->next_set + 1) % kBufSets;
+    *out = &b;
+    return PS_OK;
+}
+
+ps_status release_set_after(BufSet* b, hipStream_t stream) {
+    const hipError_t e = hipEventRecord(b->done, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    b->pending = true;
     return PS_OK;
 }
 
@@ -213,7 +243,7 @@ int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound) {
 
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
                       double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
-                      Single* r) {
+                      Single* r, int64_t max_partial_bytes) {
     // n_snapshots < 0: snapshot flags are ignored (entry points without them)
     ps_status st = validate_object(obj);
     if (st != PS_OK) return st;
@@ -225,7 +255,8 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->n_blocks = (obj->n_spins + spb - 1) / spb;
     r->n_rows = r->n_blocks * rows_per_block_of(r->S);
     const bool want_snaps = n_snapshots >= 0;
-    if ((st = prepare(ctx, seq, r->n_rows, r->S, &r->prog, r->n_coils, want_snaps)) != PS_OK) return st;
+    if ((st = prepare(ctx, seq, r->n_rows, r->S, &r->prog, r->n_coils, want_snaps, max_partial_bytes)) != PS_OK)
+        return st;
     const Program& prog = r->prog;
     if (n_samples != prog.n_samples)
         return fail(PS_E_INVALID_ARG, "n_samples (" + std::to_string(n_samples) + ") differs from the sequence's " +
@@ -251,7 +282,7 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->partial_bytes = (size_t)(r->n_rows * r->row_stride * real_bytes);
     r->fin_bytes = (size_t)finalize_scratch_doubles(r->n_rows, r->row_stride) * sizeof(double);
     r->state_bytes = prog.slices.size() > 1
-                         ? (size_t)((3 + (int64_t)kShapeCacheReals * prog.n_state_slots) * obj->n_spins * real_bytes)
+                         ? (size_t)(state_reals_per_spin(prog.n_state_slots) * obj->n_spins * real_bytes)
                          : 0;
     r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out));
     return PS_OK;
@@ -295,6 +326,7 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
         a.n_ops = (int32_t)(sl.op_end - sl.op_begin);
         a.load_state = i > 0;
         a.save_state = i + 1 < prog.slices.size();
+        a.anchor_parity = (int32_t)(i & 1);
         a.n_cache_slots = sl.n_cache_slots;
         a.cache_load = sl.cache_load;
         a.cache_save = sl.cache_save;
@@ -331,19 +363,20 @@ ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, do
     ps_status st = plan_single(ctx, obj, seq, rx, signal, n_samples, snaps, n_snapshots, S_override, &r);
     if (st != PS_OK) return st;
     if (r.empty()) return enqueue_single(ctx, r, SingleBuffers{}, stream, nullptr);
-    if ((st = wait_previous(ctx)) != PS_OK) return st;
-    if ((st = ctx->partial.reserve(r.partial_bytes)) != PS_OK) return st;
-    if (r.fin_bytes > 0 && (st = ctx->fin_scratch.reserve(r.fin_bytes)) != PS_OK) return st;
-    if (r.state_bytes > 0 && (st = ctx->state.reserve(r.state_bytes)) != PS_OK) return st;
-    if ((st = upload(ctx, r.prog, stream)) != PS_OK) return st;
-    SingleBuffers b{ctx->ops.ptr, ctx->rows.ptr, ctx->traj.ptr, ctx->partial.ptr, ctx->state.ptr,
-                    reinterpret_cast<double*>(ctx->fin_scratch.ptr)};
+    BufSet* set = nullptr;
+    if ((st = acquire_set(ctx, &set)) != PS_OK) return st;
+    if ((st = set->partial.reserve(r.partial_bytes)) != PS_OK) return st;
+    if (r.fin_bytes > 0 && (st = set->fin_scratch.reserve(r.fin_bytes)) != PS_OK) return st;
+    if (r.state_bytes > 0 && (st = set->state.reserve(r.state_bytes)) != PS_OK) return st;
+    if ((st = upload(set, r.prog, stream)) != PS_OK) return st;
+    SingleBuffers b{set->ops.ptr, set->rows.ptr, set->traj.ptr, set->partial.ptr, set->state.ptr,
+                    reinterpret_cast<double*>(set->fin_scratch.ptr)};
     const bool timing = (ctx->cfg.flags & PS_CFG_KERNEL_TIMING) != 0;
-    if ((st = enqueue_single(ctx, r, b, stream, timing ? ctx : nullptr)) != PS_OK) return st;
-    hipError_t e;
-    if ((e = hipEventRecord(ctx->done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    ctx->pending = true;
-    return PS_OK;
+    // the set's tables are being copied on `stream`: whatever happens next,
+    // the set is not reused before that work completes
+    const ps_status enq = enqueue_single(ctx, r, b, stream, timing ? ctx : nullptr);
+    st = release_set_after(set, stream);
+    return enq != PS_OK ? enq : st;
 }
 
 }  // namespace ps
@@ -360,6 +393,7 @@ ps_status ps_config_default(ps_config* cfg) {
     cfg->spins_per_lane = 0;
     cfg->max_partial_bytes = 2ll << 30;
     cfg->max_footprint_bytes = 64ll << 30;
+    cfg->max_slice_steps = 65536;
     return PS_OK;
 }
 
@@ -377,6 +411,8 @@ ps_status ps_create(ps_ctx** out, const ps_config* cfg_in) {
     }
     if (cfg.max_partial_bytes <= 0) cfg.max_partial_bytes = 2ll << 30;
     if (cfg.max_footprint_bytes <= 0) cfg.max_footprint_bytes = 64ll << 30;
+    if (cfg.max_slice_steps < 0) return fail(PS_E_INVALID_ARG, "max_slice_steps < 0");
+    if (cfg.max_slice_steps == 0) cfg.max_slice_steps = 65536;
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || count <= 0) return fail(PS_E_NO_DEVICE, "no HIP device visible");
@@ -390,9 +426,13 @@ ps_status ps_create(ps_ctx** out, const ps_config* cfg_in) {
     ctx->cfg = cfg;
     ctx->n_cu = prop.multiProcessorCount;
     DeviceGuard g(cfg.device);
-    if ((e = hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming)) != hipSuccess) {
-        delete ctx;
-        return hip_fail(e, "hipEventCreate");
+    for (BufSet& b : ctx->sets) {
+        if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) {
+            for (BufSet& c : ctx->sets)
+                if (c.done) hipEventDestroy(c.done);
+            delete ctx;
+            return hip_fail(e, "hipEventCreate");
+        }
     }
     *out = reinterpret_cast<ps_ctx*>(ctx);
     return PS_OK;
@@ -404,15 +444,14 @@ void ps_destroy(ps_ctx* handle) {
     {
         DeviceGuard g(ctx->cfg.device);
         destroy_runtime(ctx);
-        if (ctx->pending) hipEventSynchronize(ctx->done);
-        hipEventDestroy(ctx->done);
+        for (BufSet& b : ctx->sets) {
+            if (b.pending) hipEventSynchronize(b.done);
+            hipEventDestroy(b.done);
+        }
         for (auto& m : ctx->step_marks) { hipEventDestroy(m.first); hipEventDestroy(m.second); }
         for (auto& m : ctx->fin_marks) hipEventDestroy(m.second);   // m.first is a step mark
         for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
-        ctx->ops.release(); ctx->rows.release(); ctx->traj.release(); ctx->partial.release(); ctx->state.release();
-        ctx->fin_scratch.release(); ctx->batch_tables.release(); ctx->batch_records.release();
-        ctx->staging2.release();
-        ctx->staging.release();
+        for (BufSet& b : ctx->sets) b.release();
     }
     delete ctx;
 }

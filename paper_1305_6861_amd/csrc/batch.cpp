@@ -87,7 +87,7 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
     const size_t rb = ctx->cfg.precision == 64 ? 8 : 4;
     p->bytes_partial = align_up((size_t)(p->n_rows * p->row_stride) * rb);
     p->bytes_state = p->prog.slices.size() > 1
-                         ? align_up((size_t)((3 + (int64_t)kShapeCacheReals * p->prog.n_state_slots) * obj->n_spins) * rb)
+                         ? align_up((size_t)(state_reals_per_spin(p->prog.n_state_slots) * obj->n_spins) * rb)
                          : 0;
     p->bytes_mid = p->n_groups > 1 ? align_up((size_t)(p->n_groups * p->row_stride) * sizeof(double)) : 0;
     p->bytes_ops = align_up(p->prog.ops.size() * sizeof(Op));
@@ -138,6 +138,7 @@ StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     a.state = d_state;
     a.load_state = k > 0;
     a.save_state = k + 1 < prog.slices.size();
+    a.anchor_parity = (int32_t)(k & 1);
     a.n_cache_slots = sl.n_cache_slots;
     a.cache_load = sl.cache_load;
     a.cache_save = sl.cache_save;
@@ -399,15 +400,16 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
             if (sts[i] != PS_OK) return fail(sts[i], "request " + std::to_string(i) + ": " + errs[i]);
     }
     ps_status st;
-    if ((st = wait_previous(ctx)) != PS_OK) return st;
+    BufSet* set = nullptr;
+    if ((st = acquire_set(ctx, &set)) != PS_OK) return st;
     // all requests' tables first (one upload), then their work buffers
     size_t tables = 0, total = 0;
     for (ReqPlan& p : plans) {
         tables += p.table_bytes();
         total += p.device_bytes();
     }
-    if ((st = ctx->batch_tables.reserve(std::max<size_t>(total, 256))) != PS_OK) return st;
-    unsigned char* tbase = reinterpret_cast<unsigned char*>(ctx->batch_tables.ptr);
+    if ((st = set->batch_tables.reserve(std::max<size_t>(total, 256))) != PS_OK) return st;
+    unsigned char* tbase = reinterpret_cast<unsigned char*>(set->batch_tables.ptr);
     unsigned char* base = tbase + tables;
     std::vector<ReqPlan*> ptrs;
     std::vector<ReqPlan*> with_tables;
@@ -429,12 +431,9 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
         count.push_back(p.prog.slices.size());
     }
     if (ptrs.empty()) return PS_OK;
-    if ((st = upload_tables_contiguous(with_tables, ctx->batch_tables.ptr, ctx->staging, stream)) != PS_OK)
-        return st;
-    if ((st = run_rounds(ctx, ptrs, first, count, stream, ctx->batch_records, ctx->staging2, nullptr)) != PS_OK)
-        return st;
-    hipError_t e = hipEventRecord(ctx->done, stream);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    ctx->pending = true;
-    return PS_OK;
+    st = upload_tables_contiguous(with_tables, set->batch_tables.ptr, set->staging, stream);
+    if (st == PS_OK) st = run_rounds(ctx, ptrs, first, count, stream, set->batch_records, set->staging2, nullptr);
+    // the set's staging may be in a copy on `stream` even after a failure
+    const ps_status rel = release_set_after(set, stream);
+    return st != PS_OK ? st : rel;
 }

@@ -493,10 +493,30 @@ __device__ __forceinline__ void shape_fill(const Spins<real, S>& sp, const Op& o
 }
 
 // M <- Rz(phi) (A Rz(-phi) M + b) with (cos phi, sin phi) = (c, sn), from
-// the lane's slot entries; turn == false means phi = 0.
+// the lane's slot entries; turn == false means phi = 0.  With mxy_zero the
+// magnetisation is (0, 0, Mz), which Rz(-phi) leaves alone and on which only
+// the third column of A acts.
 template <typename real, int S>
-__device__ __forceinline__ void shape_apply(const real* cache, bool turn, real c, real sn, real (&mx)[S],
-                                            real (&my)[S], real (&mz)[S]) {
+__device__ __forceinline__ void shape_apply(const real* cache, bool turn, real c, real sn, bool mxy_zero,
+                                            real (&mx)[S], real (&my)[S], real (&mz)[S]) {
+    if (mxy_zero) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const real z = mz[s];
+            const real* e = cache + s * kBlock;
+            real nx = fma(e[2 * S * kBlock], z, e[9 * S * kBlock]);
+            real ny = fma(e[5 * S * kBlock], z, e[10 * S * kBlock]);
+            mz[s] = fma(e[8 * S * kBlock], z, e[11 * S * kBlock]);
+            if (turn) {
+                const real x0 = nx;
+                nx = fma(c, x0, -sn * ny);
+                ny = fma(c, ny, sn * x0);
+            }
+            mx[s] = nx;
+            my[s] = ny;
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         real x = mx[s], y = my[s];
@@ -562,7 +582,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
             sp.r1[s] = 1.0 / (double)gmem(a.t1)[i];
             sp.r2[s] = 1.0 / (double)gmem(a.t2)[i];
             if (a.load_state) {
-                const auto st = gmem(reinterpret_cast<const real*>(a.state));
+                const auto st = gmem(reinterpret_cast<const real*>(a.state)) +
+                                (int64_t)(3 * (a.anchor_parity ^ 1)) * a.n_spins;
                 sp.ar[s] = st[i]; sp.ai[s] = st[a.n_spins + i]; sp.az[s] = st[2 * a.n_spins + i];
             } else {
                 sp.ar[s] = 0; sp.ai[s] = 0; sp.az[s] = (real)sp.m0[s];
@@ -587,7 +608,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 #pragma unroll
                 for (int e = 0; e < kShapeCacheReals; ++e)
                     cache[(e * S + s) * kBlock] =
-                        i < a.n_spins ? st[(3 + kShapeCacheReals * slot + e) * a.n_spins + i] : (real)0;
+                        i < a.n_spins ? st[(kStateSlot0 + kShapeCacheReals * slot + e) * a.n_spins + i] : (real)0;
             }
         }
     }
@@ -676,7 +697,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                   tid;
                     if (mode == SHAPE_FILL) shape_fill<real, S>(sp, op, rows, n_sub, cache);
                     const double rc = op.u.shape.rot[0], rs = op.u.shape.rot[1];
-                    shape_apply<real, S>(cache, rc != 1.0 || rs != 0.0, (real)rc, (real)rs, ex, ey, ez);
+                    shape_apply<real, S>(cache, rc != 1.0 || rs != 0.0, (real)rc, (real)rs, mxy_zero, ex, ey, ez);
 #pragma unroll
                     for (int s = 0; s < S; ++s) { sp.ar[s] = ex[s]; sp.ai[s] = ey[s]; sp.az[s] = ez[s]; }
                     continue;
@@ -1183,13 +1204,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                             for (int i = 0; i < 4; ++i) red[4 * h + i] = v[i];
                         }
                         if constexpr (P == 1) {
+                            if (j + G < j_end) {           // this wave has another chunk
 #pragma unroll
-                            for (int q = 0; q < RS; ++q) {     // advance G chunks from the anchor
-                                real w_r, w_i;
-                                factor(q % S, (w0 + q / S) * 64 + lane, SF::kW, w_r, w_i);
-                                const real a_ = pr[q], b_ = pi[q];
-                                pr[q] = a_ * w_r - b_ * w_i;
-                                pi[q] = a_ * w_i + b_ * w_r;
+                                for (int q = 0; q < RS; ++q) {     // advance G chunks from the anchor
+                                    real w_r, w_i;
+                                    factor(q % S, (w0 + q / S) * 64 + lane, SF::kW, w_r, w_i);
+                                    const real a_ = pr[q], b_ = pi[q];
+                                    pr[q] = a_ * w_r - b_ * w_i;
+                                    pi[q] = a_ * w_i + b_ * w_r;
+                                }
                             }
                         }
                         real v = reduce16(red, lane);
@@ -1219,11 +1242,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 
     if (a.save_state && rep == 0) {
         const auto st = gmem(reinterpret_cast<real*>(a.state));
+        const auto sa = st + (int64_t)(3 * a.anchor_parity) * a.n_spins;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t i = base + s * 64 + lane;
             if (i < a.n_spins) {
-                st[i] = sp.ar[s]; st[a.n_spins + i] = sp.ai[s]; st[2 * a.n_spins + i] = sp.az[s];
+                sa[i] = sp.ar[s]; sa[a.n_spins + i] = sp.ai[s]; sa[2 * a.n_spins + i] = sp.az[s];
             }
         }
         for (int slot = 0; slot < kShapeSlots; ++slot) {
@@ -1235,7 +1259,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 if (i < a.n_spins) {
 #pragma unroll
                     for (int e = 0; e < kShapeCacheReals; ++e)
-                        st[(3 + kShapeCacheReals * slot + e) * a.n_spins + i] = cache[(e * S + s) * kBlock];
+                        st[(kStateSlot0 + kShapeCacheReals * slot + e) * a.n_spins + i] = cache[(e * S + s) * kBlock];
                 }
             }
         }

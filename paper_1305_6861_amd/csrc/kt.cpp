@@ -141,9 +141,15 @@ bool lattice(const double m[3], const double dk[3], int64_t q[3]) {
 using namespace ps;
 
 extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3], double t1, double t2,
-                                  double grey_step, double k_max[3], double dx_max[3], int64_t* n_configs_peak) {
+                                  double grey_step, const double extent[3], double k_max[3], double dx_max[3],
+                                  int64_t* n_spins_min, int64_t* n_configs_peak) {
     clear_error();
     if (!seq || !dk_in || !k_max || !dx_max) return fail(PS_E_INVALID_ARG, "NULL argument");
+    if (n_spins_min && !extent) return fail(PS_E_INVALID_ARG, "n_spins_min needs the object extent");
+    if (extent)
+        for (int d = 0; d < 3; ++d)
+            if (!(extent[d] >= 0) || !std::isfinite(extent[d]))
+                return fail(PS_E_INVALID_ARG, "extent must be finite and >= 0");
     if (!(t1 > 0) || !(t2 > 0)) return fail(PS_E_INVALID_ARG, "t1 and t2 must be > 0 (+inf allowed)");
     if (!(grey_step >= 0) || !std::isfinite(grey_step)) return fail(PS_E_INVALID_ARG, "grey_step must be >= 0");
     double dk[3];
@@ -228,6 +234,20 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
     for (int d = 0; d < 3; ++d) {
         k_max[d] = (double)kmax[d] * dk[d];
         dx_max[d] = k_max[d] > 0 ? 0.5 / k_max[d] : INFINITY;
+    }
+    if (n_spins_min) {
+        // eq. 5.2: isochromats no further apart than dx_max on every axis the
+        // object spans, so each such axis needs ceil(extent / dx_max) of them
+        constexpr int64_t kMaxSpins = int64_t(1) << 62;
+        int64_t n = 1;
+        for (int d = 0; d < 3; ++d) {
+            if (!(extent[d] > 0) || !std::isfinite(dx_max[d])) continue;
+            const double c = std::ceil(extent[d] / dx_max[d]);
+            if (c >= (double)kMaxSpins || (double)n * c >= (double)kMaxSpins)
+                return fail(PS_E_TOO_LARGE, "spin count beyond 2^62");
+            n *= (int64_t)c;
+        }
+        *n_spins_min = n;
     }
     if (n_configs_peak) *n_configs_peak = (int64_t)pop.peak;
     return PS_OK;

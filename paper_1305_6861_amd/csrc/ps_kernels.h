@@ -16,10 +16,14 @@ struct StepArgs {
     const void* rows;        // device, n_shape_rows * 9 doubles (rotation deltas)
     void* partial;           // device, gridDim.x * rows_per_block rows of row_stride reals
     int64_t row_stride;      // reals per workgroup row (2 per sample of the slice)
-    void* state;             // device, (3 + 12 * slots) * n_spins reals, SoA: Mxy_a re, im,
-                             // Mz_a, then kShapeCacheReals entries per kept propagator slot
-    int32_t load_state;      // resume from state instead of equilibrium
-    int32_t save_state;      // write the anchors back at the end
+    void* state;             // device, (6 + 12 * slots) * n_spins reals, SoA: two buffers of
+                             // anchors (Mxy_a re, im, Mz_a), then kShapeCacheReals entries
+                             // per kept propagator slot
+    int32_t load_state;      // resume from anchor buffer anchor_parity ^ 1 instead of equilibrium
+    int32_t save_state;      // write the anchors to buffer anchor_parity at the end
+    int32_t anchor_parity;   // slice index & 1: a slice reads the buffer the previous one wrote
+                             // and writes the other, so a readout replica that starts after
+                             // replica 0 of its tile has finished still reads the slice's start
     int32_t n_cache_slots;   // shaped-pulse propagator slots the slice's ops use
     uint32_t cache_load;     // slots read from the state at the start (bit per slot)
     uint32_t cache_save;     // slots written to the state at the end (bit per slot)

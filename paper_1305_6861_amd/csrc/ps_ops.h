@@ -91,4 +91,13 @@ enum ShapeMode : uint32_t {
 constexpr int kShapeSlots = 2;
 constexpr int kShapeCacheReals = 12;  // A (3 x 3, row-major) then b (3)
 
+// Slice state per spin, in reals (SoA rows of n_spins): two buffers of
+// anchors (Mxy_a re, im, Mz_a) that alternate between slices, then the
+// propagator slots kept across slices.  A slot is written once, by the
+// slice that fills it, and only read afterwards, so it needs one buffer.
+constexpr int kStateSlot0 = 6;
+constexpr int64_t state_reals_per_spin(int n_state_slots) {
+    return kStateSlot0 + (int64_t)kShapeCacheReals * n_state_slots;
+}
+
 }  // namespace ps

@@ -40,15 +40,27 @@ struct HostBuf {                   // pinned
 
 struct Server;                     // served / batched mode (server.cpp)
 
+// Device tables and work buffers of one stream-ordered call (ps_simulate*,
+// ps_simulate_batch), with the pinned staging its tables are uploaded from.
+// A context rotates through kBufSets of them: a call takes a set whose last
+// call has completed, so two calls in flight (on one stream or on two) never
+// wait on the host; only a third call waits for the oldest set.
+struct BufSet {
+    DevBuf ops, rows, traj, partial, state, fin_scratch;
+    DevBuf batch_tables, batch_records;   // ps_simulate_batch
+    HostBuf staging, staging2;
+    hipEvent_t done = nullptr;     // completion of the last call that used the set
+    bool pending = false;
+    void release();
+};
+constexpr int kBufSets = 2;
+
 struct Ctx {
     ps_config cfg{};
     int n_cu = 256;
     std::mutex mu;                 // serialises calls on one context
-    DevBuf ops, rows, traj, partial, state, fin_scratch;
-    DevBuf batch_tables, batch_records;   // ps_simulate_batch
-    HostBuf staging, staging2;
-    hipEvent_t done = nullptr;     // completion of the last request's work
-    bool pending = false;
+    BufSet sets[kBufSets];
+    int next_set = 0;              // round-robin position (the oldest set)
     // kernel timing (PS_CFG_KERNEL_TIMING): event pairs around launches
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> step_marks, fin_marks;
@@ -58,11 +70,16 @@ struct Ctx {
 int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins);
 hipEvent_t timing_event(Ctx* ctx);  // from the pool (timing-enabled contexts)
 ps_status validate_object(const ps_object* obj);
+// max_partial_bytes > 0 overrides the context's bound on the partial rows.
 ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S, Program* prog, int n_coils = 0,
-                  bool snapshots = false);
+                  bool snapshots = false, int64_t max_partial_bytes = 0);
 // Propagator cache slots a request tiled with S spins per lane may use.
 int shape_cache_slots(const Ctx* ctx, int S, const Program& prog);
-ps_status wait_previous(Ctx* ctx);
+// A buffer set for the next call: one whose last call has completed, or
+// else the oldest, after waiting for it.
+ps_status acquire_set(Ctx* ctx, BufSet** out);
+// Mark the set in use until the work enqueued on `stream` so far completes.
+ps_status release_set_after(BufSet* set, hipStream_t stream);
 ps_status validate_receive(const ps_receive* rx, const ps_object* obj);
 // Readout replicas (see the step kernel) a tile of a program can use: at
 // most `hard` (one per readout of its busiest slice, at most 64); replicas
@@ -102,7 +119,7 @@ struct SingleBuffers {
 };
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
                       double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
-                      Single* r);
+                      Single* r, int64_t max_partial_bytes = 0);
 // Stream-ordered launches of a planned request (tables already resident in
 // b); kernel timing events go to timing_ctx when it is not NULL.
 ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b, hipStream_t stream,

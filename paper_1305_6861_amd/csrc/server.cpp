@@ -49,6 +49,7 @@ struct Request {
     size_t footprint = 0;
     bool large = false;                // see kLargeWork
     double t_submit = 0, t_admit = -1, t_done = -1;
+    double t_kernel = 0;               // device time of the iterations it ran in
     std::string error;
 };
 
@@ -96,10 +97,10 @@ struct Server {
     // device side, touched by the scheduler thread only
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;   // timing of one iteration's kernels
     DevBuf records;
     HostBuf staging_rec, staging_tab;
     Pool pool;
-    int64_t max_slice_steps = 65536;
     // counters
     uint64_t iterations = 0;
 
@@ -201,12 +202,26 @@ void Server::loop() {
             first.push_back(r->next_slice);
             count.push_back(1);
         }
+        const bool timed = st == PS_OK && !plans.empty();
+        if (timed) {
+            hipError_t e = hipEventRecord(ev_start, stream);
+            if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
+        }
         if (st == PS_OK && !plans.empty())
             st = run_rounds(ctx, plans, first, count, stream, records, staging_rec, nullptr);
+        if (timed && st == PS_OK) {
+            hipError_t e = hipEventRecord(ev_end, stream);
+            if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
+        }
         if (st == PS_OK) {
             hipError_t e = hipEventRecord(ev, stream);
             if (e == hipSuccess) e = hipEventSynchronize(ev);
             if (e != hipSuccess) st = hip_fail(e, "server iteration");
+        }
+        double iter_kernel_s = 0.0;
+        if (timed && st == PS_OK) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev_start, ev_end) == hipSuccess) iter_kernel_s = 1e-3 * ms;
         }
         std::string err = st == PS_OK ? "" : ps_last_error();
         {
@@ -222,6 +237,7 @@ void Server::loop() {
                     continue;
                 }
                 r->next_slice += 1;
+                if (r->plan.obj.n_spins > 0 && r->plan.prog.n_samples > 0) r->t_kernel += iter_kernel_s;
                 const size_t n_sl = r->plan.obj.n_spins > 0 ? r->plan.prog.slices.size() : 1;
                 if (r->plan.prog.n_samples == 0 || r->next_slice >= n_sl) {
                     finish(r, RQ_DONE, PS_OK, "");
@@ -253,6 +269,8 @@ void destroy_runtime(Ctx* ctx) {
         s->changed.notify_all();
     }
     if (s->ev) hipEventDestroy(s->ev);
+    if (s->ev_start) hipEventDestroy(s->ev_start);
+    if (s->ev_end) hipEventDestroy(s->ev_end);
     if (s->stream) hipStreamDestroy(s->stream);
     s->records.release();
     s->staging_rec.release();
@@ -270,7 +288,12 @@ static ps_status ensure_server(Ctx* ctx) {
     s->t0 = Clock::now();
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev_end);
     if (e != hipSuccess) {
+        if (s->ev_end) hipEventDestroy(s->ev_end);
+        if (s->ev_start) hipEventDestroy(s->ev_start);
+        if (s->ev) hipEventDestroy(s->ev);
         if (s->stream) hipStreamDestroy(s->stream);
         delete s;
         return hip_fail(e, "server stream/event");
@@ -302,7 +325,7 @@ ps_status ps_submit(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq
         std::lock_guard<std::mutex> lk(ctx->mu);
         DeviceGuard g(ctx->cfg.device);
         if ((st = ensure_server(ctx)) != PS_OK) return st;
-        const int64_t steps = ctx->server->max_slice_steps;
+        const int64_t steps = ctx->cfg.max_slice_steps;
         if ((st = plan_request(ctx, obj, seq, n_samples, signal, steps, &r->plan)) != PS_OK) return st;
     }
     r->footprint = r->plan.footprint();
@@ -390,6 +413,23 @@ ps_status ps_request_info(ps_ctx* handle, uint64_t ticket, ps_request_info_t* ou
     out->footprint_bytes = (int64_t)r->footprint;
     out->n_spins = r->plan.obj.n_spins;
     out->n_steps_per_spin = r->plan.prog.n_steps;
+    out->t_kernel = r->state >= RQ_DONE ? r->t_kernel : -1.0;
+    return PS_OK;
+}
+
+ps_status ps_stats(ps_ctx* handle, uint64_t ticket, double* t_queue, double* t_kernel, double* t_e2e) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    Server* s = ctx->server;
+    if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto r = find(s, ticket);
+    if (!r) return fail(PS_E_INVALID_ARG, "unknown ticket");
+    const bool done = r->state >= RQ_DONE;
+    if (t_queue) *t_queue = r->t_admit >= 0 ? r->t_admit - r->t_submit : -1.0;
+    if (t_kernel) *t_kernel = done ? r->t_kernel : -1.0;
+    if (t_e2e) *t_e2e = done ? r->t_done - r->t_submit : -1.0;
     return PS_OK;
 }
 

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import within
 from workloads import SPOIL, Sequence, coils, configs as C
 from workloads.phantom import random_spins
 
@@ -33,9 +34,8 @@ def run(ps, obj, seq, rx=None, **kw):
 
 def per_coil(label, got, ref, tol):
     assert got.shape == ref.shape
-    errs = [oracle.rel_l2(got[c], ref[c]) for c in range(ref.shape[0])]
+    errs = [within(got[c], ref[c], tol, f"{label} coil {c}") for c in range(ref.shape[0])]
     print(f"[coils] {label} worst rel_l2={max(errs):.3e} over {len(errs)} coils", flush=True)
-    assert max(errs) <= tol, (label, errs)
 
 
 def test_loop_ring_on_2d_spin_echo(ps):
@@ -60,7 +60,7 @@ def test_turned_homogeneous_coils(ps):
     sx[1], sy[1] = 0.0, 1.0                                       # the y coil
     got = run(ps, obj, seq, (sx, sy))
     plain = oracle.simulate(obj, seq)
-    assert oracle.rel_l2(got[1], -1j * plain) <= TOL32
+    within(got[1], -1j * plain, TOL32)
     per_coil("turned coils", got, oracle.simulate(obj, seq, coils=(sx, sy)), TOL32)
 
 
@@ -124,8 +124,8 @@ def test_odd_sample_counts_row_groups_coils_and_slices(ps, precision):
         batched = ctx.simulate_batch([obj, obj.take(np.arange(777))], [seq, seq])
         torch.cuda.synchronize()
         b0, b1 = (t.cpu().numpy() for t in batched)
-    assert oracle.rel_l2(b0, plain_ref) <= tol
-    assert oracle.rel_l2(b1, oracle.simulate(obj.take(np.arange(777)), seq)) <= tol
+    within(b0, plain_ref, tol)
+    within(b1, oracle.simulate(obj.take(np.arange(777)), seq), tol)
 
 
 def test_many_coils_and_time_slices(ps):

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import within
 from workloads import SNAPSHOT, coils, configs as C
 
 pytestmark = pytest.mark.gpu
@@ -38,9 +39,8 @@ def test_split_is_bitwise_unsplit(ps, case):
     for prec in (32, 64):
         np.testing.assert_array_equal(res[True, prec], res[False, prec])
     ref = oracle.simulate(obj, seq)
-    err = oracle.rel_l2(res[True, 32], ref)
-    print(f"[split] {case} spins={obj.n_spins} rel_l2={err:.3e}", flush=True)
-    assert err <= 1e-5 and oracle.rel_l2(res[True, 64], ref) <= 1e-12
+    within(res[True, 32], ref, 1e-5, f"split {case} spins={obj.n_spins}")
+    within(res[True, 64], ref, 1e-12, f"split {case} spins={obj.n_spins} fp64")
 
 
 def test_split_with_coils_snapshots_and_slices(ps):

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import within
 from workloads import Sequence, Shape, SPOIL, configs as C
 from workloads.phantom import random_spins
 
@@ -36,11 +37,6 @@ def run(ps, obj, seq, **kw):
         out = ctx.simulate(obj, seq)
         torch.cuda.synchronize()
         return out.cpu().numpy()
-
-
-def report(label, err):
-    print(f"[cache] {label} rel_l2={err:.3e}", flush=True)
-    return err
 
 
 def rf_spoiled_sinc(n_tr: int, n_adc: int = 24) -> Sequence:
@@ -84,11 +80,11 @@ def test_3d_recipe_cache_matches_direct_and_oracle(ps):
     d32 = run(ps, obj, seq, shape_cache=False)
     c64 = run(ps, obj, seq, precision=64)
     d64 = run(ps, obj, seq, precision=64, shape_cache=False)
-    assert report("c3[16] cached", oracle.rel_l2(c32, ref)) <= TOL32
-    assert report("c3[16] direct", oracle.rel_l2(d32, ref)) <= TOL32
-    assert report("c3[16] cached vs direct", oracle.rel_l2(c32, d32)) <= CACHE_VS_DIRECT32
-    assert report("c3[16]/fp64 cached", oracle.rel_l2(c64, ref)) <= TOL64
-    assert report("c3[16]/fp64 direct", oracle.rel_l2(d64, ref)) <= TOL64
+    within(c32, ref, TOL32, "c3[16] cached")
+    within(d32, ref, TOL32, "c3[16] direct")
+    within(c32, d32, CACHE_VS_DIRECT32, "c3[16] cached vs direct")
+    within(c64, ref, TOL64, "c3[16]/fp64 cached")
+    within(d64, ref, TOL64, "c3[16]/fp64 direct")
 
 
 def test_phase_cycled_applications(ps):
@@ -98,13 +94,12 @@ def test_phase_cycled_applications(ps):
     seq = rf_spoiled_sinc(30)
     ref = oracle.simulate(obj, seq)
     got = run(ps, obj, seq)
-    assert report("rf-spoiled cached", oracle.rel_l2(got, ref)) <= TOL32
+    within(got, ref, TOL32, "rf-spoiled cached")
     direct = run(ps, obj, seq, shape_cache=False)
-    assert report("rf-spoiled direct", oracle.rel_l2(direct, ref)) <= TOL32
-    assert report("rf-spoiled cached vs direct", oracle.rel_l2(got, direct)) <= CACHE_VS_DIRECT32
-    assert report("rf-spoiled cached/fp64", oracle.rel_l2(run(ps, obj, seq, precision=64), ref)) <= TOL64
-    assert report("rf-spoiled direct/fp64",
-                  oracle.rel_l2(run(ps, obj, seq, precision=64, shape_cache=False), ref)) <= TOL64
+    within(direct, ref, TOL32, "rf-spoiled direct")
+    within(got, direct, CACHE_VS_DIRECT32, "rf-spoiled cached vs direct")
+    within(run(ps, obj, seq, precision=64), ref, TOL64, "rf-spoiled cached/fp64")
+    within(run(ps, obj, seq, precision=64, shape_cache=False), ref, TOL64, "rf-spoiled direct/fp64")
 
 
 def test_more_recurring_shapes_than_slots(ps):
@@ -112,10 +107,9 @@ def test_more_recurring_shapes_than_slots(ps):
     seq = three_shapes(9)
     ref = oracle.simulate(obj, seq)
     got = run(ps, obj, seq)
-    assert report("three shapes cached", oracle.rel_l2(got, ref)) <= TOL32
-    assert report("three shapes cached vs direct",
-                  oracle.rel_l2(got, run(ps, obj, seq, shape_cache=False))) <= CACHE_VS_DIRECT32
-    assert report("three shapes cached/fp64", oracle.rel_l2(run(ps, obj, seq, precision=64), ref)) <= TOL64
+    within(got, ref, TOL32, "three shapes cached")
+    within(got, run(ps, obj, seq, shape_cache=False), CACHE_VS_DIRECT32, "three shapes cached vs direct")
+    within(run(ps, obj, seq, precision=64), ref, TOL64, "three shapes cached/fp64")
 
 
 def test_cache_kept_across_time_slices(ps):
@@ -130,15 +124,14 @@ def test_cache_kept_across_time_slices(ps):
     small = n_rows * 2 * 4 * 24 * 6
     sliced = run(ps, obj, seq, spins_per_lane=1, max_partial_bytes=small)
     whole = run(ps, obj, seq, spins_per_lane=1)
-    assert report("sliced cached", oracle.rel_l2(sliced, ref)) <= TOL32
-    assert report("sliced vs whole", oracle.rel_l2(sliced, whole)) <= CACHE_VS_DIRECT32
+    within(sliced, ref, TOL32, "sliced cached")
+    within(sliced, whole, CACHE_VS_DIRECT32, "sliced vs whole")
     sliced64 = run(ps, obj, seq, spins_per_lane=1, precision=64, max_partial_bytes=2 * small)
-    assert report("sliced cached/fp64", oracle.rel_l2(sliced64, ref)) <= TOL64
+    within(sliced64, ref, TOL64, "sliced cached/fp64")
     # three recurring shapes, two slots, slices of 64 samples (4 repetitions)
     seq3 = three_shapes(12)
     ref3 = oracle.simulate(obj, seq3)
-    assert report("three shapes sliced", oracle.rel_l2(
-        run(ps, obj, seq3, spins_per_lane=1, max_partial_bytes=n_rows * 2 * 4 * 64), ref3)) <= TOL32
+    within(run(ps, obj, seq3, spins_per_lane=1, max_partial_bytes=n_rows * 2 * 4 * 64), ref3, TOL32, "three shapes sliced")
 
 
 @pytest.mark.parametrize("S", [1, 2])
@@ -146,7 +139,7 @@ def test_cache_tilings(ps, S):
     obj, _ = C.c3(12)
     seq = C.gre_3d_sinc(12, 3, 3)
     ref = oracle.simulate(obj, seq)
-    assert report(f"c3[12] S={S} cached", oracle.rel_l2(run(ps, obj, seq, spins_per_lane=S), ref)) <= TOL32
+    within(run(ps, obj, seq, spins_per_lane=S), ref, TOL32, f"c3[12] S={S} cached")
 
 
 def test_batched_requests_with_cached_shapes_equal_alone(ps):
@@ -158,4 +151,4 @@ def test_batched_requests_with_cached_shapes_equal_alone(ps):
         torch.cuda.synchronize()
     for (obj, seq), got in zip(reqs, outs):
         np.testing.assert_array_equal(got, run(ps, obj, seq))
-        assert oracle.rel_l2(got, oracle.simulate(obj, seq)) <= TOL32
+        within(got, oracle.simulate(obj, seq), TOL32)

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import within
 from workloads import Sequence, SNAPSHOT, SPOIL, coils, configs as C
 from workloads.phantom import random_spins
 
@@ -53,10 +54,7 @@ def with_snapshots(seq, every_tr_event=None):
 
 
 def check(label, got, ref, tol):
-    assert got.shape == ref.shape
-    err = oracle.rel_l2(got, ref)
-    print(f"[snap] {label} rel_l2={err:.3e} shape={ref.shape}", flush=True)
-    assert err <= tol, (label, err)
+    within(got, ref, tol, f"snapshots {label} shape={ref.shape}")
 
 
 def test_free_precession_and_recovery(ps):
@@ -95,7 +93,7 @@ def test_snapshots_with_shapes_coils_slices_and_ragged_spins(ps):
         sig, snap = run(ps, obj, seq, rx, **kw)
         check(f"c3[10] {kw}", snap, ref, TOL32)
         for c in range(2):
-            assert oracle.rel_l2(sig[c], ref_sig[c]) <= TOL32
+            within(sig[c], ref_sig[c], TOL32)
         np.testing.assert_array_equal(sig, plain(ps, obj, seq0, rx, **kw))
 
 

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import within
 from workloads import configs as C
 
 pytestmark = pytest.mark.gpu
@@ -27,6 +28,4 @@ def test_table78_reduced(ps, kind):
             got = ctx.simulate(obj, seq)
             torch.cuda.synchronize()
             got = got.cpu().numpy()
-        err = oracle.rel_l2(got, ref)
-        print(f"[t78] {kind} fp{prec} spins={obj.n_spins} samples={ref.size} rel_l2={err:.3e}", flush=True)
-        assert err <= tol
+        within(got, ref, tol, f"t78 {kind} fp{prec} spins={obj.n_spins}")

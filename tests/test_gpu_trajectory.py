@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import within
 from workloads import Sequence, SNAPSHOT, Trajectory, coils, configs as C
 from workloads.phantom import random_spins
 
@@ -32,9 +33,7 @@ def run(ps, obj, seq, rx=None, **kw):
 
 
 def check(label, got, ref, tol):
-    err = oracle.rel_l2(got, ref)
-    print(f"[traj] {label} rel_l2={err:.3e}", flush=True)
-    assert got.shape == ref.shape and err <= tol, (label, err)
+    within(got, ref, tol, f"trajectory {label}")
 
 
 def test_spiral_against_the_oracle(ps):

@@ -63,10 +63,43 @@ def test_random_lattice_sequences(ps, seed):
 
 
 def test_known_extents_and_spin_counts(ps):
-    r = ps.kt_extent(C.spoiled_gre_2d(32, 12), D2, 1.0, 0.1)
+    r = ps.kt_extent(C.spoiled_gre_2d(32, 12), D2, 1.0, 0.1, extent=(FOV, FOV, 0.0))
     np.testing.assert_allclose(r["k_max"], [17 / FOV, 6 / FOV, 0.0])
     assert math.isinf(r["dx_max"][2])
-    assert ps.min_spins((FOV, FOV, 0.0), r["dx_max"]) == 34 * 12
+    # eq. 5.2: spacing 1 / (2 k_max) per axis, so 2 k_max FOV isochromats on x and y
+    assert r["n_spins_min"] == 34 * 12
+    # an axis without moments needs one isochromat whatever its extent
+    assert ps.kt_extent(C.spoiled_gre_2d(32, 12), D2, 1.0, 0.1, extent=(FOV, FOV, 0.3))["n_spins_min"] == 34 * 12
+    # half the extent, half the isochromats per axis (ceil)
+    assert ps.kt_extent(C.spoiled_gre_2d(32, 12), D2, 1.0, 0.1, extent=(FOV / 2, FOV / 3, 0.0))["n_spins_min"] == 17 * 4
+    assert "n_spins_min" not in ps.kt_extent(C.spoiled_gre_2d(32, 12), D2, 1.0, 0.1)
+
+
+def test_spin_count_matches_the_aliasing_criterion(ps):
+    """The spin count the library derives makes the two-pulse echo exact
+    (eq. 5.2), checked with the oracle: a gradient of one lattice step per
+    interval over a 1-D object, isochromats spaced at the returned dx_max."""
+    import oracle
+    from workloads.phantom import SpinObject
+    L = 0.1
+    dk = (1 / L, 0.0, 0.0)
+    seq = Sequence("two pulses")
+    seq.add(5e-3, m=(1 / L, 0, 0), alpha=np.pi / 2)
+    seq.add(5e-3, m=(1 / L, 0, 0), alpha=np.pi / 2, n_adc=1)
+    r = ps.kt_extent(seq, dk, math.inf, math.inf, extent=(L, 0.0, 0.0))
+    n = r["n_spins_min"]
+    assert n == int(math.ceil(L / r["dx_max"][0]))
+
+    def echo(n_iso):
+        x = (np.arange(n_iso) / n_iso * L).astype(np.float32)
+        z = np.zeros(n_iso, np.float32)
+        obj = SpinObject(x=x, y=z, z=z, m0=np.ones(n_iso, np.float32),
+                         t1=np.full(n_iso, np.inf, np.float32), t2=np.full(n_iso, np.inf, np.float32), dw=z)
+        return oracle.simulate(obj, seq)[0] / n_iso
+
+    ok, short = echo(n), echo(max(n - 2, 1))
+    assert abs(ok - (-0.5j)) < 1e-6           # the two-pulse echo (FP32 positions round the cancellation)
+    assert abs(short - (-0.5j)) > 1e-3        # too few isochromats alias
 
 
 def test_errors(ps):
