@@ -50,18 +50,16 @@ def bench_c4(args):
     devs = [ps.to_device(o) for o, _ in reqs]
     packs = [ps.pack_sequence(s) for _, s in reqs]
     spin_steps = float(sum(o.n_spins * s.n_steps_per_spin for o, s in reqs))
+    rule_ctx = ps.Context()                 # tilings of the threshold rule
     ctx = ps.Context()
+    tuned = 0
+    if not args.no_tune:                    # one tuner run per request class
+        t_tune = time.perf_counter()
+        tuned = sum(0 if ctx.tune(d, p)["from_table"] else 1 for d, p in zip(devs, packs))
+        t_tune = time.perf_counter() - t_tune
     outs = [torch.empty(2 * s.n_samples, dtype=torch.float64, device="cuda") for _, s in reqs]
 
-    def one_per_launch():
-        for d, p, o in zip(devs, packs, outs):
-            ctx.simulate(d, p, out=o)
-
-    def batched():
-        return ctx.simulate_batch(devs, packs)
-
-    res = {}
-    for name, fn in (("one_per_launch", one_per_launch), ("batched", batched)):
+    def timed(fn):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -69,7 +67,18 @@ def bench_c4(args):
         for _ in range(args.steps):
             fn()
         torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0) / args.steps
+        return (time.perf_counter() - t0) / args.steps
+
+    res = {}
+    for tag, c in (("", ctx), ("rule_", rule_ctx)):
+        def one_per_launch():
+            for d, p, o in zip(devs, packs, outs):
+                c.simulate(d, p, out=o)
+
+        def batched():
+            return c.simulate_batch(devs, packs)
+        res[tag + "one_per_launch"] = timed(one_per_launch)
+        res[tag + "batched"] = timed(batched)
     rec = {"metric": "spin-steps/s", "value": spin_steps / res["batched"], "unit": "spin-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["batched"] * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -79,10 +88,14 @@ def bench_c4(args):
                       "spin_steps": spin_steps},
            "one_per_launch_ms": res["one_per_launch"] * 1e3,
            "speedup_vs_one_per_launch": res["one_per_launch"] / res["batched"],
+           "tiling": {"source": "autotuner" if not args.no_tune else "threshold rule",
+                      "classes_tuned": tuned, "tuning_s": t_tune if not args.no_tune else 0.0,
+                      "threshold_rule_batched_ms": res["rule_batched"] * 1e3,
+                      "threshold_rule_one_per_launch_ms": res["rule_one_per_launch"] * 1e3},
            "roofline": None, "cpu_baseline": None}
     if not args.no_cpu_baseline:
         import oracle
-        got = [t.cpu().numpy() for t in batched()]
+        got = [t.cpu().numpy() for t in ctx.simulate_batch(devs, packs)]
         t0 = time.perf_counter()
         errs = [oracle.rel_l2(g, oracle.simulate(o, s)) for g, (o, s) in zip(got, reqs)]
         dt = time.perf_counter() - t0
@@ -94,7 +107,8 @@ def bench_c4(args):
 def bench_c5(args):
     """Poisson stream: served (continuous batching) vs FIFO one launch per
     request, both replaying the same arrival schedule in real time."""
-    rec = c5_replay(args.c5_requests)
+    rec = c5_replay(args.c5_requests, serve_graphs=not args.serve_direct, rate_hz=args.c5_rate,
+                    frac_3d=args.c5_frac_3d)
     print(json.dumps(rec), flush=True)
 
 
@@ -108,12 +122,12 @@ def latency_block(n_requests: int) -> dict:
     return out
 
 
-def c5_replay(n_requests: int) -> dict:
+def c5_replay(n_requests: int, serve_graphs: bool = True, rate_hz: float = 50.0, frac_3d: float = 0.1) -> dict:
     import numpy as np
     import torch
     import paper_1305_6861_amd as ps
     from workloads import configs as C
-    sched = C.c5_stream(n_requests=n_requests)
+    sched = C.c5_stream(n_requests=n_requests, rate_hz=rate_hz, frac_3d=frac_3d)
     reqs = [C.c5_request(kind, param) for _, kind, param in sched]
     devs = [ps.to_device(o) for o, _ in reqs]
     packs = [ps.pack_sequence(s) for _, s in reqs]
@@ -134,7 +148,7 @@ def c5_replay(n_requests: int) -> dict:
         return done, time.perf_counter() - t0
 
     # served
-    ctx = ps.Context()
+    ctx = ps.Context(serve_graphs=serve_graphs)
     def s_submit(i, t):
         return (t, ctx.submit(devs[i], packs[i]))
     kernel_s, queue_s = [], []
@@ -187,7 +201,7 @@ def c5_replay(n_requests: int) -> dict:
     rec = {"metric": "spin-steps/s", "value": spin_steps / wall_s, "unit": "spin-steps/s", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": wall_s * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"c5: Poisson stream of {len(reqs)} requests at 50/s, "
+           "config": {"workload": f"c5: Poisson stream of {len(reqs)} requests at {rate_hz:g}/s, "
                                   f"{int(is3d.sum())} of them 3-D 2x64^3 sinc GRE, the rest c4-type",
                       "spin_steps": spin_steps},
            "served": {"wall_s": wall_s, "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
@@ -195,7 +209,9 @@ def c5_replay(n_requests: int) -> dict:
                       "p50_3d_ms": pct(lat_s[is3d], 50) if is3d.any() else None,
                       "p50_queue_ms": pct(np.array(queue_s), 50),
                       "p50_kernel_ms": pct(np.array(kernel_s), 50),
-                      "iterations": served_iters},
+                      "iterations": served_iters, "iterations_per_s": served_iters / wall_s,
+                      "launch": ("HIP graph replay per iteration, short iterations launched ahead" if serve_graphs
+                                 else "one iteration at a time, direct kernel launches")},
            "fifo_one_per_launch": {"wall_s": wall_f, "p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
                                    "p50_2d_ms": pct(lat_f[~is3d], 50), "p99_2d_ms": pct(lat_f[~is3d], 99)},
            "roofline": None, "cpu_baseline": None}
@@ -368,12 +384,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--spins-per-lane", type=int, default=0, help="0 = autotuned")
+    ap.add_argument("--spins-per-lane", type=int, default=0,
+                    help="0 = the autotuner's choice (or the threshold rule with --no-tune)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: tiles from the threshold rule")
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5"], default="c3",
                     help="c3 (default, the reported workload: 3-D shaped-pulse configuration), "
                          "c2 (2-D spin echo), c4 (batched vs one launch per request), "
                          "c5 (served stream vs FIFO)")
     ap.add_argument("--c5-requests", type=int, default=2000)
+    ap.add_argument("--serve-direct", action="store_true",
+                    help="c5: the served loop runs one iteration at a time with direct kernel launches "
+                         "(default: HIP graph replay, short iterations launched ahead)")
+    ap.add_argument("--c5-frac-3d", type=float, default=0.1,
+                    help="c5: share of 3-D 2x64^3 jobs in the stream (the configuration's is 0.1)")
+    ap.add_argument("--c5-rate", type=float, default=50.0,
+                    help="c5: mean arrival rate of the Poisson stream, requests/s (the configuration's is 50)")
     ap.add_argument("--latency-requests", type=int, default=300,
                     help="requests of the c5 stream prefix replayed served and FIFO for the latency block "
                          "of the default run (0: leave the block out)")
@@ -430,7 +456,15 @@ def main():
         rx_np = coil_maps.loop_ring(obj, args.coils, ring_radius=0.2, coil_radius=0.06)
         rx = tuple(torch.from_numpy(a).cuda() for a in rx_np)
     out = torch.empty(2 * n_samples * max(args.coils, 1), dtype=torch.float64, device="cuda")
-    spl, _ = ctx.tile(obj.n_spins)
+    tune = None
+    if args.spins_per_lane == 0 and not args.no_tune:
+        tune = ctx.tune(dev, packed, coils=rx)
+    tiling = ctx.tile_for(obj.n_spins, packed, args.coils)
+    spl = tiling["spins_per_lane"]
+    tiling["source"] = ("fixed" if args.spins_per_lane else "autotuner" if tiling["tuned"] else "threshold rule")
+    if tune is not None:
+        tiling["tuner"] = {k: tune[k] for k in ("best_ms", "rule_ms", "probe_events", "candidates")}
+        tiling["tuner"]["gain_over_rule_on_probe"] = tune["rule_ms"] / tune["best_ms"]
 
     if args.plan:
         plan = ctx.plan(dev, packed, coils=rx)
@@ -509,7 +543,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if fp64 else "f32",
            "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
-                      "n_samples": n_samples, "spins_per_lane": spl,
+                      "n_samples": n_samples, "spins_per_lane": spl, "tiling": tiling,
                       "precision": "fp64 throughout" if fp64 else "fp32 stepping, fp64 phases and cross-block sums",
                       "shape_cache": cache,
                       "receive_coils": args.coils or "one homogeneous coil",

@@ -72,12 +72,27 @@ typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
  * readouts (a readout changes no spin state); every sample is still computed
  * once, by the same arithmetic, so the signal is bitwise the same. */
 #define PS_CFG_NO_READOUT_SPLIT 4u
+/* ps_config.flags: tune on first use.  ps_simulate, ps_simulate_rx,
+ * ps_simulate_ex, ps_plan_create and ps_simulate_batch first run ps_tune for
+ * every request whose class (see ps_tune) has no entry in the context's
+ * tiling table yet: a synchronous probe of a few ms per candidate tiling,
+ * on a private stream ordered after the work already queued on the call's
+ * stream.  ps_submit only reads the table.  Ignored when spins_per_lane is
+ * set. */
+#define PS_CFG_AUTOTUNE 8u
+/* ps_config.flags: the served loop runs one iteration at a time, launching
+ * its kernels one by one, instead of replaying them from a HIP graph with
+ * short iterations launched ahead (the results are the same; for
+ * measurement). */
+#define PS_CFG_SERVE_DIRECT 16u
 
 typedef struct ps_config {
     int32_t device;              /* HIP device ordinal                                 */
     int32_t precision;           /* 32: FP32 stepping (FP64 phases and cross-block
                                     sums); 64: FP64 throughout                         */
-    int32_t spins_per_lane;      /* 0 = autotuned; else 1, 2, 4 or 8 (FP64: 1 or 2)    */
+    int32_t spins_per_lane;      /* 0 = the tiling table's entry for the request's
+                                    class (ps_tune), else the threshold rule of
+                                    ps_tile; or fixed: 1, 2, 4, 8 (FP64: 1 or 2)       */
     int32_t flags;               /* PS_CFG_* bits                                      */
     int64_t max_partial_bytes;   /* bound on the per-block partial-sum buffer; longer
                                     sequences run in time slices (0 = default 2 GiB)   */
@@ -150,7 +165,8 @@ typedef struct ps_sequence {
     const ps_trajectory *trajectories;  /* HOST, may be NULL when n_trajectories = 0   */
 } ps_sequence;
 
-/* Fill *cfg with the defaults (device 0, precision 32, autotuned tiles). */
+/* Fill *cfg with the defaults (device 0, precision 32, tiles from the tiling
+ * table or the threshold rule). */
 ps_status ps_config_default(ps_config *cfg);
 
 /* Create a context on cfg->device (NULL = defaults).  Fails with
@@ -286,8 +302,14 @@ ps_status ps_simulate_batch(ps_ctx *ctx, int32_t n_requests, const ps_object *ob
  * admitted request by one time slice per iteration in one batched round, so
  * requests that arrive while others run join at the next iteration
  * (continuous batching; after the master / compute-node / superposition
- * roles of sections 5.3.2 and 6.3).  Spin state stays in device memory
- * between slices.  A request's result is bitwise the same alone or in any
+ * roles of sections 5.3.2 and 6.3).  An iteration's kernels are replayed
+ * from a HIP graph (kernel nodes only, their arguments updated per
+ * iteration; PS_CFG_SERVE_DIRECT launches them one by one instead).  While
+ * iterations are short (at most 1e10 spin-steps) the next one is planned
+ * and launched before the previous completes, two in flight, and the host
+ * waits on the device only to retire completed iterations (the master learns
+ * of a finished block after its superposition, section 7.3.1).  Spin state
+ * stays in device memory between slices.  A request's result is bitwise the same alone or in any
  * mix.  The object arrays must hold their data when ps_submit is called (no
  * ordering with the caller's streams); signal must not be read before
  * ps_poll / ps_wait report completion. */
@@ -345,10 +367,71 @@ ps_status ps_release(ps_ctx *ctx, uint64_t ticket);
 /* Scheduler counters (all zero before the first ps_submit). */
 ps_status ps_server_stats(ps_ctx *ctx, ps_server_stats_t *out);
 
-/* The tiling ps_simulate uses for an object of n_spins spins on this
- * context: spins held per lane (the autotuned or configured value) and
+/* The threshold rule's tiling for an object of n_spins spins on this
+ * context (what a request gets when the tiling table has no entry for its
+ * class): spins held per lane -- the configured value, else 2 once the
+ * object gives every SIMD two waves at 2 spins per lane, else 1 -- and
  * spins per workgroup (4 waves of 64 lanes). */
 ps_status ps_tile(ps_ctx *ctx, int64_t n_spins, int32_t *spins_per_lane, int64_t *spins_per_block);
+
+/* ---- tiling autotuner -------------------------------------------------
+ * The paper sizes its spin blocks so that every compute node gets one and
+ * hands out more blocks than nodes so that their speeds level out (section
+ * 5.3.2).  Here a block is a workgroup tile of 256 S spins, S spins per
+ * lane; readout replicas split a small object's readouts over idle compute
+ * units.  ps_tune times the candidate tilings of a request on the device
+ * and records the fastest for the request's class in the context's tiling
+ * table; every later request of that class, on every entry point, uses it.
+ * A class is: precision, floor(log2 n_spins), floor(log2 of the longest
+ * readout in samples) (none without readouts), shaped pulses or not,
+ * ceil(log2 n_coils).  Candidates: S = 1, 2, 4, 8 (FP64: 1, 2) with the
+ * readout-replica rule, plus no replicas and twice the rule's count where
+ * the rule gives replicas.  Each is timed on a probe -- the request's object
+ * with the longest prefix of its sequence of about 6e10 spin-steps (at least
+ * through its first readout; the whole sequence when shorter) -- by the
+ * device time of its kernels: one warm-up and three timed runs, median.  The
+ * threshold rule's tiling is kept unless a candidate is more than 3 % faster.
+ * The result of a request depends on its tiling (bitwise; within the FP32
+ * tolerance across tilings), so a request run after its class was tuned may
+ * differ in the last bits from one run before. */
+#define PS_TUNE_MAX_CANDIDATES 12
+/* ps_tune flags: time the candidates again even if the class has an entry. */
+#define PS_TUNE_FORCE 1u
+typedef struct ps_tune_result {
+    int32_t spins_per_lane;      /* the class's tiling                                 */
+    int32_t replicas;            /* 0: no readout replicas, 1: the rule, 2: twice it   */
+    int32_t from_table;          /* 1: the class had an entry; nothing was timed       */
+    int32_t n_candidates;        /* candidates timed (0 with from_table)               */
+    double  best_ms;             /* the chosen tiling's median probe time              */
+    double  rule_ms;             /* the threshold rule's tiling on the same probe      */
+    int64_t probe_events;        /* events of the sequence prefix the probe ran        */
+    int32_t cand_spins_per_lane[PS_TUNE_MAX_CANDIDATES];
+    int32_t cand_replicas[PS_TUNE_MAX_CANDIDATES];
+    double  cand_ms[PS_TUNE_MAX_CANDIDATES];
+} ps_tune_result;
+/* Tune the request's class (arguments as for ps_simulate_rx; rx may be NULL;
+ * the object arrays must hold their data: the probe runs on a private stream
+ * after work queued on the null stream).  Synchronous; allocates a probe
+ * signal buffer for the call.  out may be NULL.  PS_E_INVALID_ARG for an
+ * invalid request, an object without spins or a context whose
+ * spins_per_lane is fixed. */
+ps_status ps_tune(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, const ps_receive *rx, uint32_t flags,
+                  ps_tune_result *out);
+/* The tiling a request of n_spins spins, this sequence and n_coils coils (0:
+ * one homogeneous coil) gets on this context, and whether it comes from the
+ * tiling table (*tuned = 1) or the threshold rule.  Any output may be NULL. */
+ps_status ps_tile_for(ps_ctx *ctx, int64_t n_spins, const ps_sequence *seq, int32_t n_coils,
+                      int32_t *spins_per_lane, int32_t *replicas, int32_t *tuned);
+/* Write the tiling table to a text file, headed by the device model, its
+ * compute-unit count and a hash of this library's sources. */
+ps_status ps_tune_save(ps_ctx *ctx, const char *path);
+/* Add the entries of a file written by ps_tune_save for this precision to
+ * the table (*n_loaded: how many; may be NULL).  PS_E_INVALID_ARG when the
+ * file is unreadable, malformed, or written for another device model or
+ * library build (nothing is loaded then). */
+ps_status ps_tune_load(ps_ctx *ctx, const char *path, int32_t *n_loaded);
+/* Empty the tiling table. */
+ps_status ps_tune_clear(ps_ctx *ctx);
 
 /* Durations in ms of the kernels launched since the previous call (contexts
  * created with PS_CFG_KERNEL_TIMING only): the step kernels in launch order

@@ -152,7 +152,8 @@ class Context:
 
     def __init__(self, device: int = 0, precision: int = 32, spins_per_lane: int = 0,
                  max_partial_bytes: int = 0, max_footprint_bytes: int = 0, kernel_timing: bool = False,
-                 shape_cache: bool = True, readout_split: bool = True, max_slice_steps: int = 0):
+                 shape_cache: bool = True, readout_split: bool = True, max_slice_steps: int = 0,
+                 autotune: bool = False, serve_graphs: bool = True):
         cfg = _b.ps_config()
         _b.check(_b.lib.ps_config_default(ctypes.byref(cfg)))
         cfg.device = device
@@ -160,7 +161,9 @@ class Context:
         cfg.spins_per_lane = spins_per_lane
         cfg.flags = (_b.PS_CFG_KERNEL_TIMING if kernel_timing else 0) | \
             (0 if shape_cache else _b.PS_CFG_NO_SHAPE_CACHE) | \
-            (0 if readout_split else _b.PS_CFG_NO_READOUT_SPLIT)
+            (0 if readout_split else _b.PS_CFG_NO_READOUT_SPLIT) | \
+            (_b.PS_CFG_AUTOTUNE if autotune else 0) | \
+            (0 if serve_graphs else _b.PS_CFG_SERVE_DIRECT)
         if max_partial_bytes:
             cfg.max_partial_bytes = max_partial_bytes
         if max_footprint_bytes:
@@ -195,6 +198,53 @@ class Context:
         spl = ctypes.c_int32(); spb = ctypes.c_int64()
         _b.check(_b.lib.ps_tile(self._h, int(n_spins), ctypes.byref(spl), ctypes.byref(spb)))
         return int(spl.value), int(spb.value)
+
+    def tile_for(self, n_spins: int, seq, n_coils: int = 0) -> dict:
+        """The tiling a request of this size and sequence gets (ps_tile_for):
+        spins per lane, readout-replica mode and whether it comes from the
+        tiling table (tuned) or the threshold rule."""
+        ps = pack_sequence(seq)
+        spl, rep, tuned = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _b.check(_b.lib.ps_tile_for(self._h, int(n_spins), ctypes.byref(ps.struct), int(n_coils),
+                                    ctypes.byref(spl), ctypes.byref(rep), ctypes.byref(tuned)))
+        return {"spins_per_lane": int(spl.value), "replicas": _b.REPLICA_MODES[int(rep.value)],
+                "tuned": bool(tuned.value)}
+
+    def tune(self, obj, seq, coils=None, force: bool = False) -> dict:
+        """Time the candidate tilings of the request's class on the device and
+        keep the fastest in the context's tiling table (ps_tune); returns the
+        chosen tiling with every candidate's median probe time in ms."""
+        import torch
+        owned = not (isinstance(obj, dict) and all(isinstance(obj[f], torch.Tensor) and obj[f].is_cuda
+                                                   for f in FIELDS))
+        dev = to_device(obj, f"cuda:{self.device}") if owned else obj
+        torch.cuda.current_stream(self.device).synchronize()
+        ps = pack_sequence(seq)
+        n_spins = int(dev["x"].numel())
+        keep, rx = _receive(coils, n_spins, self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        o = _object_struct(dev)
+        r = _b.ps_tune_result()
+        _b.check(_b.lib.ps_tune(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                ctypes.byref(rx) if rx is not None else None,
+                                _b.PS_TUNE_FORCE if force else 0, ctypes.byref(r)))
+        return {"spins_per_lane": int(r.spins_per_lane), "replicas": _b.REPLICA_MODES[int(r.replicas)],
+                "from_table": bool(r.from_table), "best_ms": float(r.best_ms), "rule_ms": float(r.rule_ms),
+                "probe_events": int(r.probe_events),
+                "candidates": [{"spins_per_lane": int(r.cand_spins_per_lane[i]),
+                                "replicas": _b.REPLICA_MODES[int(r.cand_replicas[i])], "ms": float(r.cand_ms[i])}
+                               for i in range(int(r.n_candidates))]}
+
+    def tune_save(self, path: str):
+        _b.check(_b.lib.ps_tune_save(self._h, str(path).encode()))
+
+    def tune_load(self, path: str) -> int:
+        n = ctypes.c_int32()
+        _b.check(_b.lib.ps_tune_load(self._h, str(path).encode(), ctypes.byref(n)))
+        return int(n.value)
+
+    def tune_clear(self):
+        _b.check(_b.lib.ps_tune_clear(self._h))
 
     def kernel_times(self, capacity: int = 1 << 16):
         """(step-kernel durations in ms in launch order, summed finalize-kernel

@@ -21,6 +21,10 @@ PS_EV_TRAJECTORY = 4
 PS_CFG_KERNEL_TIMING = 1
 PS_CFG_NO_SHAPE_CACHE = 2
 PS_CFG_NO_READOUT_SPLIT = 4
+PS_CFG_AUTOTUNE = 8
+PS_CFG_SERVE_DIRECT = 16
+PS_TUNE_FORCE = 1
+PS_TUNE_MAX_CANDIDATES = 12
 
 
 class PsError(RuntimeError):
@@ -90,7 +94,19 @@ class ps_server_stats_t(ctypes.Structure):
                 ("footprint_in_use", ctypes.c_int64), ("now", ctypes.c_double)]
 
 
+class ps_tune_result(ctypes.Structure):
+    _fields_ = [("spins_per_lane", ctypes.c_int32), ("replicas", ctypes.c_int32), ("from_table", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("best_ms", ctypes.c_double), ("rule_ms", ctypes.c_double),
+                ("probe_events", ctypes.c_int64),
+                ("cand_spins_per_lane", ctypes.c_int32 * PS_TUNE_MAX_CANDIDATES),
+                ("cand_replicas", ctypes.c_int32 * PS_TUNE_MAX_CANDIDATES),
+                ("cand_ms", ctypes.c_double * PS_TUNE_MAX_CANDIDATES)]
+
+
+assert ctypes.sizeof(ps_tune_result) == 232
+
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+REPLICA_MODES = {0: "none", 1: "rule", 2: "twice the rule"}
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -133,6 +149,14 @@ SIGNATURES = {
     "ps_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "ps_plan_destroy": (None, [ctypes.c_void_p]),
+    "ps_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
+                               ctypes.POINTER(ps_receive), ctypes.c_uint32, ctypes.POINTER(ps_tune_result)]),
+    "ps_tile_for": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ps_sequence), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]),
+    "ps_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "ps_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
+    "ps_tune_clear": (ctypes.c_int, [ctypes.c_void_p]),
     "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                       ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),

@@ -24,6 +24,7 @@ static_assert(sizeof(ps_object) == 64, "ps_object ABI size");
 static_assert(sizeof(ps_sequence) == 40, "ps_sequence ABI size");
 static_assert(sizeof(ps_trajectory) == 24, "ps_trajectory ABI size");
 static_assert(sizeof(ps_receive) == 24, "ps_receive ABI size");
+static_assert(sizeof(ps_tune_result) == 232, "ps_tune_result ABI size");
 
 namespace ps {
 
@@ -79,7 +80,7 @@ void HostBuf::release() {
     bytes = 0;
 }
 
-int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins) {
+int threshold_spins_per_lane(const Ctx* ctx, int64_t n_spins) {
     if (ctx->cfg.spins_per_lane > 0) return ctx->cfg.spins_per_lane;
     // Keep at least ~2 waves per SIMD (2 x 1024 SIMDs) while giving each lane
     // as many spins as possible: more spins per lane amortise the per-sample
@@ -232,17 +233,18 @@ ReplicaBound replica_bound(const Program& p, int n_out) {
 // a CU of their own only shorten the launch, whatever stepping they repeat
 // (up to n_CU / n_tiles of them); beyond that, about two workgroups per CU
 // while the repeated stepping stays below the readout work it splits.
-int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound) {
-    if (ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) return 1;
+int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32_t mode) {
+    if ((ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) || mode == REPLICAS_NONE) return 1;
     const int64_t n_cu = std::max(ctx->n_cu, 1), want = 2 * n_cu;
     if (n_tiles <= 0 || n_tiles * 2 > want) return 1;
     const int64_t own = n_cu / n_tiles;
     const int64_t shared = std::min<int64_t>((want + n_tiles - 1) / n_tiles, bound.work);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(bound.hard, std::max(own, shared)));
+    const int64_t rule = std::max<int64_t>(1, std::min<int64_t>(bound.hard, std::max(own, shared)));
+    return (int)(mode == REPLICAS_DOUBLE ? std::min<int64_t>(bound.hard, 2 * rule) : rule);
 }
 
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
-                      double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
+                      double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, const Tiling* force,
                       Single* r, int64_t max_partial_bytes) {
     // n_snapshots < 0: snapshot flags are ignored (entry points without them)
     ps_status st = validate_object(obj);
@@ -250,7 +252,9 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     if ((st = validate_receive(rx, obj)) != PS_OK) return st;
     r->n_coils = rx ? rx->n_coils : 0;
     r->n_out = std::max(r->n_coils, 1);
-    r->S = S_override > 0 ? S_override : choose_spins_per_lane(ctx, obj->n_spins);
+    const Tiling tl = force ? *force : choose_tiling(ctx, obj->n_spins, seq, r->n_coils);
+    r->S = tl.S;
+    r->replica_mode = tl.replicas;
     const int64_t spb = spins_per_block_of(r->S);
     r->n_blocks = (obj->n_spins + spb - 1) / spb;
     r->n_rows = r->n_blocks * rows_per_block_of(r->S);
@@ -284,7 +288,7 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->state_bytes = prog.slices.size() > 1
                          ? (size_t)(state_reals_per_spin(prog.n_state_slots) * obj->n_spins * real_bytes)
                          : 0;
-    r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out));
+    r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out), r->replica_mode);
     return PS_OK;
 }
 
@@ -357,10 +361,10 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
 }
 
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
-                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
+                      int64_t n_samples, hipStream_t stream, const Tiling* force, const ps_receive* rx,
                       void* snaps, int64_t n_snapshots) {
     Single r;
-    ps_status st = plan_single(ctx, obj, seq, rx, signal, n_samples, snaps, n_snapshots, S_override, &r);
+    ps_status st = plan_single(ctx, obj, seq, rx, signal, n_samples, snaps, n_snapshots, force, &r);
     if (st != PS_OK) return st;
     if (r.empty()) return enqueue_single(ctx, r, SingleBuffers{}, stream, nullptr);
     BufSet* set = nullptr;
@@ -476,7 +480,9 @@ ps_status ps_simulate(ps_ctx* handle, const ps_object* obj, const ps_sequence* s
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
-    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, nullptr);
+    const ps_status tst = autotune_if_new(ctx, obj, seq, nullptr, reinterpret_cast<hipStream_t>(stream));
+    if (tst != PS_OK) return tst;
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), nullptr, nullptr);
 }
 
 ps_status ps_count_snapshots(const ps_sequence* seq, int64_t* n_snapshots) {
@@ -497,7 +503,9 @@ ps_status ps_simulate_ex(ps_ctx* handle, const ps_object* obj, const ps_sequence
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
-    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, rx, snapshots,
+    const ps_status tst = autotune_if_new(ctx, obj, seq, rx, reinterpret_cast<hipStream_t>(stream));
+    if (tst != PS_OK) return tst;
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), nullptr, rx, snapshots,
                        n_snapshots);
 }
 
@@ -508,7 +516,9 @@ ps_status ps_simulate_rx(ps_ctx* handle, const ps_object* obj, const ps_sequence
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
-    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), 0, rx);
+    const ps_status tst = autotune_if_new(ctx, obj, seq, rx, reinterpret_cast<hipStream_t>(stream));
+    if (tst != PS_OK) return tst;
+    return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), nullptr, rx);
 }
 
 ps_status ps_tile(ps_ctx* handle, int64_t n_spins, int32_t* spins_per_lane, int64_t* spins_per_block) {
@@ -516,7 +526,7 @@ ps_status ps_tile(ps_ctx* handle, int64_t n_spins, int32_t* spins_per_lane, int6
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     if (n_spins < 0) return fail(PS_E_INVALID_ARG, "n_spins < 0");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    const int S = choose_spins_per_lane(ctx, n_spins);
+    const int S = threshold_spins_per_lane(ctx, n_spins);
     if (spins_per_lane) *spins_per_lane = S;
     if (spins_per_block) *spins_per_block = spins_per_block_of(S);
     return PS_OK;

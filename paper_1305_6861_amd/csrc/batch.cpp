@@ -34,7 +34,9 @@ ps_status plan_request(const Ctx* ctx, const ps_object* obj, const ps_sequence* 
     if (st != PS_OK) return st;
     p->obj = *obj;
     p->signal = signal;
-    p->S = choose_spins_per_lane(ctx, obj->n_spins);
+    const Tiling tl = choose_tiling(ctx, obj->n_spins, seq, 0);
+    p->S = tl.S;
+    p->replica_mode = tl.replicas;
     const int64_t spb = spins_per_block_of(p->S);
     p->n_blocks = (obj->n_spins + spb - 1) / spb;
     p->n_rows = p->n_blocks * rows_per_block_of(p->S);
@@ -152,22 +154,6 @@ StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     return a;
 }
 
-// Host image of one round's launch records, laid out for a single upload.
-struct RoundImage {
-    struct Class {                      // one spins-per-lane class
-        int S;
-        size_t items_off;               // offset of its BatchItem array in the image
-        size_t counter_off;             // offset of its queue counter
-        int32_t n_req;
-        int64_t total;
-        size_t dyn_lds;                 // largest dynamic LDS of its requests
-    };
-    std::vector<Class> classes;
-    size_t fin_off = 0;
-    int32_t n_fin = 0;
-    int64_t tiles1 = 0, tiles2 = 0;
-};
-
 // Rough work per spin of one slice of a request: one unit per sample and
 // sub-step, a few for every other operation.
 static int64_t slice_cost(const ReqPlan& p, size_t k) {
@@ -182,22 +168,20 @@ static int64_t slice_cost(const ReqPlan& p, size_t k) {
     return c;
 }
 
-ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first_slice,
-                     const std::vector<size_t>& n_slices_this_call, hipStream_t stream, DevBuf& arena,
-                     HostBuf& staging, std::vector<RoundImage>* rounds_out) {
-    // plans[i] runs slices first_slice[i] .. first_slice[i] + n_slices_this_call[i] - 1,
-    // one per round.  Tables (ops, rows) must already be resident (uploaded by the caller).
-    (void)rounds_out;
+ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first_slice,
+                       const std::vector<size_t>& n_slices_this_call, std::vector<unsigned char>* img_out,
+                       std::vector<RoundImage>* rounds_out) {
     size_t max_rounds = 0;
     for (size_t i = 0; i < plans.size(); ++i) max_rounds = std::max(max_rounds, n_slices_this_call[i]);
-    // build all rounds' records in one host image
-    std::vector<unsigned char> img;
+    std::vector<unsigned char>& img = *img_out;
+    img.clear();
     auto reserve_bytes = [&](size_t n) {
         const size_t off = align_up(img.size(), 64);
         img.resize(off + n);
         return off;
     };
-    std::vector<RoundImage> rounds(max_rounds);
+    std::vector<RoundImage>& rounds = *rounds_out;
+    rounds.assign(max_rounds, RoundImage());
     for (size_t k = 0; k < max_rounds; ++k) {
         RoundImage& R = rounds[k];
         std::map<int, std::vector<size_t>> by_S;
@@ -224,7 +208,7 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
             for (size_t q = 0; q < kv.second.size(); ++q) tiles += plans[kv.second[q]]->n_blocks;
             for (size_t q = 0; q < kv.second.size(); ++q) {
                 ReqPlan* p = plans[kv.second[q]];
-                const int R = replicas_for_load(ctx, tiles, p->max_replicas);
+                const int R = replicas_for_load(ctx, tiles, p->max_replicas, p->replica_mode);
                 BatchItem it;
                 std::memset(&it, 0, sizeof(it));
                 it.args = p->args_for_slice(first_slice[kv.second[q]] + k, R);
@@ -242,12 +226,11 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
         }
         // finalize records for requests whose slice k has samples
         std::vector<FinDesc> fd;
-        int64_t t1 = 0, t2 = 0;
         for (size_t i = 0; i < plans.size(); ++i) {
             if (k >= n_slices_this_call[i]) continue;
             ReqPlan* p = plans[i];
             const Slice& sl = p->prog.slices[first_slice[i] + k];
-            if (sl.n_samples == 0) continue;
+            if (sl.n_samples == 0 || p->obj.n_spins == 0) continue;   // empty objects are zero-filled apart
             FinDesc f;
             std::memset(&f, 0, sizeof(f));
             f.partial = p->d_partial;
@@ -257,15 +240,11 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
             f.n_groups = p->n_groups;
             f.out = p->signal + 2 * sl.sample_begin;
             f.mid = p->d_mid;
-            f.tile_begin1 = t1;
-            f.tile_begin2 = t2;
-            t1 += std::max<int64_t>(f.n_groups, 1) * finalize_tiles(f.n_vals);   // kFinVals values a thread
-            if (f.n_groups > 1) t2 += (f.n_vals + 255) / 256;                   // one value a thread
-            if (p->obj.n_spins == 0) continue;   // zero-filled separately
             fd.push_back(f);
         }
-        // recompute the prefix sums over the records kept
-        t1 = 0; t2 = 0;
+        // prefix sums of the pass-1 blocks (kFinVals values a thread) and
+        // pass-2 blocks (one value a thread)
+        int64_t t1 = 0, t2 = 0;
         for (FinDesc& f : fd) {
             f.tile_begin1 = t1; f.tile_begin2 = t2;
             t1 += std::max<int64_t>(f.n_groups, 1) * finalize_tiles(f.n_vals);
@@ -278,27 +257,45 @@ ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<s
             std::memcpy(img.data() + R.fin_off, fd.data(), sizeof(FinDesc) * fd.size());
         }
     }
-    if (img.empty()) return PS_OK;
-    ps_status st;
+    return PS_OK;
+}
+
+ps_status round_nodes(const Ctx* ctx, const RoundImage& R, unsigned char* dev, std::vector<KernelNode>* nodes) {
+    for (const RoundImage::Class& c : R.classes) {
+        const hipError_t e = batch_step_nodes(reinterpret_cast<const BatchItem*>(dev + c.items_off), c.n_req,
+                                              c.total, reinterpret_cast<unsigned long long*>(dev + c.counter_off),
+                                              c.dyn_lds, ctx->cfg.precision, c.S, ctx->n_cu, nodes);
+        if (e != hipSuccess) return hip_fail(e, "batch step node");
+    }
+    if (R.n_fin > 0) {
+        const hipError_t e = batch_finalize_nodes(reinterpret_cast<const FinDesc*>(dev + R.fin_off), R.n_fin,
+                                                  R.tiles1, R.tiles2, ctx->cfg.precision, nodes);
+        if (e != hipSuccess) return hip_fail(e, "batch finalize node");
+    }
+    return PS_OK;
+}
+
+ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first_slice,
+                     const std::vector<size_t>& n_slices_this_call, hipStream_t stream, DevBuf& arena,
+                     HostBuf& staging) {
+    // plans[i] runs slices first_slice[i] .. first_slice[i] + n_slices_this_call[i] - 1,
+    // one per round.  Tables (ops, rows) must already be resident (uploaded by the caller).
+    std::vector<unsigned char> img;
+    std::vector<RoundImage> rounds;
+    ps_status st = build_rounds(ctx, plans, first_slice, n_slices_this_call, &img, &rounds);
+    if (st != PS_OK || img.empty()) return st;
     if ((st = arena.reserve(img.size())) != PS_OK) return st;
     if ((st = staging.reserve(img.size())) != PS_OK) return st;
     std::memcpy(staging.ptr, img.data(), img.size());
     hipError_t e = hipMemcpyAsync(arena.ptr, staging.ptr, img.size(), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch records)");
     unsigned char* dev = reinterpret_cast<unsigned char*>(arena.ptr);
-    for (size_t k = 0; k < rounds.size(); ++k) {
-        const RoundImage& R = rounds[k];
-        for (const RoundImage::Class& c : R.classes) {
-            e = launch_batch_step(reinterpret_cast<const BatchItem*>(dev + c.items_off), c.n_req, c.total,
-                                  reinterpret_cast<unsigned long long*>(dev + c.counter_off), c.dyn_lds,
-                                  ctx->cfg.precision, c.S, ctx->n_cu, stream);
-            if (e != hipSuccess) return hip_fail(e, "batch step launch");
-        }
-        if (R.n_fin > 0) {
-            e = launch_batch_finalize(reinterpret_cast<const FinDesc*>(dev + R.fin_off), R.n_fin, R.tiles1,
-                                      R.tiles2, ctx->cfg.precision, stream);
-            if (e != hipSuccess) return hip_fail(e, "batch finalize launch");
-        }
+    std::vector<KernelNode> nodes;
+    for (const RoundImage& R : rounds) {
+        nodes.clear();
+        if ((st = round_nodes(ctx, R, dev, &nodes)) != PS_OK) return st;
+        for (KernelNode& n : nodes)
+            if ((e = n.launch(stream)) != hipSuccess) return hip_fail(e, "batch launch");
     }
     return PS_OK;
 }
@@ -372,6 +369,10 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    for (int32_t i = 0; i < n_requests; ++i) {
+        const ps_status tst = autotune_if_new(ctx, &objs[i], &seqs[i], nullptr, stream);
+        if (tst != PS_OK) return fail(tst, "request " + std::to_string(i) + ": " + ps_last_error());
+    }
     std::vector<ReqPlan> plans((size_t)n_requests);
     {
         // Compiling the requests' sequences is independent host work: spread
@@ -432,7 +433,7 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
     }
     if (ptrs.empty()) return PS_OK;
     st = upload_tables_contiguous(with_tables, set->batch_tables.ptr, set->staging, stream);
-    if (st == PS_OK) st = run_rounds(ctx, ptrs, first, count, stream, set->batch_records, set->staging2, nullptr);
+    if (st == PS_OK) st = run_rounds(ctx, ptrs, first, count, stream, set->batch_records, set->staging2);
     // the set's staging may be in a copy on `stream` even after a failure
     const ps_status rel = release_set_after(set, stream);
     return st != PS_OK ? st : rel;

@@ -17,6 +17,7 @@ struct ReqPlan {
     double* signal = nullptr;
     Program prog;
     int S = 1;
+    int32_t replica_mode = REPLICAS_RULE;
     ReplicaBound max_replicas;         // readout replicas one tile can use
     int64_t n_blocks = 0, n_rows = 0, row_stride = 0, n_groups = 0;
     size_t bytes_partial = 0, bytes_state = 0, bytes_mid = 0, bytes_ops = 0, bytes_rows = 0, bytes_traj = 0;
@@ -48,12 +49,35 @@ ps_status upload_tables(std::vector<ReqPlan*>& plans, HostBuf& staging, size_t s
 // from device address dev: one host image, one copy.
 ps_status upload_tables_contiguous(std::vector<ReqPlan*>& plans, void* dev, HostBuf& staging, hipStream_t stream);
 
-struct RoundImage;
-// Run slices first[i] .. first[i] + count[i] - 1 of every plan, one slice per
-// round, each round one persistent launch per spins-per-lane class plus one
-// batched finalize.  Launch records go through arena/staging.
+// Host image of one round's launch records, laid out for a single upload:
+// per spins-per-lane class its request records and queue counter (zero),
+// then the round's finalize records.
+struct RoundImage {
+    struct Class {                      // one spins-per-lane class
+        int S;
+        size_t items_off;               // offset of its BatchItem array in the image
+        size_t counter_off;             // offset of its queue counter
+        int32_t n_req;
+        int64_t total;
+        size_t dyn_lds;                 // largest dynamic LDS of its requests
+    };
+    std::vector<Class> classes;
+    size_t fin_off = 0;
+    int32_t n_fin = 0;
+    int64_t tiles1 = 0, tiles2 = 0;
+};
+// Records of slices first[i] .. first[i] + count[i] - 1 of every plan, one
+// slice per round, all rounds in one host image (no device work).
+ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first,
+                       const std::vector<size_t>& count, std::vector<unsigned char>* img,
+                       std::vector<RoundImage>* rounds);
+// The launches of one round whose image sits at device address dev: one
+// persistent step kernel per spins-per-lane class, then the batched
+// finalize passes, appended to *nodes.
+ps_status round_nodes(const Ctx* ctx, const RoundImage& round, unsigned char* dev, std::vector<KernelNode>* nodes);
+// build_rounds, one upload of the image through arena/staging, and every
+// round's launches, stream-ordered.
 ps_status run_rounds(Ctx* ctx, std::vector<ReqPlan*>& plans, const std::vector<size_t>& first,
-                     const std::vector<size_t>& count, hipStream_t stream, DevBuf& arena, HostBuf& staging,
-                     std::vector<RoundImage>* rounds_out);
+                     const std::vector<size_t>& count, hipStream_t stream, DevBuf& arena, HostBuf& staging);
 
 }  // namespace ps

@@ -1527,6 +1527,83 @@ hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, in
     return hipSuccess;
 }
 
+hipKernelNodeParams KernelNode::params() {
+    argv[0] = &a0; argv[1] = &a1; argv[2] = &a2; argv[3] = &a3;
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(func);
+    p.gridDim = grid;
+    p.blockDim = block;
+    p.sharedMemBytes = (unsigned int)shmem;
+    p.kernelParams = argv;
+    p.extra = nullptr;
+    return p;
+}
+
+hipError_t KernelNode::launch(hipStream_t st) {
+    const hipKernelNodeParams p = params();
+    return hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, p.sharedMemBytes, st);
+}
+
+template <typename real, int S>
+static hipError_t batch_node_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
+                               size_t dyn, int n_cu, std::vector<KernelNode>* out) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S>, kBlock, dyn) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t grid = std::min<int64_t>(total, (int64_t)per_cu * n_cu);
+    if (grid <= 0) return hipSuccess;
+    KernelNode k;
+    k.func = reinterpret_cast<const void*>(&batch_step_kernel<real, S>);
+    k.grid = dim3((unsigned)grid);
+    k.block = dim3(kBlock);
+    k.shmem = dyn;
+    k.n_args = 4;
+    k.a0 = reqs; k.a1 = n_req; k.a2 = total; k.a3 = counter;
+    out->push_back(k);
+    return hipSuccess;
+}
+
+hipError_t batch_step_nodes(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
+                            size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out) {
+    if (precision == 64) {
+        switch (spins_per_lane) {
+            case 1: return batch_node_t<double, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
+            case 2: return batch_node_t<double, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (spins_per_lane) {
+        case 1: return batch_node_t<float, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
+        case 2: return batch_node_t<float, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
+        case 4: return batch_node_t<float, 4>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
+        case 8: return batch_node_t<float, 8>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
+                                std::vector<KernelNode>* out) {
+    if (tiles1 > 0) {
+        KernelNode k;
+        k.func = precision == 64 ? reinterpret_cast<const void*>(&batch_finalize_pass1<double>)
+                                 : reinterpret_cast<const void*>(&batch_finalize_pass1<float>);
+        k.grid = dim3((unsigned)tiles1);
+        k.n_args = 2;
+        k.a0 = d; k.a1 = n;
+        out->push_back(k);
+    }
+    if (tiles2 > 0) {
+        KernelNode k;
+        k.func = reinterpret_cast<const void*>(&batch_finalize_pass2);
+        k.grid = dim3((unsigned)tiles2);
+        k.n_args = 2;
+        k.a0 = d; k.a1 = n;
+        out->push_back(k);
+    }
+    return hipSuccess;
+}
+
 int64_t spins_per_block_of(int spins_per_lane) { return (int64_t)kBlock * spins_per_lane; }
 
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,

@@ -53,7 +53,9 @@ ps_status ps_plan_create(ps_ctx* handle, const ps_object* obj, const ps_sequence
     DeviceGuard g(ctx->cfg.device);
     Plan* p = new Plan();
     p->ctx = ctx;
-    ps_status st = plan_single(ctx, obj, seq, rx, signal, n_samples, nullptr, -1, 0, &p->r);
+    ps_status st = autotune_if_new(ctx, obj, seq, rx, nullptr);
+    if (st != PS_OK) { plan_free(p); return st; }
+    st = plan_single(ctx, obj, seq, rx, signal, n_samples, nullptr, -1, nullptr, &p->r);
     if (st != PS_OK) { plan_free(p); return st; }
     const Program& prog = p->r.prog;
     hipError_t e;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ps_ops.h"
 
 namespace ps {
@@ -88,6 +90,29 @@ hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total
                              size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st);
 hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
                                  hipStream_t st);
+
+// A kernel launch described for a HIP graph kernel node or a direct launch:
+// the kernel, its grid and the argument values (at most four; argv points
+// into this object, so set it up again with params() after a copy).
+struct KernelNode {
+    const void* func = nullptr;
+    dim3 grid{1, 1, 1}, block{256, 1, 1};
+    size_t shmem = 0;
+    int n_args = 0;
+    const void* a0 = nullptr;
+    int32_t a1 = 0;
+    int64_t a2 = 0;
+    void* a3 = nullptr;
+    void* argv[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipKernelNodeParams params();
+    hipError_t launch(hipStream_t st);
+};
+// The launches launch_batch_step / launch_batch_finalize would make, as
+// nodes appended to *out (none when there is nothing to run).
+hipError_t batch_step_nodes(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
+                            size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out);
+hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
+                                std::vector<KernelNode>* out);
 int64_t row_group_size();
 
 }  // namespace ps

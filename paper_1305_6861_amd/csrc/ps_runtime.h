@@ -2,8 +2,10 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -55,6 +57,38 @@ struct BufSet {
 };
 constexpr int kBufSets = 2;
 
+// How a request is tiled: spins per lane (S) and how its readouts are split
+// over workgroup replicas when its tiles leave compute units idle.
+enum ReplicaMode : int32_t {
+    REPLICAS_NONE = 0,    // one workgroup per tile
+    REPLICAS_RULE = 1,    // replicas_for_load's rule
+    REPLICAS_DOUBLE = 2,  // twice the rule's count (within the tile's bound)
+};
+struct Tiling {
+    int S = 1;
+    int32_t replicas = REPLICAS_RULE;
+    bool tuned = false;   // taken from the autotuner's table
+};
+
+// Class of requests the autotuner keeps one tiling for: precision, object
+// size, readout length, shaped pulses or not, receive coils (tune.cpp).
+struct TuneKey {
+    int32_t precision = 32;
+    int32_t spins_log2 = 0;     // floor(log2(n_spins)), -1 for none
+    int32_t readout_log2 = -1;  // floor(log2(longest readout in samples)), -1 without readouts
+    int32_t shaped = 0;         // any shaped pulse
+    int32_t coils_log2 = 0;     // ceil(log2(n_coils)), 0 for one homogeneous coil
+    bool operator<(const TuneKey& o) const {
+        return std::tie(precision, spins_log2, readout_log2, shaped, coils_log2) <
+               std::tie(o.precision, o.spins_log2, o.readout_log2, o.shaped, o.coils_log2);
+    }
+};
+struct TuneEntry {
+    Tiling tiling;
+    double best_ms = 0.0;       // the winner's time on the probe
+    double rule_ms = 0.0;       // the threshold rule's tiling on the same probe
+};
+
 struct Ctx {
     ps_config cfg{};
     int n_cu = 256;
@@ -65,9 +99,23 @@ struct Ctx {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> step_marks, fin_marks;
     Server* server = nullptr;
+    std::map<TuneKey, TuneEntry> tuned;   // autotuner table (guarded by mu)
 };
 
-int choose_spins_per_lane(const Ctx* ctx, int64_t n_spins);
+// The fixed threshold rule: 2 spins per lane once the object fills the
+// device twice over at that size, else 1 (or the configured value).
+int threshold_spins_per_lane(const Ctx* ctx, int64_t n_spins);
+// Tuner class of a request (seq must be valid; n_coils 0 = one homogeneous coil).
+TuneKey tune_key(const Ctx* ctx, int64_t n_spins, const ps_sequence* seq, int n_coils);
+// The tiling a request gets: the configured spins per lane if set, else the
+// autotuner's entry for its class, else the threshold rule (with the
+// readout-replica rule, or no replicas under PS_CFG_NO_READOUT_SPLIT).
+Tiling choose_tiling(const Ctx* ctx, int64_t n_spins, const ps_sequence* seq, int n_coils);
+// With PS_CFG_AUTOTUNE: tune the request's class first if the table has no
+// entry for it (synchronous; the probe runs after the work already queued
+// on `after`).  A no-op otherwise.
+ps_status autotune_if_new(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
+                          hipStream_t after);
 hipEvent_t timing_event(Ctx* ctx);  // from the pool (timing-enabled contexts)
 ps_status validate_object(const ps_object* obj);
 // max_partial_bytes > 0 overrides the context's bound on the partial rows.
@@ -91,12 +139,13 @@ struct ReplicaBound {
     int work = 1;
 };
 ReplicaBound replica_bound(const Program& p, int n_out);
-int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound);
+int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32_t mode = REPLICAS_RULE);
 
 // One request compiled for a context: program, tiling and buffer sizes.
 struct Single {
     Program prog;
     int S = 1, n_coils = 0, n_out = 1;
+    int32_t replica_mode = REPLICAS_RULE;
     int n_replicas = 1;            // readout replicas per tile
     int64_t n_blocks = 0, n_rows = 0, coil_stride = 0, row_stride = 0;
     bool any_snaps = false;
@@ -117,15 +166,16 @@ struct SingleBuffers {
     void* state = nullptr;
     double* fin_scratch = nullptr;
 };
+// force: a tiling to use instead of choose_tiling's (NULL: choose).
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
-                      double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, int S_override,
+                      double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, const Tiling* force,
                       Single* r, int64_t max_partial_bytes = 0);
 // Stream-ordered launches of a planned request (tables already resident in
 // b); kernel timing events go to timing_ctx when it is not NULL.
 ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b, hipStream_t stream,
                          Ctx* timing_ctx);
 ps_status run_request(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, double* signal,
-                      int64_t n_samples, hipStream_t stream, int S_override, const ps_receive* rx,
+                      int64_t n_samples, hipStream_t stream, const Tiling* force, const ps_receive* rx,
                       void* snaps = nullptr, int64_t n_snapshots = -1);
 void destroy_runtime(Ctx* ctx);    // stops the server if one runs
 

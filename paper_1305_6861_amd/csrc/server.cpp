@@ -12,6 +12,20 @@
 // waiting for them to finish.  Spin state stays in HBM between slices.
 // A request is bitwise the same alone or in any mix: its tiling and slice
 // plan depend only on itself.
+//
+// The loop keeps two short iterations in flight: the slice plan of every request
+// is fixed at submission, so the host knows which requests an iteration
+// finishes without waiting for the device, and plans, uploads and launches
+// iteration i + 1 while iteration i runs.  Each in-flight iteration has its
+// own launch records, staging buffers and events (two slots, used in turn);
+// the host waits on the device only to reuse a slot, whose completed
+// iteration it then retires (finished requests are signalled and their
+// memory returns to the pool).  An iteration's launches are replayed from a
+// HIP graph of the slot, one per launch topology (the kernels of its
+// spins-per-lane classes and finalize passes); a known topology only gets
+// its kernel-node arguments updated, and the slot's previous replay has
+// completed by then.  The graph holds kernel nodes only: the queue counters
+// are zeroed by the records' upload.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -43,7 +57,10 @@ struct Request {
     int32_t state = RQ_QUEUED;
     ps_status status = PS_OK;
     bool cancel = false;
-    size_t next_slice = 0;
+    size_t enqueued = 0;               // slices launched so far
+    size_t completed = 0;              // slices whose iteration has completed
+    int inflight = 0;                  // iterations in flight that hold one of its slices
+    bool tables_up = false;            // op tables uploaded
     void* mem = nullptr;
     size_t mem_bytes = 0;
     size_t footprint = 0;
@@ -51,6 +68,12 @@ struct Request {
     double t_submit = 0, t_admit = -1, t_done = -1;
     double t_kernel = 0;               // device time of the iterations it ran in
     std::string error;
+    // device work of the request: one slice per iteration (an empty object
+    // is one zero fill)
+    size_t n_slices() const {
+        if (plan.prog.n_samples == 0) return 0;
+        return plan.obj.n_spins > 0 ? plan.prog.slices.size() : 1;
+    }
 };
 
 // Requests of at least this many spin-steps (a few ms of the whole device)
@@ -58,6 +81,22 @@ struct Request {
 // them all, while small requests keep joining every iteration beside the
 // one that runs.
 constexpr double kLargeWork = 2.5e10;
+
+// An iteration of at most this many spin-steps (about a millisecond of the
+// device) has the next one launched before it completes.
+constexpr double kAheadWork = 1e10;
+
+// Elementary intervals per spin in slice k of a request (ps_count's unit).
+static int64_t slice_steps(const ReqPlan& p, size_t k) {
+    if (k >= p.prog.slices.size()) return 0;
+    const Slice& sl = p.prog.slices[k];
+    int64_t w = 0;
+    for (int64_t i = sl.op_begin; i < sl.op_end; ++i) {
+        const Op& op = p.prog.ops[i];
+        w += (op.kind == OP_ADC || op.kind == OP_ADCT || op.kind == OP_SHAPE) ? op.n : 1;
+    }
+    return w;
+}
 
 // Device memory for admitted requests: freed blocks are kept and reused.
 struct Pool {
@@ -77,9 +116,37 @@ struct Pool {
     }
     void put(void* p, size_t n) { if (p) free_blocks.emplace(n, p); }
     void release() {
-        for (auto& kv : free_blocks) hipFree(kv.second);
+        for (auto& kv : free_blocks) (void)hipFree(kv.second);
         free_blocks.clear();
     }
+};
+
+// A HIP graph of one launch topology (the kernels of an iteration, in order).
+struct RoundGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        nodes.clear();
+    }
+};
+
+// Resources of one in-flight iteration.
+struct IterSlot {
+    DevBuf records;
+    HostBuf staging_rec, staging_tab;
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;   // timing of its kernels
+    hipEvent_t done = nullptr;                         // completion of all its work
+    bool busy = false;
+    bool timed = false;                                // ev_start / ev_end recorded
+    double work = 0.0;                                 // spin-steps of its slices
+    std::vector<std::shared_ptr<Request>> members;     // requests with work in it
+    std::map<std::vector<const void*>, RoundGraph> graphs;
+    std::vector<unsigned char> img;                    // host image of its records
 };
 
 struct Server {
@@ -96,10 +163,9 @@ struct Server {
     Clock::time_point t0;
     // device side, touched by the scheduler thread only
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    hipEvent_t ev_start = nullptr, ev_end = nullptr;   // timing of one iteration's kernels
-    DevBuf records;
-    HostBuf staging_rec, staging_tab;
+    IterSlot slots[2];
+    int next_slot = 0;
+    std::deque<int> inflight;          // slots in launch order
     Pool pool;
     // counters
     uint64_t iterations = 0;
@@ -107,6 +173,11 @@ struct Server {
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void loop();
     void finish(const std::shared_ptr<Request>& r, int32_t state, ps_status st, const std::string& err);
+    ps_status launch_iteration(IterSlot& sl, std::vector<ReqPlan*>& fresh, std::vector<ReqPlan*>& plans,
+                               std::vector<size_t>& first, std::vector<double*>& zero_fill,
+                               std::vector<int64_t>& zero_n);
+    ps_status launch_nodes(IterSlot& sl, std::vector<KernelNode>& nodes);
+    void retire_oldest(bool block, ps_status* err);
 };
 
 void Server::finish(const std::shared_ptr<Request>& r, int32_t state, ps_status st, const std::string& err) {
@@ -121,17 +192,139 @@ void Server::finish(const std::shared_ptr<Request>& r, int32_t state, ps_status 
     }
 }
 
+// Replay (or build) the slot's graph for this launch topology.
+ps_status Server::launch_nodes(IterSlot& sl, std::vector<KernelNode>& nodes) {
+    if (nodes.empty()) return PS_OK;
+    hipError_t e;
+    if (ctx->cfg.flags & PS_CFG_SERVE_DIRECT) {
+        for (KernelNode& n : nodes)
+            if ((e = n.launch(stream)) != hipSuccess) return hip_fail(e, "server launch");
+        return PS_OK;
+    }
+    std::vector<const void*> key;
+    for (const KernelNode& n : nodes) key.push_back(n.func);
+    RoundGraph& g = sl.graphs[key];
+    if (!g.exec) {
+        e = hipGraphCreate(&g.graph, 0);
+        for (size_t i = 0; i < nodes.size() && e == hipSuccess; ++i) {
+            const hipKernelNodeParams p = nodes[i].params();
+            hipGraphNode_t node = nullptr;
+            e = hipGraphAddKernelNode(&node, g.graph, i ? &g.nodes.back() : nullptr, i ? 1 : 0, &p);
+            if (e == hipSuccess) g.nodes.push_back(node);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            g.release();
+            sl.graphs.erase(key);
+            return hip_fail(e, "server graph");
+        }
+    } else {
+        for (size_t i = 0; i < nodes.size(); ++i) {
+            const hipKernelNodeParams p = nodes[i].params();
+            if ((e = hipGraphExecKernelNodeSetParams(g.exec, g.nodes[i], &p)) != hipSuccess)
+                return hip_fail(e, "server graph update");
+        }
+    }
+    if ((e = hipGraphLaunch(g.exec, stream)) != hipSuccess) return hip_fail(e, "server graph launch");
+    return PS_OK;
+}
+
+// Upload the fresh requests' tables and this iteration's records through the
+// slot's staging, then launch: zero fills of empty objects, the round's
+// graph, with the timing and completion events around them.
+ps_status Server::launch_iteration(IterSlot& sl, std::vector<ReqPlan*>& fresh, std::vector<ReqPlan*>& plans,
+                                   std::vector<size_t>& first, std::vector<double*>& zero_fill,
+                                   std::vector<int64_t>& zero_n) {
+    ps_status st = PS_OK;
+    hipError_t e;
+    if (!fresh.empty() && (st = upload_tables(fresh, sl.staging_tab, 0, stream)) != PS_OK) return st;
+    for (size_t i = 0; i < zero_fill.size(); ++i)
+        if ((e = launch_fill_zero(zero_fill[i], zero_n[i], stream)) != hipSuccess) return hip_fail(e, "fill");
+    sl.timed = false;
+    if (!plans.empty()) {
+        std::vector<size_t> count(plans.size(), 1);
+        std::vector<RoundImage> rounds;
+        if ((st = build_rounds(ctx, plans, first, count, &sl.img, &rounds)) != PS_OK) return st;
+        if (!sl.img.empty()) {
+            if ((st = sl.records.reserve(sl.img.size())) != PS_OK) return st;
+            if ((st = sl.staging_rec.reserve(sl.img.size())) != PS_OK) return st;
+            std::memcpy(sl.staging_rec.ptr, sl.img.data(), sl.img.size());
+            if ((e = hipMemcpyAsync(sl.records.ptr, sl.staging_rec.ptr, sl.img.size(), hipMemcpyHostToDevice,
+                                    stream)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(server records)");
+            std::vector<KernelNode> nodes;
+            for (const RoundImage& R : rounds)
+                if ((st = round_nodes(ctx, R, reinterpret_cast<unsigned char*>(sl.records.ptr), &nodes)) != PS_OK)
+                    return st;
+            if ((e = hipEventRecord(sl.ev_start, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((st = launch_nodes(sl, nodes)) != PS_OK) return st;
+            if ((e = hipEventRecord(sl.ev_end, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            sl.timed = true;
+        }
+    }
+    if ((e = hipEventRecord(sl.done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return PS_OK;
+}
+
+// Retire the oldest in-flight iteration once it has completed (block: wait
+// for it); its members advance, and those whose last slice it ran finish.
+void Server::retire_oldest(bool block, ps_status* err) {
+    if (inflight.empty()) return;
+    IterSlot& sl = slots[inflight.front()];
+    hipError_t e = block ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
+    if (e == hipErrorNotReady) return;
+    ps_status st = PS_OK;
+    if (e != hipSuccess) st = hip_fail(e, "server iteration");
+    double iter_kernel_s = 0.0;
+    if (st == PS_OK && sl.timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sl.ev_start, sl.ev_end) == hipSuccess) iter_kernel_s = 1e-3 * ms;
+    }
+    const std::string msg = st == PS_OK ? "" : ps_last_error();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        ++iterations;
+        for (auto& r : sl.members) {
+            r->inflight -= 1;
+            r->completed += 1;
+            if (r->plan.obj.n_spins > 0) r->t_kernel += iter_kernel_s;
+            if (r->state >= RQ_DONE) continue;
+            bool done = false;
+            if (st != PS_OK) { finish(r, RQ_FAILED, st, msg); done = true; }
+            else if (r->completed >= r->n_slices()) { finish(r, RQ_DONE, PS_OK, ""); done = true; }
+            else if (r->cancel && r->inflight == 0) { finish(r, RQ_CANCELLED, PS_E_CANCELLED, "cancelled"); done = true; }
+            if (done) active.erase(std::find(active.begin(), active.end(), r));
+        }
+        changed.notify_all();
+    }
+    sl.members.clear();
+    sl.busy = false;
+    inflight.pop_front();
+    if (err && st != PS_OK) *err = st;
+}
+
 void Server::loop() {
-    hipSetDevice(ctx->cfg.device);
+    (void)hipSetDevice(ctx->cfg.device);
     for (;;) {
+        // retire what the device has completed, without waiting
+        for (size_t n = inflight.size(); n > 0; --n) retire_oldest(false, nullptr);
         std::vector<std::shared_ptr<Request>> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
-            wake.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            auto runnable = [&] {
+                for (auto& r : active)
+                    if (r->enqueued < r->n_slices() && !r->cancel) return true;
+                    else if (r->cancel && r->inflight == 0) return true;
+                return false;
+            };
+            if (inflight.empty())
+                wake.wait(lk, [&] { return stop || !queue.empty() || runnable(); });
             if (stop) break;
-            // cancellations of running requests take effect between iterations
+            // cancellations of running requests take effect between
+            // iterations: no further slice is launched, and the request
+            // finishes once its slices in flight have completed
             for (auto it = active.begin(); it != active.end();) {
-                if ((*it)->cancel) {
+                if ((*it)->cancel && (*it)->inflight == 0) {
                     finish(*it, RQ_CANCELLED, PS_E_CANCELLED, "cancelled");
                     it = active.erase(it);
                 } else {
@@ -159,8 +352,7 @@ void Server::loop() {
             }
             changed.notify_all();
         }
-        // place and upload newly admitted requests
-        std::vector<ReqPlan*> fresh;
+        // place newly admitted requests
         for (auto& r : admitted) {
             ps_status st = pool.get(std::max<size_t>(r->plan.device_bytes(), 256), &r->mem);
             std::lock_guard<std::mutex> lk(mu);
@@ -174,81 +366,83 @@ void Server::loop() {
             r->plan.bind(reinterpret_cast<unsigned char*>(r->mem));
             r->state = RQ_RUNNING;
             r->t_admit = now();
-            active.push_back(r);
-            if (r->plan.obj.n_spins > 0) fresh.push_back(&r->plan);
-        }
-        std::vector<std::shared_ptr<Request>> running;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            running = active;
-        }
-        if (running.empty()) continue;
-        ps_status st = PS_OK;
-        if (!fresh.empty()) st = upload_tables(fresh, staging_tab, 0, stream);
-        // one slice of every running request (empty objects only zero-fill)
-        std::vector<ReqPlan*> plans;
-        std::vector<size_t> first, count;
-        for (auto& r : running) {
-            ReqPlan& p = r->plan;
-            if (p.prog.n_samples == 0) continue;
-            if (p.obj.n_spins == 0) {
-                if (r->next_slice == 0 && st == PS_OK) {
-                    hipError_t e = launch_fill_zero(p.signal, 2 * p.prog.n_samples, stream);
-                    if (e != hipSuccess) st = hip_fail(e, "fill");
-                }
+            if (r->n_slices() == 0) {            // no samples: nothing to run
+                finish(r, RQ_DONE, PS_OK, "");
+                changed.notify_all();
                 continue;
             }
-            plans.push_back(&p);
-            first.push_back(r->next_slice);
-            count.push_back(1);
+            active.push_back(r);
         }
-        const bool timed = st == PS_OK && !plans.empty();
-        if (timed) {
-            hipError_t e = hipEventRecord(ev_start, stream);
-            if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
-        }
-        if (st == PS_OK && !plans.empty())
-            st = run_rounds(ctx, plans, first, count, stream, records, staging_rec, nullptr);
-        if (timed && st == PS_OK) {
-            hipError_t e = hipEventRecord(ev_end, stream);
-            if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
-        }
-        if (st == PS_OK) {
-            hipError_t e = hipEventRecord(ev, stream);
-            if (e == hipSuccess) e = hipEventSynchronize(ev);
-            if (e != hipSuccess) st = hip_fail(e, "server iteration");
-        }
-        double iter_kernel_s = 0.0;
-        if (timed && st == PS_OK) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev_start, ev_end) == hipSuccess) iter_kernel_s = 1e-3 * ms;
-        }
-        std::string err = st == PS_OK ? "" : ps_last_error();
+        // the next iteration: one slice of every running request
+        std::vector<std::shared_ptr<Request>> members;
         {
             std::lock_guard<std::mutex> lk(mu);
-            ++iterations;
-            for (auto it = active.begin(); it != active.end();) {
-                auto& r = *it;
-                bool in_iter = std::find(running.begin(), running.end(), r) != running.end();
-                if (!in_iter) { ++it; continue; }
-                if (st != PS_OK) {
-                    finish(r, RQ_FAILED, st, err);
-                    it = active.erase(it);
-                    continue;
-                }
-                r->next_slice += 1;
-                if (r->plan.obj.n_spins > 0 && r->plan.prog.n_samples > 0) r->t_kernel += iter_kernel_s;
-                const size_t n_sl = r->plan.obj.n_spins > 0 ? r->plan.prog.slices.size() : 1;
-                if (r->plan.prog.n_samples == 0 || r->next_slice >= n_sl) {
-                    finish(r, RQ_DONE, PS_OK, "");
-                    it = active.erase(it);
-                } else {
-                    ++it;
-                }
+            for (auto& r : active)
+                if (!r->cancel && r->enqueued < r->n_slices()) members.push_back(r);
+        }
+        if (members.empty()) {
+            if (!inflight.empty()) retire_oldest(true, nullptr);
+            continue;
+        }
+        // Launch ahead only while iterations are short: there the host's
+        // retire-plan-launch gap would idle the device for a noticeable part
+        // of each iteration.  A long iteration first completes, so that a
+        // request arriving meanwhile joins the very next one.
+        if (!inflight.empty() &&
+            ((ctx->cfg.flags & PS_CFG_SERVE_DIRECT) || slots[inflight.back()].work > kAheadWork)) {
+            retire_oldest(true, nullptr);
+            continue;
+        }
+        if (slots[next_slot].busy) retire_oldest(true, nullptr);   // two in flight: wait for the older
+        IterSlot& sl = slots[next_slot];
+        std::vector<ReqPlan*> fresh, plans;
+        std::vector<size_t> first;
+        std::vector<double*> zero_fill;
+        std::vector<int64_t> zero_n;
+        sl.work = 0.0;
+        for (auto& r : members) {
+            ReqPlan& p = r->plan;
+            sl.work += (double)p.obj.n_spins * (double)slice_steps(p, r->enqueued);
+            if (p.obj.n_spins == 0) {
+                zero_fill.push_back(p.signal);
+                zero_n.push_back(2 * p.prog.n_samples);
+                continue;
+            }
+            if (!r->tables_up) fresh.push_back(&p);
+            plans.push_back(&p);
+            first.push_back(r->enqueued);
+        }
+        ps_status st = launch_iteration(sl, fresh, plans, first, zero_fill, zero_n);
+        if (st != PS_OK) {
+            // the stream may hold part of the iteration: let it drain, then
+            // fail the requests that had work in it
+            const std::string msg = ps_last_error();
+            (void)hipStreamSynchronize(stream);
+            while (!inflight.empty()) retire_oldest(true, nullptr);
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto& r : members) {
+                if (r->state >= RQ_DONE) continue;
+                finish(r, RQ_FAILED, st, msg);
+                active.erase(std::find(active.begin(), active.end(), r));
             }
             changed.notify_all();
+            continue;
         }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto& r : members) {
+                r->tables_up = true;
+                r->enqueued += 1;
+                r->inflight += 1;
+            }
+        }
+        sl.members = std::move(members);
+        sl.busy = true;
+        inflight.push_back(next_slot);
+        next_slot ^= 1;
     }
+    // the device may still run launched iterations: let them complete
+    while (!inflight.empty()) retire_oldest(true, nullptr);
 }
 
 void destroy_runtime(Ctx* ctx) {
@@ -268,13 +462,16 @@ void destroy_runtime(Ctx* ctx) {
         s->queue.clear();
         s->changed.notify_all();
     }
-    if (s->ev) hipEventDestroy(s->ev);
-    if (s->ev_start) hipEventDestroy(s->ev_start);
-    if (s->ev_end) hipEventDestroy(s->ev_end);
-    if (s->stream) hipStreamDestroy(s->stream);
-    s->records.release();
-    s->staging_rec.release();
-    s->staging_tab.release();
+    for (IterSlot& sl : s->slots) {
+        for (auto& kv : sl.graphs) kv.second.release();
+        if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
+        if (sl.ev_end) (void)hipEventDestroy(sl.ev_end);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        sl.records.release();
+        sl.staging_rec.release();
+        sl.staging_tab.release();
+    }
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     s->pool.release();
     delete s;
     ctx->server = nullptr;
@@ -287,14 +484,18 @@ static ps_status ensure_server(Ctx* ctx) {
     s->ctx = ctx;
     s->t0 = Clock::now();
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreate(&s->ev_start);
-    if (e == hipSuccess) e = hipEventCreate(&s->ev_end);
+    for (IterSlot& sl : s->slots) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&sl.ev_start);
+        if (e == hipSuccess) e = hipEventCreate(&sl.ev_end);
+    }
     if (e != hipSuccess) {
-        if (s->ev_end) hipEventDestroy(s->ev_end);
-        if (s->ev_start) hipEventDestroy(s->ev_start);
-        if (s->ev) hipEventDestroy(s->ev);
-        if (s->stream) hipStreamDestroy(s->stream);
+        for (IterSlot& sl : s->slots) {
+            if (sl.ev_end) (void)hipEventDestroy(sl.ev_end);
+            if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
+        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return hip_fail(e, "server stream/event");
     }

@@ -40,6 +40,11 @@ def test_served_mix_matches_oracle_and_alone_bitwise(ps):
         assert all(i["state"] == "done" for i in infos)
         assert infos[-1]["n_slices"] > 1
         stats = ctx.server_stats()
+        for t, i in zip(tickets, infos):                      # ps_stats while the context lives
+            st = t.stats()
+            assert st["t_queue"] >= 0 and st["t_e2e"] >= st["t_queue"]
+            assert 0 < st["t_kernel"] <= st["t_e2e"] + 1e-3  # device time within the request's life
+            assert st["t_kernel"] == i["t_kernel"]
     with ps.Context() as ctx:                                 # the 3-D job and one 2-D job alone
         alone3 = _np(ctx.submit(*reqs[-1]).wait(60.0))
         alone0 = _np(ctx.submit(*reqs[0]).wait(60.0))
@@ -48,11 +53,6 @@ def test_served_mix_matches_oracle_and_alone_bitwise(ps):
     for (o, s), got in zip(reqs, outs):
         ref = oracle.simulate(o, s)
         within(got, ref, TOL32)
-    for t, i in zip(tickets, infos):
-        st = t.stats()
-        assert st["t_queue"] >= 0 and st["t_e2e"] >= st["t_queue"]
-        assert 0 < st["t_kernel"] <= st["t_e2e"] + 1e-3      # device time within the request's life
-        assert st["t_kernel"] == i["t_kernel"]
     lat = [i["t_done"] - i["t_submit"] for i in infos]
     print(f"[serve] {len(reqs)} requests, iterations {stats['iterations']}, "
           f"latency p50 {np.percentile(lat, 50) * 1e3:.1f} ms max {max(lat) * 1e3:.1f} ms", flush=True)
@@ -171,3 +171,33 @@ def test_c5_stream_sample_against_the_oracle(ps):
     print(f"[serve] c5 sample: 200 2-D worst rel_l2 {worst2:.3e}, 20 3-D worst {worst3:.3e}, "
           f"iterations {stats['iterations']}", flush=True)
     assert worst2 <= TOL32 and worst3 <= TOL32
+
+
+def test_graph_replayed_and_direct_iterations_agree(ps):
+    """The served loop replays each iteration's kernels from a HIP graph and
+    launches the next short iteration before the previous completes; with
+    PS_CFG_SERVE_DIRECT it launches the kernels one by one.  A mix of 60
+    2-D requests and three 3-D jobs (many iterations, several launch
+    topologies, graphs re-parameterised many times) gives bitwise the same
+    results both ways and alone."""
+    from workloads.phantom import subset
+    sched = C.c5_stream(n_requests=600)
+    two_d = [(k, p) for _, k, p in sched if k == "c4"][:60]
+    three_d = [(k, p) for _, k, p in sched if k == "3d"][:3]
+    reqs = [(subset(o, 8, p % 8), s) for (k, p) in two_d for o, s in [C.c5_request(k, p)]]
+    reqs += [(subset(o, 64, p % 64), s) for (k, p) in three_d for o, s in [C.c5_request(k, p)]]
+    res = {}
+    for graphs in (True, False):
+        with ps.Context(serve_graphs=graphs) as ctx:
+            tickets = [ctx.submit(o, s) for o, s in reqs]
+            res[graphs] = [_np(t.wait(120.0)) for t in tickets]
+            iters = ctx.server_stats()["iterations"]
+        print(f"[serve] graphs={graphs}: {len(reqs)} requests in {iters} iterations", flush=True)
+    with ps.Context() as ctx:
+        alone = {i: _np(ctx.submit(*reqs[i]).wait(120.0)) for i in (0, 31, 59, 60, 62)}
+    for a, b in zip(res[True], res[False]):
+        np.testing.assert_array_equal(a, b)
+    for i, a in alone.items():
+        np.testing.assert_array_equal(res[True][i], a)
+    for i in (0, 59, 62):
+        within(res[True][i], oracle.simulate(*reqs[i]), TOL32, f"served request {i}")
