@@ -281,6 +281,31 @@ ps_status ps_plan_launch(ps_plan *plan, void *stream);
 /* Wait for the plan's last replay, then free it. */
 void ps_plan_destroy(ps_plan *plan);
 
+/* ps_simulate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the call allocates nothing -- no hipMalloc, hipFree or pinned allocation,
+ * no allocating library routine.  Its tables, partial-sum rows, finalize
+ * sums and slice state live in a static device array of 256 MiB
+ * (kNoAllocScratchBytes) that every GPU the library runs on holds from
+ * load to process end; its tables are uploaded from 8 MiB of pinned staging
+ * the context set aside at ps_create.  Arguments, output and errors as for
+ * ps_simulate; additionally PS_E_TOO_LARGE, with nothing launched, when the
+ * request does not fit: the tables exceed the staging, or the slice state
+ * (up to 30 reals per spin) plus the partial rows of its smallest time
+ * slices exceed the array.  When the context's partial-row bound would
+ * overflow the array the request runs in shorter time slices (the result
+ * then matches ps_simulate within FP32 rounding instead of bitwise).
+ * Nothing in the array has to start at zero: every value a launch reads was
+ * written earlier in the same call.  All calls on one GPU share the array
+ * (across contexts): calls on one stream run in order, calls that overlap
+ * on the device -- on different streams or from different contexts -- race
+ * and give undefined results.  The tiling is the table's or the rule's
+ * (PS_CFG_AUTOTUNE does not tune here, since tuning allocates).  A call
+ * waits on the host for the previous call's table upload before it reuses
+ * the staging. */
+ps_status ps_simulate_noalloc(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, double *signal,
+                              int64_t n_samples, void *stream);
+
 /* Simulate n_requests independent requests together, stream-ordered on
  * `stream`.  All workgroup tiles of all requests form one work queue that a
  * persistent kernel drains (one launch per spins-per-lane class and time

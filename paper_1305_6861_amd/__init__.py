@@ -381,6 +381,25 @@ class Context:
         return (sig, snap) if snapshots else sig
 
 
+def simulate_noalloc(ctx: "Context", obj, seq, out, stream=None):
+    """ps_simulate_noalloc: the signal of one request computed with the
+    library's static device scratch (the call allocates nothing).  obj must
+    be device tensors (to_device) and out a float64 tensor of 2 * n_samples
+    entries: allocating them is the caller's business."""
+    import torch
+    ps = pack_sequence(seq)
+    n_samples, _ = ps.count()
+    if out.dtype != torch.float64 or out.numel() != 2 * n_samples or not out.is_contiguous():
+        raise PsError(1, "out must be a contiguous float64 tensor of 2 * n_samples entries")
+    if stream is None:
+        stream = torch.cuda.current_stream(ctx.device)
+    o = _object_struct(obj)
+    _b.check(_b.lib.ps_simulate_noalloc(ctx._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                        ctypes.c_void_p(out.data_ptr() if n_samples else 0), n_samples,
+                                        ctypes.c_void_p(stream.cuda_stream)))
+    return out.view(torch.complex128)
+
+
 class Plan:
     """A request compiled once with its launches captured in a HIP graph
     (ps_plan_create); launch() replays it.  The object tensors, coil

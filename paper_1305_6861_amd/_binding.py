@@ -157,6 +157,8 @@ SIGNATURES = {
     "ps_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "ps_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
     "ps_tune_clear": (ctypes.c_int, [ctypes.c_void_p]),
+    "ps_simulate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                       ctypes.POINTER(ps_receive), ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),

@@ -438,6 +438,23 @@ ps_status ps_create(ps_ctx** out, const ps_config* cfg_in) {
             return hip_fail(e, "hipEventCreate");
         }
     }
+    // the allocation-free entry point's scratch (device static array, its
+    // address taken once per device with the device current) and staging
+    void* base = nullptr;
+    if ((e = noalloc_scratch(cfg.device, &base)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&ctx->noalloc_done, hipEventDisableTiming)) != hipSuccess) {
+        for (BufSet& c : ctx->sets) (void)hipEventDestroy(c.done);
+        if (ctx->noalloc_done) (void)hipEventDestroy(ctx->noalloc_done);
+        delete ctx;
+        return hip_fail(e, "allocation-free scratch set-up");
+    }
+    ctx->noalloc_base = base;
+    if (ctx->noalloc_staging.reserve(kNoAllocStagingBytes) != PS_OK) {
+        for (BufSet& c : ctx->sets) (void)hipEventDestroy(c.done);
+        (void)hipEventDestroy(ctx->noalloc_done);
+        delete ctx;
+        return fail(PS_E_NO_MEMORY, "pinned staging of the allocation-free entry point");
+    }
     *out = reinterpret_cast<ps_ctx*>(ctx);
     return PS_OK;
 }
@@ -456,6 +473,11 @@ void ps_destroy(ps_ctx* handle) {
         for (auto& m : ctx->fin_marks) hipEventDestroy(m.second);   // m.first is a step mark
         for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
         for (BufSet& b : ctx->sets) b.release();
+        if (ctx->noalloc_done) {
+            if (ctx->noalloc_pending) (void)hipEventSynchronize(ctx->noalloc_done);
+            (void)hipEventDestroy(ctx->noalloc_done);
+        }
+        ctx->noalloc_staging.release();
     }
     delete ctx;
 }
@@ -483,6 +505,80 @@ ps_status ps_simulate(ps_ctx* handle, const ps_object* obj, const ps_sequence* s
     const ps_status tst = autotune_if_new(ctx, obj, seq, nullptr, reinterpret_cast<hipStream_t>(stream));
     if (tst != PS_OK) return tst;
     return run_request(ctx, obj, seq, signal, n_samples, reinterpret_cast<hipStream_t>(stream), nullptr, nullptr);
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+ps_status ps_simulate_noalloc(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq, double* signal,
+                              int64_t n_samples, void* stream_v) {
+    clear_error();
+    if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->cfg.device);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    if (!ctx->noalloc_base) return fail(PS_E_DEVICE, "no static scratch on this context's device");
+    // Lay the request out in the scratch: tables, partial rows, finalize
+    // row-group sums, slice state.  First with the context's own bound on the
+    // partial rows (the time slicing of ps_simulate), then, while it does not
+    // fit, with the partial rows held to what the rest leaves (more slices).
+    const size_t cap = (size_t)kNoAllocScratchBytes;
+    Single r;
+    size_t off_rows = 0, off_traj = 0, off_part = 0, off_fin = 0, off_state = 0, total = 0;
+    int64_t budget = ctx->cfg.max_partial_bytes;
+    for (int attempt = 0;; ++attempt) {
+        r = Single();
+        ps_status st = plan_single(ctx, obj, seq, nullptr, signal, n_samples, nullptr, -1, nullptr, &r, budget);
+        if (st != PS_OK) return st;
+        const Program& prog = r.prog;
+        off_rows = align256(prog.ops.size() * sizeof(Op));
+        off_traj = off_rows + align256(prog.rows.size() * sizeof(double));
+        off_part = off_traj + align256(prog.traj.size() * sizeof(double));
+        off_fin = off_part + align256(r.partial_bytes);
+        off_state = off_fin + align256(r.fin_bytes);
+        total = off_state + align256(r.state_bytes);
+        if (r.empty() || total <= cap) break;
+        const size_t rest = total - align256(r.partial_bytes) - align256(r.fin_bytes);
+        // the finalize sums take about 1/32 of the FP32 (1/64 of the FP64) partial rows
+        const size_t room = rest < cap ? (cap - rest) * 31 / 32 : 0;
+        const int64_t next = std::min<int64_t>((int64_t)room, (int64_t)r.partial_bytes / 2);
+        if (attempt >= 16 || next < 4096 || next >= budget)
+            return fail(PS_E_TOO_LARGE, "the request needs " + std::to_string(total) +
+                                            " bytes of scratch at its smallest time slices; the static scratch holds " +
+                                            std::to_string(cap));
+        budget = next;
+    }
+    if (r.empty()) return enqueue_single(ctx, r, SingleBuffers{}, stream, nullptr);
+    const Program& prog = r.prog;
+    const size_t ops_bytes = prog.ops.size() * sizeof(Op), rows_bytes = prog.rows.size() * sizeof(double);
+    const size_t traj_bytes = prog.traj.size() * sizeof(double);
+    if (ops_bytes + rows_bytes + traj_bytes > ctx->noalloc_staging.bytes)
+        return fail(PS_E_TOO_LARGE, "the request's tables take " + std::to_string(ops_bytes + rows_bytes + traj_bytes) +
+                                        " bytes; the staging of the allocation-free entry point holds " +
+                                        std::to_string(ctx->noalloc_staging.bytes));
+    hipError_t e;
+    // the staging is rewritten only after the previous upload from it has run
+    if (ctx->noalloc_pending) {
+        if ((e = hipEventSynchronize(ctx->noalloc_done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        ctx->noalloc_pending = false;
+    }
+    unsigned char* h = reinterpret_cast<unsigned char*>(ctx->noalloc_staging.ptr);
+    unsigned char* d = reinterpret_cast<unsigned char*>(ctx->noalloc_base);
+    std::memcpy(h, prog.ops.data(), ops_bytes);
+    if (rows_bytes) std::memcpy(h + ops_bytes, prog.rows.data(), rows_bytes);
+    if (traj_bytes) std::memcpy(h + ops_bytes + rows_bytes, prog.traj.data(), traj_bytes);
+    if ((e = hipMemcpyAsync(d, h, ops_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (rows_bytes && (e = hipMemcpyAsync(d + off_rows, h + ops_bytes, rows_bytes, hipMemcpyHostToDevice, stream)) !=
+                           hipSuccess) ||
+        (traj_bytes && (e = hipMemcpyAsync(d + off_traj, h + ops_bytes + rows_bytes, traj_bytes,
+                                           hipMemcpyHostToDevice, stream)) != hipSuccess))
+        return hip_fail(e, "hipMemcpyAsync(tables into the scratch)");
+    SingleBuffers b{d, d + off_rows, d + off_traj, d + off_part, r.state_bytes ? d + off_state : nullptr,
+                    r.fin_bytes ? reinterpret_cast<double*>(d + off_fin) : nullptr};
+    const ps_status enq = enqueue_single(ctx, r, b, stream, nullptr);
+    if ((e = hipEventRecord(ctx->noalloc_done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ctx->noalloc_pending = true;
+    return enq;
 }
 
 ps_status ps_count_snapshots(const ps_sequence* seq, int64_t* n_snapshots) {

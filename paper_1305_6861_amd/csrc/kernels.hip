@@ -41,6 +41,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "ps_kernels.h"
@@ -1605,6 +1606,34 @@ hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int
 }
 
 int64_t spins_per_block_of(int spins_per_lane) { return (int64_t)kBlock * spins_per_lane; }
+
+// Device memory of the allocation-free entry point: op and shaped-pulse
+// tables, partial-sum rows, finalize row-group sums and slice state of one
+// request at a time.  Every GPU the library runs on holds its own copy from
+// module load to process end.  Host code must not pass `scratch` itself to a
+// kernel or a copy (in host code the name stands for a host-side shadow, not
+// a device address): it uses the address hipGetSymbolAddress returns for the
+// current device, kept per device by noalloc_scratch.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the caller makes the device current
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
                        hipStream_t st) {

@@ -115,4 +115,12 @@ hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int
                                 std::vector<KernelNode>* out);
 int64_t row_group_size();
 
+// Bytes of the static device array behind the allocation-free entry point.
+constexpr int64_t kNoAllocScratchBytes = int64_t(256) << 20;
+constexpr int kMaxDevices = 64;
+// Device address of that array on `device`, which must be the current
+// device the first time it is asked for (hipGetSymbolAddress, cached per
+// device afterwards).
+hipError_t noalloc_scratch(int device, void** ptr);
+
 }  // namespace ps

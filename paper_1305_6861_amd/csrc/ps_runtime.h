@@ -100,7 +100,16 @@ struct Ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> step_marks, fin_marks;
     Server* server = nullptr;
     std::map<TuneKey, TuneEntry> tuned;   // autotuner table (guarded by mu)
+    // allocation-free entry point: the device's static scratch array, and
+    // pinned staging for its table uploads (both set up by ps_create)
+    void* noalloc_base = nullptr;
+    HostBuf noalloc_staging;
+    hipEvent_t noalloc_done = nullptr;    // the last upload from the staging has completed
+    bool noalloc_pending = false;
 };
+// Pinned staging a context sets aside for the allocation-free entry point's
+// table uploads (bounds the tables of a request it accepts).
+constexpr size_t kNoAllocStagingBytes = size_t(8) << 20;
 
 // The fixed threshold rule: 2 spins per lane once the object fills the
 // device twice over at that size, else 1 (or the configured value).
