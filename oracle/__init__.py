@@ -74,12 +74,17 @@ def load_library(path: str):
 
 
 def _load():
+    """The oracle library: PS_ORACLE_LIB names another build of the same
+    source (the sanitizer test's); else the in-tree one, built if missing."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
-        _build.build()
-    _lib = _configure(ctypes.CDLL(_build.LIB))
+    path = os.environ.get("PS_ORACLE_LIB")
+    if not path:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+    _lib = _configure(ctypes.CDLL(path))
     return _lib
 
 
