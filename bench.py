@@ -104,6 +104,50 @@ def bench_c4(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_kt(args):
+    """The K-t engine (ps_kt_simulate) on a 256 x 256 grid of four tissue
+    classes under a 256 x 256 spoiled GRE, against the isochromat stepper on
+    the same spins and sequence; the same signal both ways (lattice moments,
+    tissue-uniform parameters)."""
+    import torch
+    import paper_1305_6861_amd as ps
+    from workloads import configs as C
+    from workloads.phantom import kt_phantom_2d
+    fov = 0.25
+    obj, begin, t1, t2, dw, _ = kt_phantom_2d(256, fov)
+    seq = C.spoiled_gre_2d(256, 256, fov, dwell=10e-6)
+    dk = (1 / fov, 1 / fov, 0.0)
+    dev = ps.to_device(obj)
+    packed = ps.pack_sequence(seq)
+    n_samples, n_steps = packed.count()
+    ctx = ps.Context()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, out
+    t_kt, s_kt = timed(lambda: ctx.kt_simulate(dev, begin, t1, t2, dw, packed, dk))
+    t_iso, s_iso = timed(lambda: ctx.simulate(dev, packed))
+    import oracle
+    err = oracle.rel_l2(s_kt.cpu().numpy(), s_iso.cpu().numpy())
+    spin_steps = float(obj.n_spins) * n_steps
+    rec = {"metric": "spin-steps/s", "value": spin_steps / t_kt, "unit": "spin-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_kt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "K-t engine: 256x256 grid of 4 tissue classes (nested discs, %d spins), "
+                                  "256x256 spoiled GRE, lattice 1/FOV" % obj.n_spins,
+                      "n_spins": obj.n_spins, "n_steps_per_spin": n_steps, "n_samples": n_samples,
+                      "step": "full call: population tracking on the host, spectrum and superposition kernels"},
+           "isochromat_ms_per_step": t_iso * 1e3, "rel_l2_kt_vs_isochromat": err,
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_c5(args):
     """Poisson stream: served (continuous batching) vs FIFO one launch per
     request, both replaying the same arrival schedule in real time."""
@@ -388,7 +432,7 @@ def main():
                     help="0 = the autotuner's choice (or the threshold rule with --no-tune)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner: tiles from the threshold rule")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5"], default="c3",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5", "kt"], default="c3",
                     help="c3 (default, the reported workload: 3-D shaped-pulse configuration), "
                          "c2 (2-D spin echo), c4 (batched vs one launch per request), "
                          "c5 (served stream vs FIFO)")
@@ -436,6 +480,8 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.workload == "kt":
+        return bench_kt(args)
 
     import torch
     import paper_1305_6861_amd as ps

@@ -264,6 +264,54 @@ ps_status ps_kt_extent(const ps_sequence *seq, const double dk[3], double t1, do
                        const double extent[3], double k_max[3], double dx_max[3], int64_t *n_spins_min,
                        int64_t *n_configs_peak);
 
+/* ---- K-t simulation ------------------------------------------------------
+ * A second engine for the signal, after the K-t formalism (sections 4.2 -
+ * 4.4) and its simulation procedure (section 5.1.2): when every gradient
+ * moment of the sequence is an integer multiple of a lattice step dk per
+ * axis (per ADC sample inside readouts, per sub-step inside shapes), the
+ * magnetisation of a tissue with uniform T1, T2 and off-resonance is a
+ * finite series of configurations whose populations do not depend on
+ * position (eq. 4.7 - 4.11).  The host tracks them per tissue through the
+ * sequence (hard pulses eq. 4.14, relaxation eq. 4.15 / 4.16, gradients
+ * eq. 4.17, the off-resonance as a turn exp(-j dw t) of every transverse
+ * population); the device evaluates every tissue's spatial-frequency
+ * function at the configurations' lattice positions and superposes them
+ * at each sample (eq. 4.19):
+ *   s[n] = sum over tissues c and transverse orders q populated at sample n
+ *          of F_c(q) W(q) S_c(q dk),
+ *   S_c(k) = sum over the tissue's spins i of m0_i exp(-2 pi j k . x_i),
+ *   W(q) = prod over the axes d of sinc(q_d dk_d voxel_d), sinc(u) =
+ *          sin(pi u) / (pi u): the spectrum of a box voxel centred on each
+ *          spin (the signal integrated over the voxel, section 5.2), 1 for
+ *          point spins (voxel = 0).
+ * With point spins this equals ps_simulate of the same spins given their
+ * tissue's T1, T2 and off-resonance, for every lattice sequence.  Readings
+ * (operator order, sample instants, PS_EV_SPOIL) are ps_simulate's. */
+typedef struct ps_kt_object {
+    int32_t        n_tissues;    /* >= 1                                               */
+    int32_t        reserved;     /* 0                                                  */
+    const double  *t1, *t2;      /* HOST, n_tissues: s, > 0, +INF allowed              */
+    const double  *dw;           /* HOST, n_tissues: rad/s, uniform over the tissue    */
+    const int64_t *tissue_begin; /* HOST, n_tissues + 1: tissue c holds spins
+                                    tissue_begin[c] .. tissue_begin[c + 1] - 1;
+                                    tissue_begin[0] = 0, [n_tissues] = n_spins        */
+    int64_t        n_spins;      /* >= 0                                               */
+    const float   *x, *y, *z;    /* DEVICE, n_spins: voxel centres, m                  */
+    const float   *m0;           /* DEVICE, n_spins: M0 of the voxel (density x volume)*/
+    double         voxel[3];     /* box size per axis, m (0: point spins on that axis) */
+} ps_kt_object;
+/* Signal of obj under seq by the K-t engine, stream-ordered on `stream`.
+ * dk: HOST, lattice step per axis in cycles/m (0 on an axis with no
+ * moment).  signal: DEVICE, 2 * n_samples doubles as for ps_simulate; the
+ * spectrum is summed in the context's precision (FP32 or FP64 sine and
+ * cosine of FP64 phases), tiles and configurations in FP64.  The population
+ * tracking runs on the host during the call.  PS_E_INVALID_ARG for a moment
+ * off the lattice, trajectory readouts, tissue arrays that do not cover the
+ * spins, or the arguments ps_simulate refuses; PS_E_TOO_LARGE past 2^22
+ * configurations of a tissue or 2^28 (sample, configuration) pairs. */
+ps_status ps_kt_simulate(ps_ctx *ctx, const ps_kt_object *obj, const ps_sequence *seq, const double dk[3],
+                         double *signal, int64_t n_samples, void *stream);
+
 /* Compiled plans: one request compiled once and its kernel launches captured
  * in a HIP graph, for callers that simulate the same (object layout,
  * sequence, coils) many times, e.g. parameter sweeps that rewrite the object

@@ -235,6 +235,44 @@ class Context:
                                 "replicas": _b.REPLICA_MODES[int(r.cand_replicas[i])], "ms": float(r.cand_ms[i])}
                                for i in range(int(r.n_candidates))]}
 
+    def kt_simulate(self, obj, tissue_begin, t1, t2, dw, seq, dk, voxel=(0.0, 0.0, 0.0), stream=None):
+        """Signal by the K-t engine (ps_kt_simulate): obj's spins (x, y, z, m0;
+        ordered tissue by tissue, tissue c holding spins tissue_begin[c] ..
+        tissue_begin[c + 1] - 1) with per-tissue t1, t2 (s) and dw (rad/s),
+        a sequence whose moments lie on the lattice dk (cycles/m per axis),
+        and box voxels of size voxel (m per axis, 0 = point spins) centred
+        on the spins.  Returns a complex128 CUDA tensor."""
+        import torch
+        fields = ("x", "y", "z", "m0")
+        dev = {}
+        for f in fields:
+            v = obj[f] if isinstance(obj, dict) else getattr(obj, f)
+            t = v if isinstance(v, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(v, np.float32))
+            dev[f] = t.to(device=f"cuda:{self.device}", dtype=torch.float32).contiguous()
+        n_spins = int(dev["x"].numel())
+        tb = np.ascontiguousarray(tissue_begin, np.int64)
+        t1a = np.ascontiguousarray(t1, np.float64)
+        t2a = np.ascontiguousarray(t2, np.float64)
+        dwa = np.ascontiguousarray(dw, np.float64)
+        n_t = int(t1a.size)
+        if tb.size != n_t + 1 or t2a.size != n_t or dwa.size != n_t:
+            raise PsError(1, "tissue_begin needs n_tissues + 1 entries and t1, t2, dw n_tissues each")
+        ps = pack_sequence(seq)
+        n_samples, _ = ps.count()
+        out = torch.empty(2 * n_samples, dtype=torch.float64, device=f"cuda:{self.device}")
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        for t in dev.values():
+            t.record_stream(stream)
+        o = _b.ps_kt_object(n_t, 0, t1a.ctypes.data, t2a.ctypes.data, dwa.ctypes.data, tb.ctypes.data, n_spins,
+                            *[dev[f].data_ptr() if n_spins else 0 for f in fields],
+                            (ctypes.c_double * 3)(*[float(v) for v in voxel]))
+        dkv = (ctypes.c_double * 3)(*[float(v) for v in dk])
+        _b.check(_b.lib.ps_kt_simulate(self._h, ctypes.byref(o), ctypes.byref(ps.struct), dkv,
+                                       ctypes.c_void_p(out.data_ptr() if n_samples else 0), n_samples,
+                                       ctypes.c_void_p(stream.cuda_stream)))
+        return out.view(torch.complex128)
+
     def tune_save(self, path: str):
         _b.check(_b.lib.ps_tune_save(self._h, str(path).encode()))
 

@@ -105,6 +105,16 @@ class ps_tune_result(ctypes.Structure):
 
 assert ctypes.sizeof(ps_tune_result) == 232
 
+
+class ps_kt_object(ctypes.Structure):
+    _fields_ = [("n_tissues", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t1", ctypes.c_void_p),
+                ("t2", ctypes.c_void_p), ("dw", ctypes.c_void_p), ("tissue_begin", ctypes.c_void_p),
+                ("n_spins", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("m0", ctypes.c_void_p), ("voxel", ctypes.c_double * 3)]
+
+
+assert ctypes.sizeof(ps_kt_object) == 104
+
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 REPLICA_MODES = {0: "none", 1: "rule", 2: "twice the rule"}
 
@@ -157,6 +167,9 @@ SIGNATURES = {
     "ps_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "ps_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
     "ps_tune_clear": (ctypes.c_int, [ctypes.c_void_p]),
+    "ps_kt_simulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_kt_object), ctypes.POINTER(ps_sequence),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p]),
     "ps_simulate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libparspin.so")
 SOURCES = ["kernels.hip", "calib.hip", "compile.cpp", "api.cpp", "batch.cpp", "server.cpp",
-           "plan.cpp", "kt.cpp", "tune.cpp"]
+           "plan.cpp", "kt.cpp", "kt_engine.cpp", "tune.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

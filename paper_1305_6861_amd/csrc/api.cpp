@@ -25,6 +25,7 @@ static_assert(sizeof(ps_sequence) == 40, "ps_sequence ABI size");
 static_assert(sizeof(ps_trajectory) == 24, "ps_trajectory ABI size");
 static_assert(sizeof(ps_receive) == 24, "ps_receive ABI size");
 static_assert(sizeof(ps_tune_result) == 232, "ps_tune_result ABI size");
+static_assert(sizeof(ps_kt_object) == 104, "ps_kt_object ABI size");
 
 namespace ps {
 

@@ -1616,6 +1616,133 @@ int64_t spins_per_block_of(int spins_per_lane) { return (int64_t)kBlock * spins_
 // current device, kept per device by noalloc_scratch.
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
+// ---------------------------------------------------------------------------
+// K-t simulation (section 5.1.2, eq. 4.19): the object's spatial-frequency
+// function at the configurations' lattice positions, superposed per sample
+// ---------------------------------------------------------------------------
+// Spectrum: one workgroup per (tissue, block of up to 32 pairs, tile of up to
+// kKtTile spins of that tissue).  Every lane holds kKtSpl spins and forms,
+// for each pair p of the block, sum over its spins of
+// m0 exp(-2 pi j k_p . x) (phase in FP64 revolutions, reduced to one
+// revolution, then the hardware sine / cosine in FP32, or FP64 sincospi);
+// the 64 sums (32 pairs x re / im) are reduced across the wave's lanes by
+// the transpose-reduce, the four waves' results added in wave order, and
+// the tile's row written to partial[item].
+template <typename real>
+__global__ __launch_bounds__(kBlock) void kt_spectrum_kernel(const KtItem* __restrict__ items,
+                                                             const double* __restrict__ pair_k,
+                                                             const float* __restrict__ x,
+                                                             const float* __restrict__ y,
+                                                             const float* __restrict__ z,
+                                                             const float* __restrict__ m0,
+                                                             real* __restrict__ partial) {
+    __shared__ double s_k[kKtPairs][3];
+    __shared__ real s_red[kWaves][64];
+    const KtItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < 3 * kKtPairs; i += kBlock)
+        s_k[i / 3][i % 3] = i / 3 < it.n_pairs ? pair_k[3 * (it.pair_begin + i / 3) + i % 3] : 0.0;
+    double px[kKtSpl], py[kKtSpl], pz[kKtSpl];
+    real w[kKtSpl];
+#pragma unroll
+    for (int s = 0; s < kKtSpl; ++s) {
+        const int64_t j = (int64_t)(wave * kKtSpl + s) * 64 + lane;   // coalesced rows of 64
+        const bool in = j < it.n_spins;
+        const int64_t i = it.spin_begin + (in ? j : 0);
+        px[s] = in ? (double)x[i] : 0.0;
+        py[s] = in ? (double)y[i] : 0.0;
+        pz[s] = in ? (double)z[i] : 0.0;
+        w[s] = in ? (real)m0[i] : (real)0;
+    }
+    __syncthreads();
+    real v[64];
+#pragma unroll
+    for (int p = 0; p < kKtPairs; ++p) {
+        const double k0 = s_k[p][0], k1 = s_k[p][1], k2 = s_k[p][2];
+        real re = 0, im = 0;
+#pragma unroll
+        for (int s = 0; s < kKtSpl; ++s) {
+            real c, sn;
+            Math<real>::cis(fma(k0, px[s], fma(k1, py[s], k2 * pz[s])), c, sn);
+            re = fma(w[s], c, re);
+            im = fma(-w[s], sn, im);
+        }
+        v[2 * p] = re;
+        v[2 * p + 1] = im;
+    }
+    real r = wave_reduce64(v, lane);       // lane l: component l & 1 of pair l >> 1
+    s_red[wave][lane] = r;
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int g = 1; g < kWaves; ++g) r += s_red[g][lane];
+        partial[(int64_t)blockIdx.x * 64 + lane] = r;
+    }
+}
+
+// S(pair) = sum over the tiles of its tissue of the tiles' partial sums, in
+// tile order, FP64.
+template <typename real>
+__global__ void kt_pair_sum_kernel(const KtPairSum* __restrict__ ps, int64_t n_pairs, const real* __restrict__ partial,
+                                   double* __restrict__ spec) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_pairs) return;
+    const KtPairSum q = ps[u];
+    double re = 0.0, im = 0.0;
+    for (int32_t t = 0; t < q.n_tiles; ++t) {
+        const real* row = partial + (q.item0 + t) * 64 + 2 * q.slot;
+        re += (double)row[0];
+        im += (double)row[1];
+    }
+    spec[2 * u] = re;
+    spec[2 * u + 1] = im;
+}
+
+// signal[n] = sum over the sample's entries of a_e S(pair_e) (eq. 4.19).
+__global__ void kt_combine_kernel(const KtEntry* __restrict__ entries, const int64_t* __restrict__ offsets,
+                                  int64_t n_samples, const double* __restrict__ spec, double* __restrict__ signal) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_samples) return;
+    double re = 0.0, im = 0.0;
+    for (int64_t e = offsets[n]; e < offsets[n + 1]; ++e) {
+        const KtEntry q = entries[e];
+        const double sr = spec[2 * q.pair], si = spec[2 * q.pair + 1];
+        re += q.a_re * sr - q.a_im * si;
+        im += q.a_re * si + q.a_im * sr;
+    }
+    signal[2 * n] = re;
+    signal[2 * n + 1] = im;
+}
+
+hipError_t launch_kt(const KtItem* items, int64_t n_items, const double* pair_k, const KtPairSum* pair_sums,
+                     int64_t n_pairs, const KtEntry* entries, const int64_t* offsets, int64_t n_samples,
+                     const float* x, const float* y, const float* z, const float* m0, void* partial, double* spec,
+                     double* signal, int precision, hipStream_t st) {
+    if (n_samples <= 0) return hipSuccess;
+    if (n_items > 0) {
+        if (n_items > 0x7fffffffll) return hipErrorInvalidValue;
+        if (precision == 64)
+            hipLaunchKernelGGL(kt_spectrum_kernel<double>, dim3((unsigned)n_items), dim3(kBlock), 0, st, items,
+                               pair_k, x, y, z, m0, reinterpret_cast<double*>(partial));
+        else
+            hipLaunchKernelGGL(kt_spectrum_kernel<float>, dim3((unsigned)n_items), dim3(kBlock), 0, st, items,
+                               pair_k, x, y, z, m0, reinterpret_cast<float*>(partial));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const unsigned g = (unsigned)((n_pairs + 255) / 256);
+        if (precision == 64)
+            hipLaunchKernelGGL(kt_pair_sum_kernel<double>, dim3(g), dim3(256), 0, st, pair_sums, n_pairs,
+                               reinterpret_cast<const double*>(partial), spec);
+        else
+            hipLaunchKernelGGL(kt_pair_sum_kernel<float>, dim3(g), dim3(256), 0, st, pair_sums, n_pairs,
+                               reinterpret_cast<const float*>(partial), spec);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kt_combine_kernel, dim3((unsigned)((n_samples + 255) / 256)), dim3(256), 0, st, entries,
+                       offsets, n_samples, spec, signal);
+    return hipGetLastError();
+}
+
 hipError_t noalloc_scratch(int device, void** ptr) {
     static std::mutex mu;
     static void* addr[kMaxDevices] = {};

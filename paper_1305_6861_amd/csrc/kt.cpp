@@ -25,102 +25,86 @@
 
 #include "../../include/parspin.h"
 #include "compile.h"
+#include "kt.h"
 #include "ps_runtime.h"
 
 namespace ps {
-namespace {
 
-using cplx = std::complex<double>;
-
-// lattice order packed into 64 bits: 21 signed bits per axis
-constexpr int64_t kBits = 21;
-constexpr int64_t kLim = (int64_t(1) << (kBits - 1)) - 1;
-
-int64_t pack(int64_t a, int64_t b, int64_t c) {
-    const int64_t m = (int64_t(1) << kBits) - 1;
-    return ((a & m) << (2 * kBits)) | ((b & m) << kBits) | (c & m);
+int64_t kt_pack(int64_t a, int64_t b, int64_t c) {
+    const int64_t m = (int64_t(1) << kKtBits) - 1;
+    return ((a & m) << (2 * kKtBits)) | ((b & m) << kKtBits) | (c & m);
 }
-int64_t unpack_axis(int64_t key, int d) {
-    const int64_t m = (int64_t(1) << kBits) - 1;
-    int64_t v = (key >> (kBits * (2 - d))) & m;
-    if (v & (int64_t(1) << (kBits - 1))) v -= (int64_t(1) << kBits);
+
+int64_t kt_axis(int64_t key, int d) {
+    const int64_t m = (int64_t(1) << kKtBits) - 1;
+    int64_t v = (key >> (kKtBits * (2 - d))) & m;
+    if (v & (int64_t(1) << (kKtBits - 1))) v -= (int64_t(1) << kKtBits);
     return v;
 }
-int64_t negate(int64_t key) { return pack(-unpack_axis(key, 0), -unpack_axis(key, 1), -unpack_axis(key, 2)); }
 
-struct Tissue {
-    double r1, r2;           // 1/T1, 1/T2
-};
+int64_t kt_negate(int64_t key) { return kt_pack(-kt_axis(key, 0), -kt_axis(key, 1), -kt_axis(key, 2)); }
 
-class Populations {
-public:
-    std::unordered_map<int64_t, cplx> F, Z;
-    size_t peak = 0;
+KtPopulations::KtPopulations() { Z[kt_pack(0, 0, 0)] = 1.0; }
 
-    Populations() { Z[pack(0, 0, 0)] = 1.0; }
-
-    void pulse(double alpha, double phi) {
-        if (alpha == 0.0) return;
-        double r[9];
-        rf_matrix(alpha, phi, r);
-        // T = C R C^-1 with C mapping (Mx, My, Mz) to (Mx + j My, Mx - j My, Mz);
-        // rows 0 and 2 are needed: F'(k) and Z'(k) from (F(k), conj F(-k), Z(k))
-        const cplx j(0.0, 1.0);
-        const cplx C[3][3] = {{1.0, j, 0.0}, {1.0, -j, 0.0}, {0.0, 0.0, 1.0}};
-        const cplx Ci[3][3] = {{0.5, 0.5, 0.0}, {-0.5 * j, 0.5 * j, 0.0}, {0.0, 0.0, 1.0}};
-        cplx CR[3][3], T[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                CR[a][b] = 0.0;
-                for (int c = 0; c < 3; ++c) CR[a][b] += C[a][c] * r[3 * c + b];
-            }
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                T[a][b] = 0.0;
-                for (int c = 0; c < 3; ++c) T[a][b] += CR[a][c] * Ci[c][b];
-            }
-        std::unordered_set<int64_t> keys;
-        keys.reserve(2 * F.size() + Z.size());
-        for (auto& kv : F) { keys.insert(kv.first); keys.insert(negate(kv.first)); }
-        for (auto& kv : Z) keys.insert(kv.first);
-        std::unordered_map<int64_t, cplx> nF, nZ;
-        nF.reserve(keys.size());
-        nZ.reserve(keys.size());
-        for (int64_t k : keys) {
-            auto fi = F.find(k), mi = F.find(negate(k));
-            auto zi = Z.find(k);
-            const cplx u = fi != F.end() ? fi->second : 0.0;
-            const cplx v = mi != F.end() ? std::conj(mi->second) : 0.0;
-            const cplx w = zi != Z.end() ? zi->second : 0.0;
-            const cplx fu = T[0][0] * u + T[0][1] * v + T[0][2] * w;
-            const cplx zw = T[2][0] * u + T[2][1] * v + T[2][2] * w;
-            if (fu != 0.0) nF[k] = fu;
-            if (zw != 0.0) nZ[k] = zw;
+void KtPopulations::pulse(double alpha, double phi) {
+    if (alpha == 0.0) return;
+    double r[9];
+    rf_matrix(alpha, phi, r);
+    // T = C R C^-1 with C mapping (Mx, My, Mz) to (Mx + j My, Mx - j My, Mz);
+    // rows 0 and 2 are needed: F'(k) and Z'(k) from (F(k), conj F(-k), Z(k))
+    const cplx j(0.0, 1.0);
+    const cplx C[3][3] = {{1.0, j, 0.0}, {1.0, -j, 0.0}, {0.0, 0.0, 1.0}};
+    const cplx Ci[3][3] = {{0.5, 0.5, 0.0}, {-0.5 * j, 0.5 * j, 0.0}, {0.0, 0.0, 1.0}};
+    cplx CR[3][3], T[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            CR[a][b] = 0.0;
+            for (int c = 0; c < 3; ++c) CR[a][b] += C[a][c] * r[3 * c + b];
         }
-        F.swap(nF);
-        Z.swap(nZ);
-        peak = std::max(peak, F.size());
-    }
-
-    void interval(double tau, const int64_t q[3], const Tissue& t) {
-        const double e1 = std::exp(-tau * t.r1), e2 = std::exp(-tau * t.r2);
-        std::unordered_map<int64_t, cplx> nF;
-        nF.reserve(F.size());
-        for (auto& kv : F) {
-            const int64_t k = kv.first;
-            nF[pack(unpack_axis(k, 0) + q[0], unpack_axis(k, 1) + q[1], unpack_axis(k, 2) + q[2])] = kv.second * e2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            T[a][b] = 0.0;
+            for (int c = 0; c < 3; ++c) T[a][b] += CR[a][c] * Ci[c][b];
         }
-        F.swap(nF);
-        for (auto& kv : Z) kv.second *= e1;
-        Z[pack(0, 0, 0)] += 1.0 - e1;
+    std::unordered_set<int64_t> keys;
+    keys.reserve(2 * F.size() + Z.size());
+    for (auto& kv : F) { keys.insert(kv.first); keys.insert(kt_negate(kv.first)); }
+    for (auto& kv : Z) keys.insert(kv.first);
+    std::unordered_map<int64_t, cplx> nF, nZ;
+    nF.reserve(keys.size());
+    nZ.reserve(keys.size());
+    for (int64_t k : keys) {
+        auto fi = F.find(k), mi = F.find(kt_negate(k));
+        auto zi = Z.find(k);
+        const cplx u = fi != F.end() ? fi->second : 0.0;
+        const cplx v = mi != F.end() ? std::conj(mi->second) : 0.0;
+        const cplx w = zi != Z.end() ? zi->second : 0.0;
+        const cplx fu = T[0][0] * u + T[0][1] * v + T[0][2] * w;
+        const cplx zw = T[2][0] * u + T[2][1] * v + T[2][2] * w;
+        if (fu != 0.0) nF[k] = fu;
+        if (zw != 0.0) nZ[k] = zw;
     }
+    F.swap(nF);
+    Z.swap(nZ);
+    peak = std::max(peak, F.size());
+}
 
-    void spoil() { F.clear(); }
-};
+void KtPopulations::interval(double tau, const int64_t q[3], const KtTissue& t) {
+    const double e1 = std::exp(-tau * t.r1), e2 = std::exp(-tau * t.r2);
+    // transverse decay and the tissue's uniform off-resonance turn, e^(-j dw tau)
+    const cplx turn = t.dw != 0.0 ? e2 * cplx(std::cos(t.dw * tau), -std::sin(t.dw * tau)) : cplx(e2, 0.0);
+    std::unordered_map<int64_t, cplx> nF;
+    nF.reserve(F.size());
+    for (auto& kv : F) {
+        const int64_t k = kv.first;
+        nF[kt_pack(kt_axis(k, 0) + q[0], kt_axis(k, 1) + q[1], kt_axis(k, 2) + q[2])] = kv.second * turn;
+    }
+    F.swap(nF);
+    for (auto& kv : Z) kv.second *= e1;
+    Z[kt_pack(0, 0, 0)] += 1.0 - e1;
+}
 
-int64_t iabs(int64_t v) { return v < 0 ? -v : v; }
-
-bool lattice(const double m[3], const double dk[3], int64_t q[3]) {
+bool kt_lattice(const double m[3], const double dk[3], int64_t q[3]) {
     for (int d = 0; d < 3; ++d) {
         if (dk[d] == 0.0) {
             if (std::fabs(m[d]) > 1e-9) return false;
@@ -129,13 +113,16 @@ bool lattice(const double m[3], const double dk[3], int64_t q[3]) {
         }
         const double r = m[d] / dk[d];
         const double n = std::nearbyint(r);
-        if (std::fabs(r - n) > 1e-6 * std::max(1.0, std::fabs(r)) || std::fabs(n) > (double)kLim / 2) return false;
+        if (std::fabs(r - n) > 1e-6 * std::max(1.0, std::fabs(r)) || std::fabs(n) > (double)kKtLim / 2) return false;
         q[d] = (int64_t)n;
     }
     return true;
 }
 
+namespace {
+int64_t iabs(int64_t v) { return v < 0 ? -v : v; }
 }  // namespace
+
 }  // namespace ps
 
 using namespace ps;
@@ -163,8 +150,8 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
         ps_status st = compile_sequence(seq, &p, &err);
         if (st != PS_OK) return fail(st, err);
     }
-    const Tissue tis{1.0 / t1, 1.0 / t2};
-    Populations pop;
+    const KtTissue tis{1.0 / t1, 1.0 / t2, 0.0};
+    KtPopulations pop;
     int64_t kmax[3] = {0, 0, 0};
     constexpr double kPopTol = 1e-12;      // rounding left by cancelling terms
     constexpr size_t kCap = size_t(1) << 22;
@@ -173,7 +160,7 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
         for (auto* src : {&pop.F, &pop.Z})
             for (auto& kv : *src)
                 if (std::abs(kv.second) > kPopTol)
-                    for (int d = 0; d < 3; ++d) kmax[d] = std::max(kmax[d], iabs(unpack_axis(kv.first, d)));
+                    for (int d = 0; d < 3; ++d) kmax[d] = std::max(kmax[d], iabs(kt_axis(kv.first, d)));
     };
     auto track_sample = [&]() {
         if (pop.F.empty()) return;
@@ -184,7 +171,7 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
         v.reserve(pop.F.size());
         for (int d = 0; d < 3; ++d) {
             v.clear();
-            for (auto& kv : pop.F) v.emplace_back(iabs(unpack_axis(kv.first, d)), std::abs(kv.second));
+            for (auto& kv : pop.F) v.emplace_back(iabs(kt_axis(kv.first, d)), std::abs(kv.second));
             std::sort(v.begin(), v.end(), [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) {
                 return a.first != b.first ? a.first > b.first : a.second > b.second;
             });
@@ -205,7 +192,7 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
         if (ev.rf_shape >= 0) {
             const ps_rf_shape& sh = seq->shapes[ev.rf_shape];
             int64_t q[3];
-            if (!lattice(sh.m_sub, dk, q))
+            if (!kt_lattice(sh.m_sub, dk, q))
                 return fail(PS_E_INVALID_ARG, "shape " + std::to_string(ev.rf_shape) +
                                                   ": sub-step moment is not a multiple of dk");
             for (int32_t s = 0; s < sh.n_sub; ++s) {
@@ -221,7 +208,7 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
         const int64_t n = (int64_t)ev.n_adc, K = n > 0 ? n : 1;
         const double mu[3] = {ev.m[0] / (double)K, ev.m[1] / (double)K, ev.m[2] / (double)K};
         int64_t q[3];
-        if (!lattice(mu, dk, q))
+        if (!kt_lattice(mu, dk, q))
             return fail(PS_E_INVALID_ARG, "event " + std::to_string(e) + ": (per-sample) moment is not a multiple of dk");
         for (int64_t s = 0; s < K; ++s) {
             pop.interval(ev.dt / (double)K, q, tis);

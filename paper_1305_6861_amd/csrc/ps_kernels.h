@@ -115,6 +115,36 @@ hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int
                                 std::vector<KernelNode>* out);
 int64_t row_group_size();
 
+// K-t simulation (kt_engine.cpp): work items of the spectrum kernel, the
+// tile-sum description of every (tissue, lattice point) pair, and the
+// per-sample entries a_e (population times voxel weight) of eq. 4.19.
+constexpr int kKtPairs = 32;               // pairs per work item (64 reduced values)
+constexpr int kKtSpl = 4;                  // spins per lane
+constexpr int64_t kKtTile = 256 * kKtSpl;  // spins per work item
+struct alignas(16) KtItem {
+    int64_t spin_begin;      // first spin of the tile
+    int64_t pair_begin;      // first pair of the block (pair_k rows)
+    int32_t n_spins;         // spins of the tile (<= kKtTile)
+    int32_t n_pairs;         // pairs of the block (<= kKtPairs)
+};
+struct alignas(16) KtPairSum {
+    int64_t item0;           // work item of the pair's block and the tissue's first tile
+    int32_t n_tiles;         // tiles of the tissue (items item0 .. item0 + n_tiles - 1)
+    int32_t slot;            // position of the pair in its block
+};
+struct alignas(16) KtEntry {
+    double a_re, a_im;       // population times voxel weight
+    int64_t pair;
+    int64_t pad;
+};
+// Spectrum over (tissue, pair block, tile) items into partial (n_items x 64
+// reals of the precision), tile sums per pair into spec (2 n_pairs doubles),
+// then signal (2 n_samples doubles) from the entries.
+hipError_t launch_kt(const KtItem* items, int64_t n_items, const double* pair_k, const KtPairSum* pair_sums,
+                     int64_t n_pairs, const KtEntry* entries, const int64_t* offsets, int64_t n_samples,
+                     const float* x, const float* y, const float* z, const float* m0, void* partial, double* spec,
+                     double* signal, int precision, hipStream_t st);
+
 // Bytes of the static device array behind the allocation-free entry point.
 constexpr int64_t kNoAllocScratchBytes = int64_t(256) << 20;
 constexpr int kMaxDevices = 64;

@@ -235,3 +235,55 @@ def grid3d_legendre(n_side: int, fov: float, seed: int, c_tesla: float, radius: 
     obj = SpinObject(x=xx, y=yy, z=zz, m0=rho, t1=t1, t2=t2, dw=dw)
     obj.meta.update(kind="grid3d_legendre", n=n_side, fov=fov, seed=seed, c_tesla=c_tesla, radius=radius)
     return obj
+
+
+# Tissue classes of the K-t phantom: (rho, T1 s, T2 s, off-resonance Hz).
+# Illustrative values of the usual brain-like ordering; uniform per class.
+KT_TISSUES = (
+    (0.9, 0.30, 0.080, -50.0),   # outer ring ("fat-like", shifted)
+    (0.7, 0.80, 0.070, 0.0),     # "white matter"
+    (0.8, 1.30, 0.100, 10.0),    # "grey matter"
+    (1.0, 4.00, 2.000, 0.0),     # "fluid"
+)
+
+
+def kt_phantom_2d(n: int, fov: float = 0.25, iso_per_axis: int = 1):
+    """2-D n x n voxel grid at z = 0 made of the KT_TISSUES classes in nested
+    discs (radii 0.45, 0.36, 0.24, 0.10 of the FOV; voxels outside hold no
+    spins), ordered tissue by tissue.  With iso_per_axis = m every voxel
+    holds m x m isochromats at the centres of its m x m sub-cells, each with
+    m0 = rho / m^2 (a sampling of the voxel's uniform density).
+
+    Returns (SpinObject with each spin's tissue T1, T2 and dw,
+    tissue_begin offsets, t1, t2, dw per tissue (dw in rad/s; the float32
+    values the spins hold, widened), voxel size).
+    """
+    d = fov / n
+    c = grid_positions(n, fov)
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    r = np.hypot(xx, yy).reshape(-1) / fov
+    radii = (0.45, 0.36, 0.24, 0.10)
+    cls = np.full(r.shape, -1)
+    for t, rad in enumerate(radii):
+        cls[r <= rad] = t
+    m = iso_per_axis
+    sub = (np.arange(m) + 0.5) * (d / m) - d / 2
+    sy, sx = np.meshgrid(sub, sub, indexing="ij")
+    xs, ys, m0, t1, t2, dw, begin = [], [], [], [], [], [], [0]
+    for t, (rho, T1, T2, f) in enumerate(KT_TISSUES):
+        sel = np.nonzero(cls == t)[0]
+        px = (xx.reshape(-1)[sel][:, None] + sx.reshape(-1)[None, :]).reshape(-1)
+        py = (yy.reshape(-1)[sel][:, None] + sy.reshape(-1)[None, :]).reshape(-1)
+        xs.append(px); ys.append(py)
+        m0.append(np.full(px.shape, rho / (m * m)))
+        t1.append(np.full(px.shape, T1)); t2.append(np.full(px.shape, T2))
+        dw.append(np.full(px.shape, 2 * np.pi * f))
+        begin.append(begin[-1] + px.size)
+    x = np.concatenate(xs); y = np.concatenate(ys)
+    obj = SpinObject(x=x, y=y, z=np.zeros_like(x), m0=np.concatenate(m0), t1=np.concatenate(t1),
+                     t2=np.concatenate(t2), dw=np.concatenate(dw))
+    obj.meta.update(kind="kt_phantom_2d", n=n, fov=fov, iso_per_axis=m)
+    # per-tissue values as the spins store them (float32), widened exactly
+    tis = np.array(KT_TISSUES, dtype=np.float64)
+    w32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    return (obj, np.array(begin, dtype=np.int64), w32(tis[:, 1]), w32(tis[:, 2]), w32(2 * np.pi * tis[:, 3]), d)
