@@ -435,6 +435,26 @@ ps_status ps_request_info(ps_ctx *ctx, uint64_t ticket, ps_request_info_t *out);
  * Values not known yet (a request still queued or running) are -1; any
  * output pointer may be NULL.  PS_E_INVALID_ARG for an unknown ticket. */
 ps_status ps_stats(ps_ctx *ctx, uint64_t ticket, double *t_queue, double *t_kernel, double *t_e2e);
+/* ---- scheduler test support -----------------------------------------------
+ * A context whose served loop (ps_submit and the calls below) runs without a
+ * device, for testing admission, continuous batching, cancellation, failure
+ * handling and the timing bookkeeping on a CPU.  It computes no
+ * magnetisation: every served iteration "runs" each member's time slice by
+ * writing into the request's signal, which must be HOST memory here, the
+ * pattern (re, im) = (n_spins + sample index, slice index) for every sample
+ * of the slice (zeros for an object without spins), and "takes"
+ * iteration_seconds of stand-in device time; the object arrays are never
+ * read.  The iteration numbered fail_iteration (0-based, -1: none) reports
+ * a device error: the requests with a slice in it fail with PS_E_DEVICE,
+ * the others go on.  Only ps_submit, ps_poll, ps_wait, ps_cancel,
+ * ps_request_info, ps_stats, ps_release, ps_server_stats and ps_destroy
+ * accept such a context; every other call returns PS_E_INVALID_ARG. */
+typedef struct ps_test_backend {
+    double  iteration_seconds;   /* >= 0                                               */
+    int64_t fail_iteration;      /* -1 or the iteration that fails                     */
+} ps_test_backend;
+ps_status ps_create_scheduler_test(ps_ctx **out, const ps_config *cfg, const ps_test_backend *backend);
+
 /* Forget a finished request's record (PS_E_NOT_READY while in flight). */
 ps_status ps_release(ps_ctx *ctx, uint64_t ticket);
 /* Scheduler counters (all zero before the first ps_submit). */

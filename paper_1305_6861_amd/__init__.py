@@ -28,7 +28,7 @@ from ._binding import PsError, PS_EV_SPOIL, PS_EV_SNAPSHOT, PS_EV_TRAJECTORY
 
 FIELDS = ("x", "y", "z", "m0", "t1", "t2", "dw")
 
-__all__ = ["Context", "Plan", "Ticket", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence",
+__all__ = ["Context", "Plan", "Ticket", "SchedulerTest", "PsError", "PS_EV_SPOIL", "PS_EV_SNAPSHOT", "count", "pack_sequence",
            "to_device", "kt_extent", "FIELDS"]
 
 
@@ -493,6 +493,45 @@ class Plan:
         self.close()
 
 
+class SchedulerTest(Context):
+    """A context whose served loop runs with no device (ps_create_scheduler_test):
+    iterations write the stand-in pattern (re, im) = (n_spins + sample index,
+    slice index) into host signal arrays and take iteration_seconds; the
+    iteration numbered fail_iteration reports a device error.  For testing
+    admission, batching, cancellation and failure handling on a CPU."""
+
+    def __init__(self, iteration_seconds: float = 0.0, fail_iteration: int = -1, max_footprint_bytes: int = 0,
+                 max_slice_steps: int = 0, precision: int = 32):
+        cfg = _b.ps_config()
+        _b.check(_b.lib.ps_config_default(ctypes.byref(cfg)))
+        cfg.precision = precision
+        if max_footprint_bytes:
+            cfg.max_footprint_bytes = max_footprint_bytes
+        if max_slice_steps:
+            cfg.max_slice_steps = max_slice_steps
+        tb = _b.ps_test_backend(float(iteration_seconds), int(fail_iteration))
+        h = ctypes.c_void_p()
+        _b.check(_b.lib.ps_create_scheduler_test(ctypes.byref(h), ctypes.byref(cfg), ctypes.byref(tb)))
+        self._h = h
+        self.device = 0
+        self.precision = precision
+
+    def submit(self, obj, seq):
+        """Queue a request; its object arrays are host arrays (never read) and
+        its signal a host float64 array owned by the ticket."""
+        arrs = {f: np.ascontiguousarray(obj[f] if isinstance(obj, dict) else getattr(obj, f), np.float32)
+                for f in FIELDS}
+        n = int(arrs["x"].shape[0])
+        ps = pack_sequence(seq)
+        ns, _ = ps.count()
+        out = np.full(2 * max(ns, 1), np.nan)
+        o = _b.ps_object(n, *[arrs[f].ctypes.data if n else 0 for f in FIELDS])
+        t = ctypes.c_uint64()
+        _b.check(_b.lib.ps_submit(self._h, ctypes.byref(o), ctypes.byref(ps.struct),
+                                  ctypes.c_void_p(out.ctypes.data if ns else 0), ns, ctypes.byref(t)))
+        return HostTicket(self, int(t.value), out[:2 * ns], (arrs, ps))
+
+
 def _receive(coils, n_spins: int, device: int):
     """(kept tensors, ps_receive or None) for a pair (s_x, s_y)."""
     import torch
@@ -546,3 +585,11 @@ class Ticket:
 
     def release(self):
         _b.check(_b.lib.ps_release(self.ctx._h, self.ticket))
+
+
+class HostTicket(Ticket):
+    """Ticket of a scheduler-test request: its signal is a host array."""
+
+    def wait(self, timeout_s: float = -1.0):
+        _b.check(_b.lib.ps_wait(self.ctx._h, self.ticket, float(timeout_s)))
+        return self._out

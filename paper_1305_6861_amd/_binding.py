@@ -106,6 +106,10 @@ class ps_tune_result(ctypes.Structure):
 assert ctypes.sizeof(ps_tune_result) == 232
 
 
+class ps_test_backend(ctypes.Structure):
+    _fields_ = [("iteration_seconds", ctypes.c_double), ("fail_iteration", ctypes.c_int64)]
+
+
 class ps_kt_object(ctypes.Structure):
     _fields_ = [("n_tissues", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t1", ctypes.c_void_p),
                 ("t2", ctypes.c_void_p), ("dw", ctypes.c_void_p), ("tissue_begin", ctypes.c_void_p),
@@ -170,6 +174,8 @@ SIGNATURES = {
     "ps_kt_simulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_kt_object), ctypes.POINTER(ps_sequence),
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p]),
+    "ps_create_scheduler_test": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ps_config),
+                                                ctypes.POINTER(ps_test_backend)]),
     "ps_simulate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "ps_simulate_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),

@@ -460,9 +460,38 @@ ps_status ps_create(ps_ctx** out, const ps_config* cfg_in) {
     return PS_OK;
 }
 
+ps_status ps_create_scheduler_test(ps_ctx** out, const ps_config* cfg_in, const ps_test_backend* backend) {
+    clear_error();
+    if (!out || !backend) return fail(PS_E_INVALID_ARG, "out or backend is NULL");
+    *out = nullptr;
+    if (!(backend->iteration_seconds >= 0) || !std::isfinite(backend->iteration_seconds) ||
+        backend->fail_iteration < -1)
+        return fail(PS_E_INVALID_ARG, "iteration_seconds must be >= 0 and fail_iteration >= -1");
+    ps_config cfg;
+    if (cfg_in) cfg = *cfg_in; else ps_config_default(&cfg);
+    if (cfg.precision != 32 && cfg.precision != 64) return fail(PS_E_INVALID_ARG, "precision must be 32 or 64");
+    if (cfg.max_partial_bytes <= 0) cfg.max_partial_bytes = 2ll << 30;
+    if (cfg.max_footprint_bytes <= 0) cfg.max_footprint_bytes = 64ll << 30;
+    if (cfg.max_slice_steps < 0) return fail(PS_E_INVALID_ARG, "max_slice_steps < 0");
+    if (cfg.max_slice_steps == 0) cfg.max_slice_steps = 65536;
+    Ctx* ctx = new (std::nothrow) Ctx();
+    if (!ctx) return fail(PS_E_NO_MEMORY, "context allocation");
+    ctx->cfg = cfg;
+    ctx->n_cu = 256;
+    ctx->scheduler_test = true;
+    ctx->test_backend = *backend;
+    *out = reinterpret_cast<ps_ctx*>(ctx);
+    return PS_OK;
+}
+
 void ps_destroy(ps_ctx* handle) {
     if (!handle) return;
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) {
+        destroy_runtime(ctx);
+        delete ctx;
+        return;
+    }
     {
         DeviceGuard g(ctx->cfg.device);
         destroy_runtime(ctx);
@@ -501,6 +530,7 @@ ps_status ps_simulate(ps_ctx* handle, const ps_object* obj, const ps_sequence* s
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     const ps_status tst = autotune_if_new(ctx, obj, seq, nullptr, reinterpret_cast<hipStream_t>(stream));
@@ -515,6 +545,7 @@ ps_status ps_simulate_noalloc(ps_ctx* handle, const ps_object* obj, const ps_seq
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
@@ -598,6 +629,7 @@ ps_status ps_simulate_ex(ps_ctx* handle, const ps_object* obj, const ps_sequence
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     if (n_snapshots < 0) return fail(PS_E_INVALID_ARG, "n_snapshots < 0");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     const ps_status tst = autotune_if_new(ctx, obj, seq, rx, reinterpret_cast<hipStream_t>(stream));
@@ -611,6 +643,7 @@ ps_status ps_simulate_rx(ps_ctx* handle, const ps_object* obj, const ps_sequence
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     const ps_status tst = autotune_if_new(ctx, obj, seq, rx, reinterpret_cast<hipStream_t>(stream));
@@ -634,6 +667,7 @@ ps_status ps_valu_peak(ps_ctx* handle, int32_t precision, double* tflops) {
     if (!handle || !tflops) return fail(PS_E_INVALID_ARG, "ctx or tflops is NULL");
     if (precision != 32 && precision != 64) return fail(PS_E_INVALID_ARG, "precision must be 32 or 64");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     constexpr int64_t kBlocks = 8192;

@@ -366,6 +366,7 @@ extern "C" ps_status ps_simulate_batch(ps_ctx* handle, int32_t n_requests, const
     if (n_requests == 0) return PS_OK;
     if (!objs || !seqs || !signals || !n_samples) return fail(PS_E_INVALID_ARG, "NULL request array");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);

@@ -46,8 +46,26 @@ int64_t kt_negate(int64_t key) { return kt_pack(-kt_axis(key, 0), -kt_axis(key, 
 
 KtPopulations::KtPopulations() { Z[kt_pack(0, 0, 0)] = 1.0; }
 
+void KtPopulations::settle() {
+    if (shift_[0] == 0 && shift_[1] == 0 && shift_[2] == 0 && scale_ == cplx(1.0, 0.0)) return;
+    std::unordered_map<int64_t, cplx> nF;
+    nF.reserve(F_.size());
+    each_F([&](int64_t k, cplx f) { nF[k] = f; });
+    F_.swap(nF);
+    shift_[0] = shift_[1] = shift_[2] = 0;
+    scale_ = 1.0;
+}
+
+void KtPopulations::spoil() {
+    F_.clear();
+    shift_[0] = shift_[1] = shift_[2] = 0;
+    scale_ = 1.0;
+}
+
 void KtPopulations::pulse(double alpha, double phi) {
     if (alpha == 0.0) return;
+    settle();
+    std::unordered_map<int64_t, cplx>& F = F_;
     double r[9];
     rf_matrix(alpha, phi, r);
     // T = C R C^-1 with C mapping (Mx, My, Mz) to (Mx + j My, Mx - j My, Mz);
@@ -86,20 +104,17 @@ void KtPopulations::pulse(double alpha, double phi) {
     }
     F.swap(nF);
     Z.swap(nZ);
-    peak = std::max(peak, F.size());
+    peak = std::max(peak, F_.size());
 }
 
 void KtPopulations::interval(double tau, const int64_t q[3], const KtTissue& t) {
     const double e1 = std::exp(-tau * t.r1), e2 = std::exp(-tau * t.r2);
     // transverse decay and the tissue's uniform off-resonance turn, e^(-j dw tau)
     const cplx turn = t.dw != 0.0 ? e2 * cplx(std::cos(t.dw * tau), -std::sin(t.dw * tau)) : cplx(e2, 0.0);
-    std::unordered_map<int64_t, cplx> nF;
-    nF.reserve(F.size());
-    for (auto& kv : F) {
-        const int64_t k = kv.first;
-        nF[kt_pack(kt_axis(k, 0) + q[0], kt_axis(k, 1) + q[1], kt_axis(k, 2) + q[2])] = kv.second * turn;
-    }
-    F.swap(nF);
+    for (int d = 0; d < 3; ++d) shift_[d] += q[d];
+    scale_ *= turn;
+    // keep the pending factor well inside the double range
+    if (std::abs(scale_) < 1e-150) settle();
     for (auto& kv : Z) kv.second *= e1;
     Z[kt_pack(0, 0, 0)] += 1.0 - e1;
 }
@@ -156,22 +171,27 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
     constexpr double kPopTol = 1e-12;      // rounding left by cancelling terms
     constexpr size_t kCap = size_t(1) << 22;
 
+    auto track_order = [&](int64_t k, cplx f) {
+        if (std::abs(f) > kPopTol)
+            for (int d = 0; d < 3; ++d) kmax[d] = std::max(kmax[d], iabs(kt_axis(k, d)));
+    };
     auto track_all = [&]() {
-        for (auto* src : {&pop.F, &pop.Z})
-            for (auto& kv : *src)
-                if (std::abs(kv.second) > kPopTol)
-                    for (int d = 0; d < 3; ++d) kmax[d] = std::max(kmax[d], iabs(kt_axis(kv.first, d)));
+        pop.each_F(track_order);
+        for (auto& kv : pop.Z) track_order(kv.first, kv.second);
     };
     auto track_sample = [&]() {
-        if (pop.F.empty()) return;
+        if (pop.n_transverse() == 0) return;
+        std::vector<std::pair<int64_t, cplx>> F;
+        F.reserve(pop.n_transverse());
+        pop.each_F([&](int64_t k, cplx f) { F.emplace_back(k, f); });
         double ref = 0.0;
-        for (auto& kv : pop.F) ref = std::max(ref, std::abs(kv.second));
+        for (auto& kv : F) ref = std::max(ref, std::abs(kv.second));
         const double budget = 0.5 * grey_step * ref;
         std::vector<std::pair<int64_t, double>> v;
-        v.reserve(pop.F.size());
+        v.reserve(F.size());
         for (int d = 0; d < 3; ++d) {
             v.clear();
-            for (auto& kv : pop.F) v.emplace_back(iabs(kt_axis(kv.first, d)), std::abs(kv.second));
+            for (auto& kv : F) v.emplace_back(iabs(kt_axis(kv.first, d)), std::abs(kv.second));
             std::sort(v.begin(), v.end(), [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) {
                 return a.first != b.first ? a.first > b.first : a.second > b.second;
             });
@@ -185,7 +205,7 @@ extern "C" ps_status ps_kt_extent(const ps_sequence* seq, const double dk_in[3],
         }
     };
     const bool pruned = grey_step > 0;
-    auto too_large = [&]() { return pop.F.size() > kCap || pop.Z.size() > kCap; };
+    auto too_large = [&]() { return pop.n_transverse() > kCap || pop.Z.size() > kCap; };
 
     for (int64_t e = 0; e < seq->n_events; ++e) {
         const ps_event& ev = seq->events[e];

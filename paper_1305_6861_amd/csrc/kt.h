@@ -36,15 +36,35 @@ struct KtTissue {
     double dw = 0.0;         // rad/s, uniform over the tissue
 };
 
+// A gradient or a decay changes every transverse population in the same way
+// (a shift of all orders by q, a factor e2 exp(-j dw tau)), so the store
+// keeps them pending -- F(order) = stored F(order - shift) x scale -- and
+// applies them only before a pulse mixes orders: stepping a readout sample
+// by sample costs no rehashing.
 class KtPopulations {
 public:
-    std::unordered_map<int64_t, cplx> F, Z;
+    std::unordered_map<int64_t, cplx> Z;
     size_t peak = 0;         // most transverse configurations at once
 
     KtPopulations();
     void pulse(double alpha, double phi);
     void interval(double tau, const int64_t q[3], const KtTissue& t);
-    void spoil() { F.clear(); }
+    void spoil();
+    size_t n_transverse() const { return F_.size(); }
+    // fn(packed order, population) for every transverse configuration
+    template <typename Fn>
+    void each_F(Fn&& fn) const {
+        for (const auto& kv : F_)
+            fn(kt_pack(kt_axis(kv.first, 0) + shift_[0], kt_axis(kv.first, 1) + shift_[1],
+                       kt_axis(kv.first, 2) + shift_[2]),
+               kv.second * scale_);
+    }
+
+private:
+    std::unordered_map<int64_t, cplx> F_;
+    int64_t shift_[3] = {0, 0, 0};
+    cplx scale_ = 1.0;
+    void settle();           // apply the pending shift and scale to the store
 };
 
 // The lattice vector q with m = q dk per axis (axes with dk = 0 carry no

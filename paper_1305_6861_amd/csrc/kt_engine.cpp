@@ -70,6 +70,7 @@ extern "C" ps_status ps_kt_simulate(ps_ctx* handle, const ps_kt_object* obj, con
     clear_error();
     if (!handle || !obj || !seq || !dk_in) return fail(PS_E_INVALID_ARG, "ctx, obj, seq or dk is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
@@ -120,6 +121,15 @@ extern "C" ps_status ps_kt_simulate(ps_ctx* handle, const ps_kt_object* obj, con
     std::vector<int32_t> pair_tissue;
     std::vector<int64_t> pair_key;
     std::vector<RawEntry> raw;
+    {   // at least one populated order per tissue and sample in most sequences
+        int32_t with_spins = 0;
+        for (int32_t c = 0; c < obj->n_tissues; ++c) with_spins += obj->tissue_begin[c + 1] > obj->tissue_begin[c];
+        const size_t guess = (size_t)std::min<int64_t>(n_samples * (int64_t)with_spins, int64_t(1) << 24);
+        pair_of.reserve(guess);
+        pair_tissue.reserve(guess);
+        pair_key.reserve(guess);
+        raw.reserve(guess);
+    }
     for (int32_t c = 0; c < obj->n_tissues; ++c) {
         if (obj->tissue_begin[c + 1] == obj->tissue_begin[c]) continue;   // no spins: no signal
         const KtTissue tis{1.0 / obj->t1[c], 1.0 / obj->t2[c], obj->dw[c]};
@@ -147,29 +157,29 @@ extern "C" ps_status ps_kt_simulate(ps_ctx* handle, const ps_kt_object* obj, con
                                                   ": (per-sample) moment is not a multiple of dk");
             for (int64_t s = 0; s < K; ++s) {
                 pop.interval(ev.dt / (double)K, q, tis);
-                if (pop.F.size() > kMaxConfigs || pop.Z.size() > kMaxConfigs)
+                if (pop.n_transverse() > kMaxConfigs || pop.Z.size() > kMaxConfigs)
                     return fail(PS_E_TOO_LARGE, "tissue " + std::to_string(c) + ": more than 2^22 configurations");
                 if (n == 0) continue;
-                for (auto& kv : pop.F) {
-                    if (std::abs(kv.second) <= kKtPopFloor) continue;
-                    const PairKey pk{c, kv.first};
+                pop.each_F([&](int64_t order, cplx f) {
+                    if (std::abs(f) <= kKtPopFloor) return;
+                    const PairKey pk{c, order};
                     auto it = pair_of.find(pk);
                     int64_t u;
                     if (it == pair_of.end()) {
                         u = (int64_t)pair_tissue.size();
                         pair_of.emplace(pk, u);
                         pair_tissue.push_back(c);
-                        pair_key.push_back(kv.first);
+                        pair_key.push_back(order);
                     } else {
                         u = it->second;
                     }
                     // voxel spectrum at the configuration's position
                     double w = 1.0;
-                    for (int d = 0; d < 3; ++d) w *= sinc_pi((double)kt_axis(kv.first, d) * dk[d] * vox[d]);
-                    raw.push_back(RawEntry{sample, u, w * kv.second.real(), w * kv.second.imag()});
-                    if ((int64_t)raw.size() > kMaxEntries)
-                        return fail(PS_E_TOO_LARGE, "more than 2^28 (sample, configuration) entries");
-                }
+                    for (int d = 0; d < 3; ++d) w *= sinc_pi((double)kt_axis(order, d) * dk[d] * vox[d]);
+                    raw.push_back(RawEntry{sample, u, w * f.real(), w * f.imag()});
+                });
+                if ((int64_t)raw.size() > kMaxEntries)
+                    return fail(PS_E_TOO_LARGE, "more than 2^28 (sample, configuration) entries");
                 ++sample;
             }
             if (ev.flags & PS_EV_SPOIL) pop.spoil();

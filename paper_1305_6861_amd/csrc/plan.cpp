@@ -49,6 +49,7 @@ ps_status ps_plan_create(ps_ctx* handle, const ps_object* obj, const ps_sequence
     if (!handle || !out) return fail(PS_E_INVALID_ARG, "ctx or out is NULL");
     *out = nullptr;
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     Plan* p = new Plan();

@@ -106,6 +106,10 @@ struct Ctx {
     HostBuf noalloc_staging;
     hipEvent_t noalloc_done = nullptr;    // the last upload from the staging has completed
     bool noalloc_pending = false;
+    // scheduler-test context (ps_create_scheduler_test): no device; the
+    // served loop runs against a stand-in that writes a fixed pattern
+    bool scheduler_test = false;
+    ps_test_backend test_backend{};
 };
 // Pinned staging a context sets aside for the allocation-free entry point's
 // table uploads (bounds the tables of a request it accepts).

@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdint>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -101,7 +102,14 @@ static int64_t slice_steps(const ReqPlan& p, size_t k) {
 // Device memory for admitted requests: freed blocks are kept and reused.
 struct Pool {
     std::multimap<size_t, void*> free_blocks;
+    bool stand_in = false;             // scheduler test: addresses that are never dereferenced
+    uintptr_t next_token = 0;
     ps_status get(size_t n, void** out) {
+        if (stand_in) {
+            next_token += (n + 4095) / 4096 * 4096 + 4096;
+            *out = reinterpret_cast<void*>(next_token);
+            return PS_OK;
+        }
         auto it = free_blocks.lower_bound(n);
         if (it != free_blocks.end() && it->first <= 2 * n) {
             *out = it->second;
@@ -114,7 +122,7 @@ struct Pool {
         *out = p;
         return PS_OK;
     }
-    void put(void* p, size_t n) { if (p) free_blocks.emplace(n, p); }
+    void put(void* p, size_t n) { if (p && !stand_in) free_blocks.emplace(n, p); }
     void release() {
         for (auto& kv : free_blocks) (void)hipFree(kv.second);
         free_blocks.clear();
@@ -144,6 +152,8 @@ struct IterSlot {
     bool busy = false;
     bool timed = false;                                // ev_start / ev_end recorded
     double work = 0.0;                                 // spin-steps of its slices
+    Clock::time_point stand_in_done;                   // scheduler test: completion instant
+    bool stand_in_fails = false;                       // scheduler test: injected device error
     std::vector<std::shared_ptr<Request>> members;     // requests with work in it
     std::map<std::vector<const void*>, RoundGraph> graphs;
     std::vector<unsigned char> img;                    // host image of its records
@@ -170,8 +180,13 @@ struct Server {
     // counters
     uint64_t iterations = 0;
 
+    bool stand_in = false;             // scheduler-test context (no device)
+    int64_t launched = 0;              // iterations launched so far
+
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void loop();
+    ps_status stand_in_launch(IterSlot& sl, std::vector<ReqPlan*>& plans, std::vector<size_t>& first,
+                              std::vector<double*>& zero_fill, std::vector<int64_t>& zero_n);
     void finish(const std::shared_ptr<Request>& r, int32_t state, ps_status st, const std::string& err);
     ps_status launch_iteration(IterSlot& sl, std::vector<ReqPlan*>& fresh, std::vector<ReqPlan*>& plans,
                                std::vector<size_t>& first, std::vector<double*>& zero_fill,
@@ -229,6 +244,31 @@ ps_status Server::launch_nodes(IterSlot& sl, std::vector<KernelNode>& nodes) {
     return PS_OK;
 }
 
+// Scheduler test: the iteration's slices write the stand-in pattern into the
+// requests' (host) signals right away; the iteration completes
+// iteration_seconds after its launch (after the previous one).
+ps_status Server::stand_in_launch(IterSlot& sl, std::vector<ReqPlan*>& plans, std::vector<size_t>& first,
+                                  std::vector<double*>& zero_fill, std::vector<int64_t>& zero_n) {
+    for (size_t i = 0; i < zero_fill.size(); ++i)
+        for (int64_t j = 0; j < zero_n[i]; ++j) zero_fill[i][j] = 0.0;
+    for (size_t i = 0; i < plans.size(); ++i) {
+        const ReqPlan& p = *plans[i];
+        const Slice& slc = p.prog.slices[first[i]];
+        for (int64_t n = slc.sample_begin; n < slc.sample_begin + slc.n_samples; ++n) {
+            p.signal[2 * n] = (double)p.obj.n_spins + (double)n;
+            p.signal[2 * n + 1] = (double)first[i];
+        }
+    }
+    const auto dur = std::chrono::duration_cast<Clock::duration>(
+        std::chrono::duration<double>(ctx->test_backend.iteration_seconds));
+    Clock::time_point start = Clock::now();
+    if (!inflight.empty()) start = std::max(start, slots[inflight.back()].stand_in_done);
+    sl.stand_in_done = start + dur;
+    sl.stand_in_fails = ctx->test_backend.fail_iteration == launched;
+    sl.timed = !plans.empty();
+    return PS_OK;
+}
+
 // Upload the fresh requests' tables and this iteration's records through the
 // slot's staging, then launch: zero fills of empty objects, the round's
 // graph, with the timing and completion events around them.
@@ -271,14 +311,21 @@ ps_status Server::launch_iteration(IterSlot& sl, std::vector<ReqPlan*>& fresh, s
 void Server::retire_oldest(bool block, ps_status* err) {
     if (inflight.empty()) return;
     IterSlot& sl = slots[inflight.front()];
-    hipError_t e = block ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
-    if (e == hipErrorNotReady) return;
     ps_status st = PS_OK;
-    if (e != hipSuccess) st = hip_fail(e, "server iteration");
     double iter_kernel_s = 0.0;
-    if (st == PS_OK && sl.timed) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, sl.ev_start, sl.ev_end) == hipSuccess) iter_kernel_s = 1e-3 * ms;
+    if (stand_in) {
+        if (!block && Clock::now() < sl.stand_in_done) return;
+        std::this_thread::sleep_until(sl.stand_in_done);
+        if (sl.stand_in_fails) st = fail(PS_E_DEVICE, "injected device error (scheduler test)");
+        else if (sl.timed) iter_kernel_s = ctx->test_backend.iteration_seconds;
+    } else {
+        hipError_t e = block ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
+        if (e == hipErrorNotReady) return;
+        if (e != hipSuccess) st = hip_fail(e, "server iteration");
+        if (st == PS_OK && sl.timed) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, sl.ev_start, sl.ev_end) == hipSuccess) iter_kernel_s = 1e-3 * ms;
+        }
     }
     const std::string msg = st == PS_OK ? "" : ps_last_error();
     {
@@ -304,7 +351,7 @@ void Server::retire_oldest(bool block, ps_status* err) {
 }
 
 void Server::loop() {
-    (void)hipSetDevice(ctx->cfg.device);
+    if (!stand_in) (void)hipSetDevice(ctx->cfg.device);
     for (;;) {
         // retire what the device has completed, without waiting
         for (size_t n = inflight.size(); n > 0; --n) retire_oldest(false, nullptr);
@@ -412,12 +459,14 @@ void Server::loop() {
             plans.push_back(&p);
             first.push_back(r->enqueued);
         }
-        ps_status st = launch_iteration(sl, fresh, plans, first, zero_fill, zero_n);
+        ps_status st = stand_in ? stand_in_launch(sl, plans, first, zero_fill, zero_n)
+                                : launch_iteration(sl, fresh, plans, first, zero_fill, zero_n);
+        ++launched;
         if (st != PS_OK) {
             // the stream may hold part of the iteration: let it drain, then
             // fail the requests that had work in it
             const std::string msg = ps_last_error();
-            (void)hipStreamSynchronize(stream);
+            if (!stand_in) (void)hipStreamSynchronize(stream);
             while (!inflight.empty()) retire_oldest(true, nullptr);
             std::lock_guard<std::mutex> lk(mu);
             for (auto& r : members) {
@@ -483,6 +532,13 @@ static ps_status ensure_server(Ctx* ctx) {
     if (!s) return fail(PS_E_NO_MEMORY, "server allocation");
     s->ctx = ctx;
     s->t0 = Clock::now();
+    if (ctx->scheduler_test) {
+        s->stand_in = true;
+        s->pool.stand_in = true;
+        ctx->server = s;
+        s->thr = std::thread([s] { s->loop(); });
+        return PS_OK;
+    }
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     for (IterSlot& sl : s->slots) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
@@ -524,7 +580,8 @@ ps_status ps_submit(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq
     ps_status st;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        DeviceGuard g(ctx->cfg.device);
+        std::unique_ptr<DeviceGuard> g;
+        if (!ctx->scheduler_test) g.reset(new DeviceGuard(ctx->cfg.device));
         if ((st = ensure_server(ctx)) != PS_OK) return st;
         const int64_t steps = ctx->cfg.max_slice_steps;
         if ((st = plan_request(ctx, obj, seq, n_samples, signal, steps, &r->plan)) != PS_OK) return st;

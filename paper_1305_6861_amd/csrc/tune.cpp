@@ -291,6 +291,7 @@ ps_status ps_tune(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq, 
     if (!handle || !obj || !seq) return fail(PS_E_INVALID_ARG, "ctx, obj or seq is NULL");
     if (flags & ~(uint32_t)PS_TUNE_FORCE) return fail(PS_E_INVALID_ARG, "unknown tune flags");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    if (ctx->scheduler_test) return fail(PS_E_INVALID_ARG, "a scheduler-test context runs no kernels");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->cfg.device);
     if (out) std::memset(out, 0, sizeof(*out));
