@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -98,7 +99,9 @@ struct Ctx {
     // kernel timing (PS_CFG_KERNEL_TIMING): event pairs around launches
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> step_marks, fin_marks;
-    Server* server = nullptr;
+    // set once by the first ps_submit (under mu) and read without mu by the
+    // served-request calls of other threads
+    std::atomic<Server*> server{nullptr};
     std::map<TuneKey, TuneEntry> tuned;   // autotuner table (guarded by mu)
     // allocation-free entry point: the device's static scratch array, and
     // pinned staging for its table uploads (both set up by ps_create)

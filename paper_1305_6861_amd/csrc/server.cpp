@@ -495,7 +495,7 @@ void Server::loop() {
 }
 
 void destroy_runtime(Ctx* ctx) {
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -523,11 +523,11 @@ void destroy_runtime(Ctx* ctx) {
     if (s->stream) (void)hipStreamDestroy(s->stream);
     s->pool.release();
     delete s;
-    ctx->server = nullptr;
+    ctx->server.store(nullptr, std::memory_order_release);
 }
 
 static ps_status ensure_server(Ctx* ctx) {
-    if (ctx->server) return PS_OK;
+    if (ctx->server.load(std::memory_order_acquire)) return PS_OK;
     Server* s = new (std::nothrow) Server();
     if (!s) return fail(PS_E_NO_MEMORY, "server allocation");
     s->ctx = ctx;
@@ -535,8 +535,8 @@ static ps_status ensure_server(Ctx* ctx) {
     if (ctx->scheduler_test) {
         s->stand_in = true;
         s->pool.stand_in = true;
-        ctx->server = s;
         s->thr = std::thread([s] { s->loop(); });
+        ctx->server.store(s, std::memory_order_release);
         return PS_OK;
     }
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -555,8 +555,8 @@ static ps_status ensure_server(Ctx* ctx) {
         delete s;
         return hip_fail(e, "server stream/event");
     }
-    ctx->server = s;
     s->thr = std::thread([s] { s->loop(); });
+    ctx->server.store(s, std::memory_order_release);
     return PS_OK;
 }
 
@@ -591,7 +591,7 @@ ps_status ps_submit(ps_ctx* handle, const ps_object* obj, const ps_sequence* seq
     if (r->footprint > (size_t)ctx->cfg.max_footprint_bytes)
         return fail(PS_E_TOO_LARGE, "request footprint " + std::to_string(r->footprint) +
                                         " bytes exceeds the cap of " + std::to_string(ctx->cfg.max_footprint_bytes));
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         r->ticket = s->next_ticket++;
@@ -608,7 +608,7 @@ ps_status ps_poll(ps_ctx* handle, uint64_t ticket, int32_t* done) {
     clear_error();
     if (!handle || !done) return fail(PS_E_INVALID_ARG, "ctx or done is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
     std::lock_guard<std::mutex> lk(s->mu);
     auto r = find(s, ticket);
@@ -621,7 +621,7 @@ ps_status ps_wait(ps_ctx* handle, uint64_t ticket, double timeout_s) {
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
     std::unique_lock<std::mutex> lk(s->mu);
     auto r = find(s, ticket);
@@ -640,7 +640,7 @@ ps_status ps_cancel(ps_ctx* handle, uint64_t ticket) {
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -656,7 +656,7 @@ ps_status ps_request_info(ps_ctx* handle, uint64_t ticket, ps_request_info_t* ou
     clear_error();
     if (!handle || !out) return fail(PS_E_INVALID_ARG, "ctx or out is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
     std::lock_guard<std::mutex> lk(s->mu);
     auto r = find(s, ticket);
@@ -679,7 +679,7 @@ ps_status ps_stats(ps_ctx* handle, uint64_t ticket, double* t_queue, double* t_k
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
     std::lock_guard<std::mutex> lk(s->mu);
     auto r = find(s, ticket);
@@ -695,7 +695,7 @@ ps_status ps_release(ps_ctx* handle, uint64_t ticket) {
     clear_error();
     if (!handle) return fail(PS_E_INVALID_ARG, "ctx is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return fail(PS_E_INVALID_ARG, "unknown ticket");
     std::lock_guard<std::mutex> lk(s->mu);
     auto r = find(s, ticket);
@@ -710,7 +710,7 @@ ps_status ps_server_stats(ps_ctx* handle, ps_server_stats_t* out) {
     if (!handle || !out) return fail(PS_E_INVALID_ARG, "ctx or out is NULL");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
     std::memset(out, 0, sizeof(*out));
-    Server* s = ctx->server;
+    Server* s = ctx->server.load(std::memory_order_acquire);
     if (!s) return PS_OK;
     std::lock_guard<std::mutex> lk(s->mu);
     out->iterations = (int64_t)s->iterations;

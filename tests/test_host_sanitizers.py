@@ -56,6 +56,63 @@ def test_oracle_pins_under_sanitizers(tmp_path):
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-3000:])
 
 
+@pytest.fixture(scope="module")
+def kernel_objects(tmp_path_factory):
+    """The library's kernel sources built by hipcc as for the library (linked
+    into the served-loop driver, never run there)."""
+    from paper_1305_6861_amd import build as lb
+    d = tmp_path_factory.mktemp("kernels")
+    objs, procs = [], []
+    for src in ("kernels.hip", "calib.hip"):
+        obj = str(d / (src + ".o"))
+        procs.append(subprocess.Popen([lb.HIPCC, *lb.COMMON, "-c", os.path.join(CSRC, src), "-o", obj],
+                                      stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
+        objs.append(obj)
+    for p in procs:
+        out, _ = p.communicate()
+        assert p.returncode == 0, out.decode(errors="replace")[-3000:]
+    return objs
+
+
+def _served_loop_binary(tmp_path, sanitize, objs):
+    """tests/host_sched_sanitize.cpp linked with the library's host sources
+    built by g++ with the given sanitizer flags."""
+    host = ["api.cpp", "server.cpp", "batch.cpp", "compile.cpp", "tune.cpp", "kt.cpp", "kt_engine.cpp", "plan.cpp"]
+    exe = str(tmp_path / "host_sched")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-w", *sanitize, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "host_sched_sanitize.cpp"),
+           *[os.path.join(CSRC, h) for h in host], *objs, "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib", "-lpthread", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return exe
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/lib/libamdhip64.so"), reason="needs the HIP runtime to link")
+@pytest.mark.parametrize("kind", ["thread", "address"])
+def test_served_loop_under_sanitizers(tmp_path, kind, kernel_objects):
+    """The served loop's locking and bookkeeping: four client threads submit,
+    poll, wait (with and without time-outs), cancel and release 120 requests
+    on a scheduler-test context while a fifth reads the server counters and
+    one iteration fails by design.  ThreadSanitizer: no data race; ASan and
+    UBSan: no memory error.  (A suppression covers the double-lock report
+    that gcc 11's ThreadSanitizer gives for a condition-variable wait with a
+    time-out: libstdc++ waits through pthread_cond_clockwait there, which
+    that ThreadSanitizer does not intercept, so it misses the unlock.)"""
+    flags = (["-fsanitize=thread"] if kind == "thread"
+             else ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"])
+    exe = _served_loop_binary(tmp_path, flags, kernel_objects)
+    supp = tmp_path / "tsan.supp"
+    supp.write_text("mutex:ps_wait\n")
+    env = dict(os.environ, TSAN_OPTIONS=f"halt_on_error=1 suppressions={supp}",
+               ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    for _ in range(3):
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+        print(r.stdout, r.stderr[-3000:])
+        assert r.returncode == 0, r.stderr[-4000:]
+        assert " 0 problems" in r.stdout
+
+
 def test_the_harness_catches_a_planted_overflow(tmp_path):
     """The same flags and preload catch a heap overflow in a library loaded
     through ctypes (so a clean run above means something)."""
