@@ -85,6 +85,14 @@ typedef struct ps_ctx ps_ctx;  /* opaque; one per device */
  * short iterations launched ahead (the results are the same; for
  * measurement). */
 #define PS_CFG_SERVE_DIRECT 16u
+/* ps_config.flags: FP32 readouts on the vector ALUs only.  By default, at one
+ * spin per lane, a readout of at least 64 samples whose per-sample step
+ * (moment and dwell) it shares with the neighbouring readout is summed over
+ * the spins on the matrix cores: the superposition of eq. 3.32 over a tile of
+ * 128 samples is a complex matrix product, (sample block) x (spin) times
+ * (spin) x (sample in block).  Both give the signal within FP32 rounding;
+ * this flag exists to measure and test the vector path. */
+#define PS_CFG_NO_MATRIX_READOUT 32u
 
 typedef struct ps_config {
     int32_t device;              /* HIP device ordinal                                 */

@@ -153,7 +153,7 @@ class Context:
     def __init__(self, device: int = 0, precision: int = 32, spins_per_lane: int = 0,
                  max_partial_bytes: int = 0, max_footprint_bytes: int = 0, kernel_timing: bool = False,
                  shape_cache: bool = True, readout_split: bool = True, max_slice_steps: int = 0,
-                 autotune: bool = False, serve_graphs: bool = True):
+                 autotune: bool = False, serve_graphs: bool = True, matrix_readout: bool = True):
         cfg = _b.ps_config()
         _b.check(_b.lib.ps_config_default(ctypes.byref(cfg)))
         cfg.device = device
@@ -163,7 +163,8 @@ class Context:
             (0 if shape_cache else _b.PS_CFG_NO_SHAPE_CACHE) | \
             (0 if readout_split else _b.PS_CFG_NO_READOUT_SPLIT) | \
             (_b.PS_CFG_AUTOTUNE if autotune else 0) | \
-            (0 if serve_graphs else _b.PS_CFG_SERVE_DIRECT)
+            (0 if serve_graphs else _b.PS_CFG_SERVE_DIRECT) | \
+            (0 if matrix_readout else _b.PS_CFG_NO_MATRIX_READOUT)
         if max_partial_bytes:
             cfg.max_partial_bytes = max_partial_bytes
         if max_footprint_bytes:

@@ -23,6 +23,7 @@ PS_CFG_NO_SHAPE_CACHE = 2
 PS_CFG_NO_READOUT_SPLIT = 4
 PS_CFG_AUTOTUNE = 8
 PS_CFG_SERVE_DIRECT = 16
+PS_CFG_NO_MATRIX_READOUT = 32
 PS_TUNE_FORCE = 1
 PS_TUNE_MAX_CANDIDATES = 12
 

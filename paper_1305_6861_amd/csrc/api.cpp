@@ -136,6 +136,7 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S,
     plan_slices(prog, max_samples);
     assign_shape_slots(prog, shape_cache_slots(ctx, S, *prog));
     if (ctx->cfg.precision != 64) narrow_rotations(&prog->ops);
+    if (ctx->cfg.precision != 64 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT)) mark_matrix_readouts(prog);
     return PS_OK;
 }
 
@@ -324,6 +325,8 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
     a.snaps = r.snaps;
     a.n_replicas = r.n_replicas;
     a.n_tiles = r.n_blocks;
+    for (int d = 0; d < 3; ++d) a.mx_mu[d] = prog.matrix_mu[d];
+    a.mx_tau = prog.matrix_tau;
     const Op* ops_dev = reinterpret_cast<const Op*>(b.ops);
     for (size_t i = 0; i < prog.slices.size(); ++i) {
         const Slice& sl = prog.slices[i];
@@ -341,7 +344,7 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
             if (!t0 || !t1 || !t2) return fail(PS_E_DEVICE, "timing event creation failed");
             hipEventRecord(t0, stream);
         }
-        if ((e = launch_step(a, precision, r.S, r.n_blocks, stream)) != hipSuccess)
+        if ((e = launch_step(a, precision, r.S, r.n_blocks, stream, prog.matrix_only)) != hipSuccess)
             return hip_fail(e, "step kernel launch");
         if (timing_ctx) hipEventRecord(t1, stream);
         for (int c = 0; c < r.n_out && sl.n_samples > 0; ++c) {

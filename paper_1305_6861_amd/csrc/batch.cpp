@@ -151,6 +151,8 @@ StepArgs ReqPlan::args_for_slice(size_t k, int n_replicas) const {
     a.snaps = nullptr;
     a.n_replicas = std::max(n_replicas, 1);
     a.n_tiles = n_blocks;
+    for (int d = 0; d < 3; ++d) a.mx_mu[d] = prog.matrix_mu[d];
+    a.mx_tau = prog.matrix_tau;
     return a;
 }
 
@@ -184,9 +186,12 @@ ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::
     rounds.assign(max_rounds, RoundImage());
     for (size_t k = 0; k < max_rounds; ++k) {
         RoundImage& R = rounds[k];
-        std::map<int, std::vector<size_t>> by_S;
+        // one launch per kernel: spins per lane, and at one spin per lane
+        // whether the request's readouts all take the matrix cores
+        std::map<std::pair<int, bool>, std::vector<size_t>> by_S;
         for (size_t i = 0; i < plans.size(); ++i)
-            if (k < n_slices_this_call[i] && plans[i]->obj.n_spins > 0) by_S[plans[i]->S].push_back(i);
+            if (k < n_slices_this_call[i] && plans[i]->obj.n_spins > 0)
+                by_S[{plans[i]->S, plans[i]->S == 1 && plans[i]->prog.matrix_only}].push_back(i);
         for (auto& kv : by_S) {
             // Longest tiles first: workgroups take items in record order, so
             // the requests whose tiles take longest start first and short
@@ -197,7 +202,8 @@ ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::
             std::stable_sort(kv.second.begin(), kv.second.end(),
                              [&](size_t a, size_t b) { return cost[a] > cost[b]; });
             RoundImage::Class c;
-            c.S = kv.first;
+            c.S = kv.first.first;
+            c.matrix_only = kv.first.second;
             c.n_req = (int32_t)kv.second.size();
             c.items_off = reserve_bytes(sizeof(BatchItem) * kv.second.size());
             c.counter_off = reserve_bytes(sizeof(unsigned long long));
@@ -264,7 +270,7 @@ ps_status round_nodes(const Ctx* ctx, const RoundImage& R, unsigned char* dev, s
     for (const RoundImage::Class& c : R.classes) {
         const hipError_t e = batch_step_nodes(reinterpret_cast<const BatchItem*>(dev + c.items_off), c.n_req,
                                               c.total, reinterpret_cast<unsigned long long*>(dev + c.counter_off),
-                                              c.dyn_lds, ctx->cfg.precision, c.S, ctx->n_cu, nodes);
+                                              c.dyn_lds, ctx->cfg.precision, c.S, ctx->n_cu, nodes, c.matrix_only);
         if (e != hipSuccess) return hip_fail(e, "batch step node");
     }
     if (R.n_fin > 0) {

@@ -55,6 +55,7 @@ ps_status upload_tables_contiguous(std::vector<ReqPlan*>& plans, void* dev, Host
 struct RoundImage {
     struct Class {                      // one spins-per-lane class
         int S;
+        bool matrix_only;               // its requests' programs all are (Program::matrix_only)
         size_t items_off;               // offset of its BatchItem array in the image
         size_t counter_off;             // offset of its queue counter
         int32_t n_req;

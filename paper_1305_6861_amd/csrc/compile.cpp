@@ -365,4 +365,35 @@ void narrow_rotations(std::vector<Op>* ops) {
     }
 }
 
+void mark_matrix_readouts(Program* p) {
+    std::vector<Op>* ops = &p->ops;
+    auto same_step = [](const Op& a, const Op& b) {
+        return a.u.adc.tau == b.u.adc.tau && a.u.adc.mu[0] == b.u.adc.mu[0] && a.u.adc.mu[1] == b.u.adc.mu[1] &&
+               a.u.adc.mu[2] == b.u.adc.mu[2];
+    };
+    std::vector<size_t> adc;
+    for (size_t i = 0; i < ops->size(); ++i)
+        if ((*ops)[i].kind == OP_ADC) adc.push_back(i);
+    for (size_t a = 0; a < adc.size(); ++a) {
+        Op& op = (*ops)[adc[a]];
+        op.flags &= ~OPF_MATRIX;
+        if (op.n < (uint32_t)kMatrixMinSamples) continue;
+        const bool prev = a > 0 && same_step((*ops)[adc[a - 1]], op);
+        const bool next = a + 1 < adc.size() && same_step((*ops)[adc[a + 1]], op);
+        if (prev || next) op.flags |= OPF_MATRIX;
+    }
+    p->matrix_only = true;
+    const Op* first = nullptr;
+    for (const Op& op : *ops) {
+        if (op.kind == OP_ADCT || (op.kind == OP_ADC && !(op.flags & OPF_MATRIX))) p->matrix_only = false;
+        if (op.kind != OP_ADC) continue;
+        if (!first) first = &op;
+        else if (!same_step(*first, op)) p->matrix_only = false;
+    }
+    if (p->matrix_only && first) {
+        for (int d = 0; d < 3; ++d) p->matrix_mu[d] = first->u.adc.mu[d];
+        p->matrix_tau = first->u.adc.tau;
+    }
+}
+
 }  // namespace ps

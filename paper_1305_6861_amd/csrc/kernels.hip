@@ -37,6 +37,22 @@
 // sum each lane ends with into its wave group's row.  A second kernel sums
 // all rows in FP64 in row order.  Every order is fixed, so results are
 // bitwise reproducible for a given tiling.
+//
+// Matrix-core readout (FP32, one spin per lane, readouts the host flags
+// OPF_MATRIX): with sample t = 16 b + j of a 128-sample tile, the signal is
+//   s(16 b + j) = sum_n (m_n z_n^(16 b)) z_n^j,
+// a complex matrix product over the spins n of (8 x N) and (N x 16), where
+// m_n is the spin's value at the tile's first sample.  Written with real
+// operands (rows (b, re/im), two contraction slots (re, im) per spin) it is
+// one v_mfma_f32_16x16x4_f32 per two spins and tile.  The factors z^j and
+// z^(16 b) depend only on the spin and the readout's per-sample step, so
+// they are built once per step and kept in registers: z^j in the B operand's
+// layout, z^(16 b) for the lane's own spin.  Per tile each lane forms its
+// spin's eight a_b = m z^(16 b) and stores them (Re, Im, -Im: the three
+// entries the real form of a complex product needs) in the wave's LDS tile,
+// from which the A operands are read four MFMAs at a time.  The waves'
+// 16 x 16 results are added in LDS in wave order, and one row per workgroup
+// is written, as in the vector path.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -134,6 +150,31 @@ template <> struct Math<double> {
         sincospi(2.0 * f, &si, &co);
     }
 };
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Tables of the matrix-core readout held by each lane (one spin per lane;
+// see the file comment).  MFMA q (q = 0 .. 31) of a tile takes the spins of
+// lanes q and q + 32; lane l supplies operand A[i][k] with i = l & 15 (row
+// (b, p) = (i >> 1, i & 1)) and k = l >> 4 (spin lane q + 32 (k >> 1),
+// component c = k & 1), and operand B[k][j] with j = l & 15:
+//   A = row (b, p), slot c of a_b: Re a_b for p == c, -Im a_b for
+//       (p, c) = (0, 1), Im a_b for (1, 0);
+//   bq[q] = component c of z^j of that spin.
+// (wr, wi)[b] = z^(16 b) (b = 1 .. 7) and (zr, zi) = z^128 belong to the
+// lane's own spin.
+template <bool On> struct MatrixTables {};
+template <> struct MatrixTables<true> {
+    float bq[32];
+    float wr[8], wi[8];
+    float zr, zi;
+};
+// The A-operand tile of a wave in LDS: rows (h, b, v) for the spins of
+// lanes 32 h .. 32 h + 31 (v = 0: Re a_b, 1: Im a_b, 2: -Im a_b), 32 columns
+// (one per spin); column q is stored at q ^ (4 (row & 7)), which keeps each
+// 4-column group contiguous and spreads the 16 rows a 16-lane read touches
+// over the LDS banks.
+constexpr int kMatrixARows = 2 * 8 * 3;
 
 // ---------------------------------------------------------------------------
 // wave-wide transpose-reduce of 64 values per lane -> 1 value per lane
@@ -434,11 +475,22 @@ __device__ __forceinline__ void step_delta(double c, double tau, double r2, real
 
 // LDS of a step workgroup outside the dynamic part (s_ops, s_x below).
 template <typename real, int S>
+struct MatrixReadout {
+    static constexpr bool on = std::is_same<real, float>::value && S == 1;
+    static constexpr int LW = on ? kWaves : 1;   // LDS extents (1 when off)
+};
+
+template <typename real, int S>
 constexpr size_t static_lds_bytes() {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int NF = StepFactors<real, S>::NF;
+    // the matrix-core arrays exist only where that readout does (the
+    // compiler drops the placeholders of the other kernels)
+    constexpr size_t matrix = MatrixReadout<real, S>::on
+                                  ? sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64
+                                  : 0;
     return sizeof(Op) * kOpChunk + sizeof(real) * 2 * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 64 * 2 +
-           sizeof(real) * S * NF * kBlock + sizeof(real) * (G > 1 ? kWaves : 1) * 64;
+           sizeof(real) * S * NF * kBlock + sizeof(real) * (G > 1 ? kWaves : 1) * 64 + matrix;
 }
 
 // Shaped-pulse propagator of every spin of this lane (see ps_ops.h): the
@@ -541,9 +593,148 @@ __device__ __forceinline__ void shape_apply(const real* cache, bool turn, real c
     }
 }
 
+// Matrix-core readout tables of the lane (MatrixTables) for the per-sample
+// step (mu, tau): every factor from its own FP64 phase, the other spins'
+// parameters (for the B operand) fetched by lane shuffles.
+__device__ __forceinline__ void matrix_tables(const Spins<float, 1>& sp, const double (&mu)[3], double tau, int lane,
+                                              MatrixTables<true>& mt) {
+    const int j = lane & 15;                 // B: sample inside the block
+    const int c = (lane >> 4) & 1;           // contraction slot: component of the spin
+    const int half = lane >> 5;
+    {
+        const double ph = phase_rev(mu, tau, sp.x[0], sp.y[0], sp.z[0], sp.dw[0]);
+        auto power = [&](double e, float& re, float& im) {   // z^e of the lane's own spin
+            float co, sn;
+            Math<float>::cis(ph * e, co, sn);
+            const float m = Math<float>::expneg(tau * e, sp.r2[0]);
+            re = m * co;
+            im = -m * sn;
+        };
+        mt.wr[0] = 1.0f;
+        mt.wi[0] = 0.0f;
+#pragma unroll
+        for (int b = 1; b < 8; ++b) power(16.0 * b, mt.wr[b], mt.wi[b]);
+        power((double)kMatrixTile, mt.zr, mt.zi);
+    }
+    static_for<0, 32>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int src = q + 32 * half;
+        const float x = __shfl(sp.x[0], src), y = __shfl(sp.y[0], src), z = __shfl(sp.z[0], src),
+                    dw = __shfl(sp.dw[0], src);
+        const double r2 = __shfl(sp.r2[0], src);
+        float co, sn;
+        Math<float>::cis(phase_rev(mu, tau, x, y, z, dw) * (double)j, co, sn);
+        const float e = Math<float>::expneg(tau * (double)j, r2);
+        mt.bq[q] = c == 0 ? e * co : -e * sn;           // component c of z^j
+    });
+}
+
+// Matrix-core readout of one ADC operation (n samples) for one receive coil
+// (weight (wx, wy) when weighted): tiles of kMatrixTile samples; m starts
+// each tile from an FP64 phase every kMatrixReanchor tiles and is stepped by
+// z^128 in between.  s_a is the wave's A-operand tile; out points at the
+// coil's first sample of this operation in the workgroup's row (2 reals per
+// sample).  Every wave of the workgroup takes part (one barrier per tile).
+constexpr int kMatrixReanchor = 8;
+
+__device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const Op& op, const double (&mu)[3],
+                                               double tau, int n, bool weighted, float wx, float wy,
+                                               const MatrixTables<true>& mt, float* s_a, float4* s_md,
+                                               int& m_pass, int wave, int lane,
+                                               __attribute__((address_space(1))) float* out) {
+    const int n_tiles = (n + kMatrixTile - 1) / kMatrixTile;
+    const int half = lane >> 5;
+    const int col = lane & 31;
+    // this lane's A operand: row (h, b, v) with v from (p, c) (see MatrixTables)
+    const int p = lane & 1, c = (lane >> 4) & 1;
+    const int a_row = (half * 8 + ((lane & 15) >> 1)) * 3 + (p == c ? 0 : (p == 1 ? 1 : 2));
+    const float* a_src = s_a + a_row * 32;
+    const int a_swz = 4 * (a_row & 7);
+    float mr = 0.0f, mi = 0.0f;
+    for (int tile = 0; tile < n_tiles; ++tile) {
+        if (tile % kMatrixReanchor == 0) {
+            // value at sample s0 from the anchors, as in the vector path
+            const double s0 = (double)tile * kMatrixTile;
+            const double t = op.txy + s0 * tau;
+            const double k[3] = {op.k[0] + s0 * mu[0], op.k[1] + s0 * mu[1], op.k[2] + s0 * mu[2]};
+            const float e2 = Math<float>::expneg(t, sp.r2[0]);
+            float co, sn;
+            Math<float>::cis(phase_rev(k, t, sp.x[0], sp.y[0], sp.z[0], sp.dw[0]), co, sn);
+            const float pr = e2 * (sp.ar[0] * co + sp.ai[0] * sn);
+            const float pi = e2 * (sp.ai[0] * co - sp.ar[0] * sn);
+            if (weighted) {
+                mr = fmaf(wx, pr, wy * pi);
+                mi = fmaf(wx, pi, -wy * pr);
+            } else {
+                mr = pr;
+                mi = pi;
+            }
+        } else {
+            const float t_ = mr * mt.zr - mi * mt.zi;
+            mi = mr * mt.zi + mi * mt.zr;
+            mr = t_;
+        }
+        // this spin's a_b = m z^(16 b) into the wave's tile; LDS operations
+        // of a wave complete in order, so the reads below see these writes
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            float re = mr, im = mi, nim = -mi;
+            if (b > 0) {
+                const float t2 = mi * mt.wr[b], t1 = mi * mt.wi[b];
+                re = fmaf(mr, mt.wr[b], -t1);
+                im = fmaf(mr, mt.wi[b], t2);
+                nim = fmaf(-mr, mt.wi[b], -t2);
+            }
+            const int r0 = (half * 8 + b) * 3;
+            s_a[(r0 + 0) * 32 + (col ^ (4 * ((r0 + 0) & 7)))] = re;
+            s_a[(r0 + 1) * 32 + (col ^ (4 * ((r0 + 1) & 7)))] = im;
+            s_a[(r0 + 2) * 32 + (col ^ (4 * ((r0 + 2) & 7)))] = nim;
+        }
+        // all eight operand reads in flight before the first product, so
+        // that no LDS latency sits between the matrix-core instructions
+        float4 av[8];
+        static_for<0, 8>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            av[g] = *reinterpret_cast<const float4*>(a_src + ((4 * g) ^ a_swz));
+        });
+        floatx4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        static_for<0, 8>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].x, mt.bq[4 * g + 0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].y, mt.bq[4 * g + 1], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].z, mt.bq[4 * g + 2], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].w, mt.bq[4 * g + 3], acc1, 0, 0, 0);
+        });
+        // lane l holds rows 4 (l >> 4) + r (r = 0 .. 3) of column l & 15;
+        // two buffers for alternate tiles: a wave that writes buffer tb here
+        // has passed the previous tile's barrier, which every reader of tb's
+        // earlier contents had reached after reading it
+        const int tb = m_pass++ & 1;
+        s_md[(tb * kWaves + wave) * 64 + lane] =
+            make_float4(acc0[0] + acc1[0], acc0[1] + acc1[1], acc0[2] + acc1[2], acc0[3] + acc1[3]);
+        __syncthreads();
+        // thread (wave w, lane l): element w of lane l, added over the waves
+        // in wave order; it is component w & 1 of sample
+        // 16 (2 (l >> 4) + (w >> 1)) + (l & 15)
+        const float* md = reinterpret_cast<const float*>(s_md + tb * kWaves * 64);
+        float v = md[lane * 4 + wave];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) v += md[(w * 64 + lane) * 4 + wave];
+        const int t = 32 * (lane >> 4) + 16 * (wave >> 1) + (lane & 15);
+        const int smp = tile * kMatrixTile + t;
+        if (smp < n) out[2 * (int64_t)smp + (wave & 1)] = v;
+    }
+}
+
 // One workgroup tile of one request: spins [blk * 256 S, (blk + 1) * 256 S)
 // through the slice's operations, partial sums into the tile's rows.
-template <typename real, int S>
+// MO: the matrix-only kernel (FP32, S = 1) of programs whose readouts are all
+// marked OPF_MATRIX, none tabulated, all with the step (a.mx_mu, a.mx_tau):
+// it is built without the vector and trajectory readouts and builds the
+// tables once, before the operations, so that they are loop-invariant and
+// keep their registers (tables rebuilt inside the loop make the register
+// allocator move them at every readout).
+template <typename real, int S, bool MO = false>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, const int rep) {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int R = G * S;                 // spins per lane inside readouts
@@ -561,6 +752,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     // and read by the lanes of its wave group, one 16-byte vector per lane
     __shared__ __align__(16) real s_stepf[S][NF / V][kBlock][V];
     __shared__ real s_red[G > 1 ? kWaves : 1][64];   // chunk sums of waves sharing a chunk
+    // matrix-core readout: each wave's A-operand tile, and the waves'
+    // 16 x 16 results of a tile, in two buffers used by alternate tiles
+    constexpr bool kMatrix = MatrixReadout<real, S>::on;
+    static_assert(!MO || kMatrix, "the matrix-only kernel is FP32 at one spin per lane");
+    constexpr int LW = MatrixReadout<real, S>::LW;
+    constexpr int LR = kMatrix ? kMatrixARows * 32 : 1;
+    __shared__ __align__(16) float s_ta[LW][LR];
+    __shared__ __align__(16) float4 s_md[2][LW][64];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
     // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
@@ -625,8 +824,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     int adc_seen = 0;                        // readouts met so far (replica split)
     int x_pass = 0;                          // readout passes met so far (s_x buffer)
     bool step_valid = false;
+    MatrixTables<kMatrix> mt;                // valid for (mt_mu, mt_tau) when mt_valid
+    double mt_mu[3] = {0.0, 0.0, 0.0}, mt_tau = 0.0;
+    bool mt_valid = false;
+    int m_pass = 0;                          // matrix tiles met so far (s_md buffer)
     const auto partial = gmem(reinterpret_cast<real*>(a.partial)) +
                     (blk * (kWaves / G) + wave / G) * a.row_stride;
+    if constexpr (MO) {
+        const double mu0[3] = {a.mx_mu[0], a.mx_mu[1], a.mx_mu[2]};
+        matrix_tables(sp, mu0, a.mx_tau, lane, mt);
+    }
 
     for (int c0 = 0; c0 < a.n_ops; c0 += kOpChunk) {
         const int cn = min(kOpChunk, a.n_ops - c0);
@@ -740,7 +947,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     }
                     sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s];
                 }
-            } else if (kind == OP_ADCT) {
+            } else if (!MO && kind == OP_ADCT) {     // (no tabulated readouts reach MO)
                 // Readout at tabulated instants (non-uniform trajectories):
                 // every sample is evaluated directly from the anchors,
                 //   p_s = Mxy_a E2(t_s) exp(-j 2 pi (k_s . x + dw t_s / 2 pi)).
@@ -1011,6 +1218,35 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 const int aux = (int)__builtin_amdgcn_readfirstlane(op.aux);
                 const double tau = uniform(op.u.adc.tau);
                 const double mu[3] = {uniform(op.u.adc.mu[0]), uniform(op.u.adc.mu[1]), uniform(op.u.adc.mu[2])};
+                if constexpr (kMatrix) {
+                    if (MO || (__builtin_amdgcn_readfirstlane(op.flags) & OPF_MATRIX)) {
+                        if (!MO && !(mt_valid && mu[0] == mt_mu[0] && mu[1] == mt_mu[1] && mu[2] == mt_mu[2] &&
+                                     tau == mt_tau)) {
+                            matrix_tables(sp, mu, tau, lane, mt);
+                            mt_mu[0] = mu[0]; mt_mu[1] = mu[1]; mt_mu[2] = mu[2];
+                            mt_tau = tau;
+                            mt_valid = true;
+                        }
+                        if (a.n_coils == 0) {
+                            matrix_readout(sp, op, mu, tau, n, false, 1.0f, 0.0f, mt, s_ta[wave < LW ? wave : 0],
+                                           &s_md[0][0][0], m_pass, wave, lane, partial + 2 * (int64_t)aux);
+                            continue;
+                        }
+                        for (int coil = 0; coil < a.n_coils; ++coil) {
+                            // coil weight (S_x - j S_y) at the spin
+                            const int64_t i = base + lane;
+                            float wx = 0.0f, wy = 0.0f;
+                            if (i < a.n_spins) {
+                                wx = gmem(a.s_x)[coil * a.n_spins + i];
+                                wy = gmem(a.s_y)[coil * a.n_spins + i];
+                            }
+                            matrix_readout(sp, op, mu, tau, n, true, wx, wy, mt, s_ta[wave < LW ? wave : 0],
+                                           &s_md[0][0][0], m_pass, wave, lane,
+                                           partial + coil * a.coil_stride + 2 * (int64_t)aux);
+                        }
+                        continue;
+                    }
+                }
                 // Per spin: the sample-0 value p0 and the step factors
                 // (StepFactors), all from FP64 phases.  Step factors depend
                 // only on (mu, tau) and the spin; successive readouts of a
@@ -1267,25 +1503,22 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     }
 }
 
-// Waves per SIMD the register allocation is held to: for FP32, three at 1
-// spin per lane (its readout of 4 spins per lane fits 168 registers; the
-// spills left are on cold paths: the prologue and the shaped-pulse set-up)
-// and two at 2 (the readout is tuned to fit 256 registers, and a second
-// wave hides the latency of its LDS and transcendental operations); else
-// whatever the code needs.  Three waves per SIMD give objects of 2 to 3
-// waves per SIMD at S = 1 a single pass over the chip instead of a full
-// pass and a partial one.
+// Waves per SIMD the register allocation is held to: for FP32, two at 1
+// and 2 spins per lane (at 1 the matrix-core readout keeps 50 table
+// registers live next to the vector readout's; at 2 the readout is tuned to
+// fit 256 registers, and a second wave hides the latency of its LDS and
+// transcendental operations); else whatever the code needs.
 template <typename real, int S>
 struct StepOccupancy {
-    static constexpr int kWavesPerEU = !std::is_same<real, float>::value ? 1 : S == 1 ? 3 : S == 2 ? 2 : 1;
+    static constexpr int kWavesPerEU = !std::is_same<real, float>::value ? 1 : S <= 2 ? 2 : 1;
 };
 
 // Workgroup b runs tile b % n_tiles as readout replica b / n_tiles.
-template <typename real, int S>
+template <typename real, int S, bool MO = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S>::kWavesPerEU)))
 void step_kernel(StepArgs a) {
     const int64_t b = blockIdx.x;
-    step_body<real, S>(a, b % a.n_tiles, (int)(b / a.n_tiles));
+    step_body<real, S, MO>(a, b % a.n_tiles, (int)(b / a.n_tiles));
 }
 
 // Persistent form: workgroups take (request, tile, readout replica) items
@@ -1294,7 +1527,7 @@ void step_kernel(StepArgs a) {
 // request's items being its tiles times its replicas, replica-major).  Every
 // item writes only its own rows and samples, so which workgroup runs it
 // never changes a result.
-template <typename real, int S>
+template <typename real, int S, bool MO = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S>::kWavesPerEU)))
 void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_t total,
                        unsigned long long* counter) {
@@ -1312,7 +1545,7 @@ void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_
         }
         const StepArgs a = reqs[lo].args;
         const int64_t local = item - reqs[lo].item_begin;   // replica-major over the tiles
-        step_body<real, S>(a, local % a.n_tiles, (int)(local / a.n_tiles));
+        step_body<real, S, MO>(a, local % a.n_tiles, (int)(local / a.n_tiles));
     }
 }
 
@@ -1469,32 +1702,36 @@ int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape
     return n;
 }
 
-template <typename real, int S>
+template <typename real, int S, bool MO = false>
 static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t st) {
     const size_t dyn = dyn_lds_t<real, S>(a.n_shape_rows, a.n_cache_slots);
     StepArgs b = a;
     b.n_tiles = n_blocks;
     if (b.n_replicas < 1) b.n_replicas = 1;
-    hipLaunchKernelGGL((step_kernel<real, S>), dim3((unsigned)(n_blocks * b.n_replicas)), dim3(kBlock), dyn, st, b);
+    hipLaunchKernelGGL((step_kernel<real, S, MO>), dim3((unsigned)(n_blocks * b.n_replicas)), dim3(kBlock), dyn, st,
+                       b);
     return hipGetLastError();
 }
 
-template <typename real, int S>
+template <typename real, int S, bool MO = false>
 static hipError_t launch_batch_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                                  size_t dyn, int n_cu, hipStream_t st) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S>, kBlock, dyn) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S, MO>, kBlock, dyn) !=
             hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t grid = std::min<int64_t>(total, (int64_t)per_cu * n_cu);
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((batch_step_kernel<real, S>), dim3((unsigned)grid), dim3(kBlock), dyn, st, reqs, n_req,
+    hipLaunchKernelGGL((batch_step_kernel<real, S, MO>), dim3((unsigned)grid), dim3(kBlock), dyn, st, reqs, n_req,
                        total, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st) {
+                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st,
+                             bool matrix_only) {
+    if (precision != 64 && spins_per_lane == 1 && matrix_only)
+        return launch_batch_t<float, 1, true>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
     if (precision == 64) {
         switch (spins_per_lane) {
             case 1: return launch_batch_t<double, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
@@ -1545,17 +1782,17 @@ hipError_t KernelNode::launch(hipStream_t st) {
     return hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, p.sharedMemBytes, st);
 }
 
-template <typename real, int S>
+template <typename real, int S, bool MO = false>
 static hipError_t batch_node_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                                size_t dyn, int n_cu, std::vector<KernelNode>* out) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S>, kBlock, dyn) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S, MO>, kBlock, dyn) !=
             hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t grid = std::min<int64_t>(total, (int64_t)per_cu * n_cu);
     if (grid <= 0) return hipSuccess;
     KernelNode k;
-    k.func = reinterpret_cast<const void*>(&batch_step_kernel<real, S>);
+    k.func = reinterpret_cast<const void*>(&batch_step_kernel<real, S, MO>);
     k.grid = dim3((unsigned)grid);
     k.block = dim3(kBlock);
     k.shmem = dyn;
@@ -1566,7 +1803,10 @@ static hipError_t batch_node_t(const BatchItem* reqs, int32_t n_req, int64_t tot
 }
 
 hipError_t batch_step_nodes(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                            size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out) {
+                            size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out,
+                            bool matrix_only) {
+    if (precision != 64 && spins_per_lane == 1 && matrix_only)
+        return batch_node_t<float, 1, true>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
     if (precision == 64) {
         switch (spins_per_lane) {
             case 1: return batch_node_t<double, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
@@ -1763,8 +2003,9 @@ hipError_t noalloc_scratch(int device, void** ptr) {
 }
 
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
-                       hipStream_t st) {
+                       hipStream_t st, bool matrix_only) {
     if (n_blocks <= 0) return hipSuccess;
+    if (precision != 64 && spins_per_lane == 1 && matrix_only) return launch_step_t<float, 1, true>(a, n_blocks, st);
     if (precision == 64) {
         switch (spins_per_lane) {
             case 1: return launch_step_t<double, 1>(a, n_blocks, st);

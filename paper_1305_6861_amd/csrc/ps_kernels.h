@@ -36,6 +36,8 @@ struct StepArgs {
     const double* traj;      // device, trajectory rows (K + k_s, txy + t_s), 4 doubles each
     int32_t n_replicas;      // readout replicas per tile (>= 1; launch_step only)
     int64_t n_tiles;         // workgroup tiles of the object (set by launch_step)
+    double mx_mu[3];         // matrix-only kernel: the per-sample step (mu, tau) that every
+    double mx_tau;           // readout of the program shares
 };
 
 // One request of a persistent batched launch: its arguments and the number
@@ -64,8 +66,14 @@ int64_t rows_per_block_of(int spins_per_lane);
 
 // Launches n_blocks * a.n_replicas workgroups: every tile of the object
 // once per readout replica (replicas split the slice's readouts).
+// matrix_only (a program whose readouts are all marked OPF_MATRIX, none
+// tabulated, and share one per-sample step, given in a.mx_mu / a.mx_tau)
+// selects, at FP32 and one spin per lane, a kernel built without the vector
+// and trajectory readouts that builds the matrix-core tables once, before
+// its operations, so they stay in the same registers throughout; elsewhere
+// it is ignored.
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
-                       hipStream_t st);
+                       hipStream_t st, bool matrix_only = false);
 // Dynamic LDS of a step workgroup: shaped-pulse rows and propagator slots.
 size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots);
 // Propagator slots (at most kShapeSlots) that fit a step workgroup's LDS
@@ -87,7 +95,8 @@ hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t st);
 // counter (device) must hold 0; dyn_lds covers every request's
 // step_dyn_lds_bytes.
 hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st);
+                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st,
+                             bool matrix_only = false);
 hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
                                  hipStream_t st);
 
@@ -110,7 +119,8 @@ struct KernelNode {
 // The launches launch_batch_step / launch_batch_finalize would make, as
 // nodes appended to *out (none when there is nothing to run).
 hipError_t batch_step_nodes(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
-                            size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out);
+                            size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out,
+                            bool matrix_only = false);
 hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
                                 std::vector<KernelNode>* out);
 int64_t row_group_size();

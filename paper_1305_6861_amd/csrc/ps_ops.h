@@ -33,7 +33,14 @@ enum OpKind : uint32_t {
 enum OpFlags : uint32_t {
     OPF_MXY_ZERO = 1u,  // Mxy_a is known to be 0 for every spin (after init/spoil)
     OPF_EVEN_T = 2u,    // ADCT: sample instants equally spaced by u.tab.dt
+    OPF_MATRIX = 4u,    // ADC: sum over the spins on the matrix cores (FP32,
+                        // one spin per lane; other tilings ignore it)
 };
+
+// Matrix-core readouts: tiles of kMatrixTile samples; the host marks a
+// readout for them from kMatrixMinSamples samples on.
+constexpr int kMatrixTile = 128;
+constexpr int kMatrixMinSamples = 64;
 
 // 128-byte operation record.
 struct alignas(16) Op {

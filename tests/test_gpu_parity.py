@@ -108,21 +108,22 @@ def test_c3_full_object_subset_truncated(ctx32):
     check(ctx32, subset(obj, 4096, 7), seq.truncated(3 * 48), TOL32, label="c3 subset/4096")
 
 
-def test_c3_full_sequence_spin_subset_sliced_s2(ps):
+def test_c3_full_sequence_spin_subset_sliced(ps):
     """Every 1024th spin of the full 2 x 128^3 object (4,096 spins) through
-    all 16,384 repetitions at 2 spins per lane, with the partial-sum buffer
-    held to 4 MiB so that the 2,097,152 samples run as 32 time slices of
-    65,536: the sinc propagator cached in the first slice is written to the
-    slice state and read back by all 31 later slices at S = 2, and the spin
-    anchors pass through the alternating anchor buffers.  Without readout
-    replicas (the tiling the full object gets), and with them (8 tiles, so
-    replicas share every slice's 512 readouts)."""
+    all 16,384 repetitions, with the partial-sum buffer held to 4 MiB.  At 2
+    spins per lane the 2,097,152 samples run as 32 time slices of 65,536: the
+    sinc propagator cached in the first slice is written to the slice state
+    and read back by all 31 later slices at S = 2, and the spin anchors pass
+    through the alternating anchor buffers.  Without readout replicas (the
+    tiling the full object gets), and with them (8 tiles, so replicas share
+    every slice's 512 readouts).  At 1 spin per lane (64 slices) every
+    readout is summed on the matrix cores."""
     obj, seq = C.c3()
     sub = subset(obj, 1024, 5)
     ref = oracle.simulate(sub, seq)
-    for split in (False, True):
-        with ps.Context(precision=32, spins_per_lane=2, readout_split=split, max_partial_bytes=4 << 20) as ctx:
-            within(gpu(ctx, sub, seq), ref, TOL32, f"c3 subset/1024 full sequence S=2, 32 slices, split={split}")
+    for S, split in ((2, False), (2, True), (1, False), (1, True)):
+        with ps.Context(precision=32, spins_per_lane=S, readout_split=split, max_partial_bytes=4 << 20) as ctx:
+            within(gpu(ctx, sub, seq), ref, TOL32, f"c3 subset/1024 full sequence S={S}, sliced, split={split}")
 
 
 def test_replicas_across_many_slices_fp64(ps):
