@@ -118,7 +118,7 @@ ps_status validate_object(const ps_object* obj) {
 
 int shape_cache_slots(const Ctx* ctx, int S, const Program& prog) {
     if (ctx->cfg.flags & PS_CFG_NO_SHAPE_CACHE) return 0;
-    return shape_cache_slots_fitting(ctx->cfg.precision, S, (int32_t)(prog.rows.size() / 9));
+    return shape_cache_slots_fitting(ctx->cfg.precision, S, (int32_t)(prog.rows.size() / 9), prog.matrix_only);
 }
 
 // Compile + slice a request for a given number of partial-sum rows, spins
@@ -134,9 +134,10 @@ ps_status prepare(const Ctx* ctx, const ps_sequence* seq, int64_t n_rows, int S,
     int64_t max_samples = budget / per_sample;
     if (max_samples < 64) max_samples = 64;
     plan_slices(prog, max_samples);
+    // the readout path first: the matrix-only kernel's LDS sets the slots
+    if (ctx->cfg.precision != 64 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT)) mark_matrix_readouts(prog);
     assign_shape_slots(prog, shape_cache_slots(ctx, S, *prog));
     if (ctx->cfg.precision != 64) narrow_rotations(&prog->ops);
-    if (ctx->cfg.precision != 64 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT)) mark_matrix_readouts(prog);
     return PS_OK;
 }
 

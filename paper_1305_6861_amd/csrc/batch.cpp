@@ -222,7 +222,7 @@ ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::
                 it.n_items = p->n_blocks * R;
                 total += it.n_items;
                 dyn = std::max(dyn, step_dyn_lds_bytes(ctx->cfg.precision, c.S, it.args.n_shape_rows,
-                                                       it.args.n_cache_slots));
+                                                       it.args.n_cache_slots, c.matrix_only));
                 std::memcpy(img.data() + c.items_off + q * sizeof(BatchItem), &it, sizeof(it));
             }
             c.total = total;

@@ -510,8 +510,8 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-template <typename real, int S>
-__device__ __forceinline__ void shape_fill(const Spins<real, S>& sp, const Op& op, const double* rows, int n_sub,
+template <typename real, int S, typename RowPtr>
+__device__ __forceinline__ void shape_fill(const Spins<real, S>& sp, const Op& op, RowPtr rows, int n_sub,
                                            real* cache) {
     const double tau = op.u.shape.tau;
     static_for<0, S>([&](auto si) {
@@ -524,7 +524,10 @@ __device__ __forceinline__ void shape_fill(const Spins<real, S>& sp, const Op& o
         // vectors 0..2: columns of A; vector 3: b
         double vx[4] = {1.0, 0.0, 0.0, 0.0}, vy[4] = {0.0, 1.0, 0.0, 0.0}, vz[4] = {0.0, 0.0, 1.0, 0.0};
         for (int q = 0; q < n_sub; ++q) {
-            rotate<double, 4>(rows + 9 * q, vx, vy, vz);
+            double r[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) r[e] = rows[9 * q + e];
+            rotate<double, 4>(r, vx, vy, vz);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const double a_ = vx[v], b_ = vy[v];
@@ -761,10 +764,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     __shared__ __align__(16) float s_ta[LW][LR];
     __shared__ __align__(16) float4 s_md[2][LW][64];
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    double* s_rows = reinterpret_cast<double*>(s_dyn);   // shaped-pulse deltas, FP64
+    // shaped-pulse deltas, FP64: staged in LDS, except in the matrix-only
+    // kernel, which reads them (wave-uniform) through the scalar cache and
+    // keeps its LDS for a third workgroup per CU
+    double* s_rows = reinterpret_cast<double*>(s_dyn);
+    const auto c_rows = reinterpret_cast<__attribute__((address_space(4))) const double*>(
+        reinterpret_cast<uintptr_t>(a.rows));
     // then the propagator cache: a.n_cache_slots slots of kShapeCacheReals x S
     // x kBlock reals; every lane reads only the entries it wrote itself
-    real* s_cache = reinterpret_cast<real*>(s_rows + 9 * a.n_shape_rows);
+    real* s_cache = reinterpret_cast<real*>(s_rows + (MO ? 0 : 9 * a.n_shape_rows));
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -814,7 +822,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     }
 
     // shaped-pulse rotation rows -> LDS (made visible by the first barrier below)
-    {
+    if constexpr (!MO) {
         const auto rows = gmem(reinterpret_cast<const double*>(a.rows));
         for (int i = tid; i < a.n_shape_rows * 9; i += kBlock) s_rows[i] = rows[i];
     }
@@ -898,7 +906,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 evaluate<real, S>(sp, op, mxy_zero, ex, ey, ez);
                 const uint32_t mode = __builtin_amdgcn_readfirstlane(op.u.shape.mode);
                 const int n_sub = (int)__builtin_amdgcn_readfirstlane(op.n);
-                const double* rows = s_rows + 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
+                const int row0 = 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
+                // rows: LDS, or the constant address space in the matrix-only kernel
+                auto shaped = [&](auto rows) {
                 if (mode != SHAPE_DIRECT) {
                     real* cache = s_cache +
                                   (int)__builtin_amdgcn_readfirstlane(op.u.shape.slot) * (kShapeCacheReals * S * kBlock) +
@@ -908,7 +918,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     shape_apply<real, S>(cache, rc != 1.0 || rs != 0.0, (real)rc, (real)rs, mxy_zero, ex, ey, ez);
 #pragma unroll
                     for (int s = 0; s < S; ++s) { sp.ar[s] = ex[s]; sp.ai[s] = ey[s]; sp.az[s] = ez[s]; }
-                    continue;
+                    return;
                 }
                 double mx[S], my[S], mz[S];
                 const double tau = op.u.shape.tau;
@@ -929,7 +939,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     m0d[s] = (double)sp.m0[s];
                 }
                 for (int q = 0; q < n_sub; ++q) {
-                    rotate<double, S>(rows + 9 * q, mx, my, mz);
+                    double r[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) r[e] = rows[9 * q + e];
+                    rotate<double, S>(r, mx, my, mz);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         const double a_ = mx[s], b_ = my[s];
@@ -947,6 +960,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                     }
                     sp.ar[s] = (real)mx[s]; sp.ai[s] = (real)my[s]; sp.az[s] = (real)mz[s];
                 }
+                };
+                if constexpr (MO) shaped(c_rows + row0);
+                else shaped(s_rows + row0);
             } else if (!MO && kind == OP_ADCT) {     // (no tabulated readouts reach MO)
                 // Readout at tabulated instants (non-uniform trajectories):
                 // every sample is evaluated directly from the anchors,
@@ -1507,15 +1523,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 // and 2 spins per lane (at 1 the matrix-core readout keeps 50 table
 // registers live next to the vector readout's; at 2 the readout is tuned to
 // fit 256 registers, and a second wave hides the latency of its LDS and
-// transcendental operations); else whatever the code needs.
-template <typename real, int S>
+// transcendental operations) and three in the matrix-only kernel (its
+// spills are on cold paths: the prologue, the table build and the
+// shaped-pulse fill); else whatever the code needs.
+template <typename real, int S, bool MO = false>
 struct StepOccupancy {
-    static constexpr int kWavesPerEU = !std::is_same<real, float>::value ? 1 : S <= 2 ? 2 : 1;
+    static constexpr int kWavesPerEU = MO ? 3 : !std::is_same<real, float>::value ? 1 : S <= 2 ? 2 : 1;
 };
 
 // Workgroup b runs tile b % n_tiles as readout replica b / n_tiles.
 template <typename real, int S, bool MO = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S>::kWavesPerEU)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, MO>::kWavesPerEU)))
 void step_kernel(StepArgs a) {
     const int64_t b = blockIdx.x;
     step_body<real, S, MO>(a, b % a.n_tiles, (int)(b / a.n_tiles));
@@ -1528,7 +1546,7 @@ void step_kernel(StepArgs a) {
 // item writes only its own rows and samples, so which workgroup runs it
 // never changes a result.
 template <typename real, int S, bool MO = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S>::kWavesPerEU)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, MO>::kWavesPerEU)))
 void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_t total,
                        unsigned long long* counter) {
     __shared__ unsigned long long s_item;
@@ -1662,13 +1680,22 @@ __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <typename real, int S>
+template <typename real, int S, bool MO = false>
 static size_t dyn_lds_t(int32_t n_shape_rows, int32_t n_cache_slots) {
-    return (size_t)n_shape_rows * 9 * sizeof(double) +
+    return (MO ? 0 : (size_t)n_shape_rows * 9 * sizeof(double)) +
            (size_t)n_cache_slots * kShapeCacheReals * S * kBlock * sizeof(real);
 }
 
-size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots) {
+// LDS the matrix-only kernel declares: operation chunk, A-operand tiles and
+// result buffers (the vector path's arrays are not in it).
+constexpr size_t matrix_only_static_lds_bytes() {
+    return sizeof(Op) * kOpChunk + sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64;
+}
+
+size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
+                          bool matrix_only) {
+    if (precision != 64 && spins_per_lane == 1 && matrix_only)
+        return dyn_lds_t<float, 1, true>(n_shape_rows, n_cache_slots);
     if (precision == 64) return spins_per_lane == 1 ? dyn_lds_t<double, 1>(n_shape_rows, n_cache_slots)
                                                     : dyn_lds_t<double, 2>(n_shape_rows, n_cache_slots);
     switch (spins_per_lane) {
@@ -1679,7 +1706,7 @@ size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_row
     }
 }
 
-int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows) {
+int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, bool matrix_only) {
     // FP32: keep a workgroup's LDS within half of a CU's 160 KiB so that two
     // workgroups (8 waves, the register-bound occupancy at S = 2) stay
     // resident per CU.  At S = 1 registers allow three; slots that push a
@@ -1687,8 +1714,13 @@ int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape
     // evaluations, which cost far more.  FP64 kernels run one workgroup per
     // CU anyway.
     const size_t kBudget = (precision == 64 ? 160 : 80) * 1024;
+    // The matrix-only kernel reads its shaped-pulse rows from memory: with one
+    // slot (12 KiB) it stays within a third of the CU's LDS, the three
+    // workgroups per CU its registers allow.
     size_t fixed;
-    if (precision == 64) fixed = spins_per_lane == 1 ? static_lds_bytes<double, 1>() : static_lds_bytes<double, 2>();
+    const bool mo = precision != 64 && spins_per_lane == 1 && matrix_only;
+    if (mo) fixed = matrix_only_static_lds_bytes();
+    else if (precision == 64) fixed = spins_per_lane == 1 ? static_lds_bytes<double, 1>() : static_lds_bytes<double, 2>();
     else switch (spins_per_lane) {
         case 1: fixed = static_lds_bytes<float, 1>(); break;
         case 2: fixed = static_lds_bytes<float, 2>(); break;
@@ -1697,14 +1729,14 @@ int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape
     }
     int n = 0;
     while (n < kShapeSlots &&
-           fixed + step_dyn_lds_bytes(precision, spins_per_lane, n_shape_rows, n + 1) <= kBudget)
+           fixed + step_dyn_lds_bytes(precision, spins_per_lane, n_shape_rows, n + 1, mo) <= kBudget)
         ++n;
     return n;
 }
 
 template <typename real, int S, bool MO = false>
 static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t st) {
-    const size_t dyn = dyn_lds_t<real, S>(a.n_shape_rows, a.n_cache_slots);
+    const size_t dyn = dyn_lds_t<real, S, MO>(a.n_shape_rows, a.n_cache_slots);
     StepArgs b = a;
     b.n_tiles = n_blocks;
     if (b.n_replicas < 1) b.n_replicas = 1;

@@ -74,11 +74,13 @@ int64_t rows_per_block_of(int spins_per_lane);
 // it is ignored.
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
                        hipStream_t st, bool matrix_only = false);
-// Dynamic LDS of a step workgroup: shaped-pulse rows and propagator slots.
-size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots);
+// Dynamic LDS of a step workgroup: shaped-pulse rows (not in the
+// matrix-only kernel, see launch_step) and propagator slots.
+size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
+                          bool matrix_only = false);
 // Propagator slots (at most kShapeSlots) that fit a step workgroup's LDS
 // budget next to n_shape_rows shaped-pulse rows.
-int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows);
+int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, bool matrix_only = false);
 // Finalize pass 1: each thread sums kFinVals consecutive values, so partial
 // rows and the coil blocks inside them are padded to a multiple of kFinVals
 // values; finalize_tiles(n) workgroups of 256 threads cover n values.

@@ -88,11 +88,15 @@ def test_c2_full_sequence_spin_subset(ps):
     both_paths(ps, subset(obj, 64, 3), seq, "c2 subset/64")
 
 
-def test_c3_recipe_reduced(ps):
-    """3-D GRE with the cached sinc at 16^3 x 2 species, 128-sample readouts."""
+@pytest.mark.parametrize("shape_cache", [True, False])
+def test_c3_recipe_reduced(ps, shape_cache):
+    """3-D GRE with the sinc at 16^3 x 2 species, 128-sample readouts: the
+    matrix-only kernel, which reads the sinc's sub-pulse rotations from
+    memory instead of LDS, with the cached propagator and stepping the
+    sub-steps directly."""
     obj, _ = C.c3(16)
     seq = C.gre_3d_sinc(128, 8, 3)
-    both_paths(ps, obj, seq, "c3 16^3 128-sample readouts")
+    both_paths(ps, obj, seq, f"c3 16^3 128-sample readouts shape_cache={shape_cache}", shape_cache=shape_cache)
 
 
 @pytest.mark.parametrize("n_coils", [1, 3])
