@@ -411,23 +411,61 @@ __device__ __forceinline__ double phase_rev(const double* k, double t, float x, 
     return fma(k[0], (double)x, fma(k[1], (double)y, fma(k[2], (double)z, (double)dw * kInv2Pi * t)));
 }
 
+// Relaxation factors of the lane's spin kept for the time they were last
+// formed for (the matrix-only kernel, one spin per lane): a sequence that
+// repeats its timing (every repetition of a Cartesian scan) forms them once.
+// A kept factor is the one the same computation gives, so results do not
+// change.
+template <bool On> struct DecayCache {};
+template <> struct DecayCache<true> {
+    double t1_time = -1.0, t2_time = -1.0;   // wave-uniform keys (times are >= 0)
+    float d1 = 0.0f, e2 = 0.0f;              // 1 - exp(-t1_time / T1), exp(-t2_time / T2)
+};
+
+template <typename real, int S, bool C>
+__device__ __forceinline__ real one_minus_e1(const Spins<real, S>& sp, int s, double t, DecayCache<C>* dc) {
+    if constexpr (C) {
+        if (t != dc->t1_time) {
+            dc->d1 = Math<real>::one_minus_expneg(t, sp.r1[s]);
+            dc->t1_time = t;
+        }
+        return dc->d1;
+    } else {
+        return Math<real>::one_minus_expneg(t, sp.r1[s]);
+    }
+}
+
+template <typename real, int S, bool C>
+__device__ __forceinline__ real e2_of(const Spins<real, S>& sp, int s, double t, DecayCache<C>* dc) {
+    if constexpr (C) {
+        if (t != dc->t2_time) {
+            dc->e2 = Math<real>::expneg(t, sp.r2[s]);
+            dc->t2_time = t;
+        }
+        return dc->e2;
+    } else {
+        return Math<real>::expneg(t, sp.r2[s]);
+    }
+}
+
 // Magnetisation at the instant described by (k, txy, tz) from the anchors.
-template <typename real, int S>
+template <typename real, int S, bool C = false>
 __device__ __forceinline__ void evaluate(const Spins<real, S>& sp, const Op& op, bool mxy_zero,
-                                         real (&mx)[S], real (&my)[S], real (&mz)[S]) {
+                                         real (&mx)[S], real (&my)[S], real (&mz)[S],
+                                         DecayCache<C>* dc = nullptr) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         // T1 recovery over tz as Mz_a + (M0 - Mz_a)(1 - E1): in a saturated
         // steady state Mz << M0, and M0 + (Mz_a - M0) E1 would cancel, turning
         // the rounding of E1 into a bias that is the same for this spin in
         // every repetition.
-        const real d1 = Math<real>::one_minus_expneg(op.tz, sp.r1[s]);
+        const real d1 = one_minus_e1<real, S, C>(sp, s, uniform(op.tz), dc);
         const real m0 = (real)sp.m0[s];
         mz[s] = fma(m0 - sp.az[s], d1, sp.az[s]);
         if (mxy_zero) {
             mx[s] = 0; my[s] = 0;
         } else {
-            real e2 = Math<real>::expneg(op.txy, sp.r2[s]);
+            real e2 = e2_of<real, S, C>(sp, s, uniform(op.txy), dc);
             real c, sn;
             Math<real>::cis(phase_rev(op.k, op.txy, sp.x[s], sp.y[s], sp.z[s], sp.dw[s]), c, sn);
             // (ar + j ai) (c - j sn)
@@ -640,11 +678,12 @@ __device__ __forceinline__ void matrix_tables(const Spins<float, 1>& sp, const d
 // sample).  Every wave of the workgroup takes part (one barrier per tile).
 constexpr int kMatrixReanchor = 8;
 
+template <bool C>
 __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const Op& op, const double (&mu)[3],
                                                double tau, int n, bool weighted, float wx, float wy,
                                                const MatrixTables<true>& mt, float* s_a, float4* s_md,
                                                int& m_pass, int wave, int lane,
-                                               __attribute__((address_space(1))) float* out) {
+                                               __attribute__((address_space(1))) float* out, DecayCache<C>* dc) {
     const int n_tiles = (n + kMatrixTile - 1) / kMatrixTile;
     const int half = lane >> 5;
     const int col = lane & 31;
@@ -658,9 +697,9 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
         if (tile % kMatrixReanchor == 0) {
             // value at sample s0 from the anchors, as in the vector path
             const double s0 = (double)tile * kMatrixTile;
-            const double t = op.txy + s0 * tau;
+            const double t = uniform(op.txy) + s0 * tau;
             const double k[3] = {op.k[0] + s0 * mu[0], op.k[1] + s0 * mu[1], op.k[2] + s0 * mu[2]};
-            const float e2 = Math<float>::expneg(t, sp.r2[0]);
+            const float e2 = e2_of<float, 1, C>(sp, 0, t, dc);
             float co, sn;
             Math<float>::cis(phase_rev(k, t, sp.x[0], sp.y[0], sp.z[0], sp.dw[0]), co, sn);
             const float pr = e2 * (sp.ar[0] * co + sp.ai[0] * sn);
@@ -746,7 +785,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     constexpr int NF = SF::NF;               // step factors per spin (re, im pairs)
     constexpr int V = SF::V;
     using vec_t = typename Vec16<real>::type;
-    __shared__ Op s_ops[kOpChunk];
+    __shared__ Op s_ops[MO ? 1 : kOpChunk];
     // readout sample-0 values (re, im) handed over inside wave groups, in two
     // buffers used by alternate readout passes
     __shared__ __align__(16) real s_x[2][G > 1 ? kWaves : 1][G > 1 ? S : 1][64][2];
@@ -832,6 +871,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     int adc_seen = 0;                        // readouts met so far (replica split)
     int x_pass = 0;                          // readout passes met so far (s_x buffer)
     bool step_valid = false;
+    DecayCache<MO> dc;                       // relaxation factors kept across repetitions
     MatrixTables<kMatrix> mt;                // valid for (mt_mu, mt_tau) when mt_valid
     double mt_mu[3] = {0.0, 0.0, 0.0}, mt_tau = 0.0;
     bool mt_valid = false;
@@ -843,25 +883,39 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
         matrix_tables(sp, mu0, a.mx_tau, lane, mt);
     }
 
-    for (int c0 = 0; c0 < a.n_ops; c0 += kOpChunk) {
-        const int cn = min(kOpChunk, a.n_ops - c0);
-        __syncthreads();
-        {
-            const auto src = gmem(reinterpret_cast<const uint32_t*>(a.ops + c0));
-            uint4* dst = reinterpret_cast<uint4*>(s_ops);
-            for (int i = tid; i < cn * 8; i += kBlock)
-                dst[i] = make_uint4(src[4 * i], src[4 * i + 1], src[4 * i + 2], src[4 * i + 3]);
+    // Operation records: staged in LDS a chunk at a time, except in the
+    // matrix-only kernel, which loads each (wave-uniform) record through the
+    // scalar cache straight into scalar registers: no vector instructions to
+    // make its fields uniform, no staging barriers.
+    const auto c_ops = reinterpret_cast<__attribute__((address_space(4))) const uint32_t*>(
+        reinterpret_cast<uintptr_t>(a.ops));
+    for (int c0 = 0; c0 < a.n_ops; c0 += (MO ? a.n_ops : kOpChunk)) {
+        const int cn = MO ? a.n_ops : min(kOpChunk, a.n_ops - c0);
+        if constexpr (!MO) {
+            __syncthreads();
+            {
+                const auto src = gmem(reinterpret_cast<const uint32_t*>(a.ops + c0));
+                uint4* dst = reinterpret_cast<uint4*>(s_ops);
+                for (int i = tid; i < cn * 8; i += kBlock)
+                    dst[i] = make_uint4(src[4 * i], src[4 * i + 1], src[4 * i + 2], src[4 * i + 3]);
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
         for (int j = 0; j < cn; ++j) {
-            const Op& op = s_ops[j];
+            Op op_copy;
+            if constexpr (MO) {
+                uint32_t* w = reinterpret_cast<uint32_t*>(&op_copy);
+#pragma unroll
+                for (int i = 0; i < (int)(sizeof(Op) / 4); ++i) w[i] = c_ops[(c0 + j) * (int)(sizeof(Op) / 4) + i];
+            }
+            const Op& op = MO ? op_copy : s_ops[j];
             const uint32_t kind = __builtin_amdgcn_readfirstlane(op.kind);
             const bool mxy_zero = (__builtin_amdgcn_readfirstlane(op.flags) & OPF_MXY_ZERO) != 0;
 
             if (kind == OP_RF) {
                 real mx[S], my[S], mz[S];
-                evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
+                evaluate<real, S, MO>(sp, op, mxy_zero, mx, my, mz, &dc);
                 const real* D = rot_of<real>(op);
                 if (mxy_zero) {              // (0, 0, Mz): only the third column of D acts
                     const real d02 = D[2], d12 = D[5], d22 = D[8];
@@ -882,7 +936,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 // the anchors are left as they are; replica 0 stores it
                 if (rep != 0) continue;
                 real mx[S], my[S], mz[S];
-                evaluate<real, S>(sp, op, mxy_zero, mx, my, mz);
+                evaluate<real, S, MO>(sp, op, mxy_zero, mx, my, mz, &dc);
                 const auto out = gmem(reinterpret_cast<real*>(a.snaps)) +
                             (int64_t)__builtin_amdgcn_readfirstlane(op.aux) * 3 * a.n_spins;
 #pragma unroll
@@ -903,7 +957,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                 // The rows hold the shape's own phases; the event's RF phase
                 // conjugates the whole pulse by Rz (see ps_ops.h).
                 real ex[S], ey[S], ez[S];
-                evaluate<real, S>(sp, op, mxy_zero, ex, ey, ez);
+                evaluate<real, S, MO>(sp, op, mxy_zero, ex, ey, ez, &dc);
                 const uint32_t mode = __builtin_amdgcn_readfirstlane(op.u.shape.mode);
                 const int n_sub = (int)__builtin_amdgcn_readfirstlane(op.n);
                 const int row0 = 9 * (int)__builtin_amdgcn_readfirstlane(op.aux);
@@ -1245,7 +1299,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                         }
                         if (a.n_coils == 0) {
                             matrix_readout(sp, op, mu, tau, n, false, 1.0f, 0.0f, mt, s_ta[wave < LW ? wave : 0],
-                                           &s_md[0][0][0], m_pass, wave, lane, partial + 2 * (int64_t)aux);
+                                           &s_md[0][0][0], m_pass, wave, lane, partial + 2 * (int64_t)aux, &dc);
                             continue;
                         }
                         for (int coil = 0; coil < a.n_coils; ++coil) {
@@ -1258,7 +1312,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                             }
                             matrix_readout(sp, op, mu, tau, n, true, wx, wy, mt, s_ta[wave < LW ? wave : 0],
                                            &s_md[0][0][0], m_pass, wave, lane,
-                                           partial + coil * a.coil_stride + 2 * (int64_t)aux);
+                                           partial + coil * a.coil_stride + 2 * (int64_t)aux, &dc);
                         }
                         continue;
                     }
@@ -1686,10 +1740,11 @@ static size_t dyn_lds_t(int32_t n_shape_rows, int32_t n_cache_slots) {
            (size_t)n_cache_slots * kShapeCacheReals * S * kBlock * sizeof(real);
 }
 
-// LDS the matrix-only kernel declares: operation chunk, A-operand tiles and
-// result buffers (the vector path's arrays are not in it).
+// LDS the matrix-only kernel declares: A-operand tiles and result buffers
+// (it reads its operations through the scalar cache, and the vector path's
+// arrays are not in it).
 constexpr size_t matrix_only_static_lds_bytes() {
-    return sizeof(Op) * kOpChunk + sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64;
+    return sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64;
 }
 
 size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
