@@ -225,10 +225,29 @@ ReplicaBound replica_bound(const Program& p, int n_out) {
     ReplicaBound b;
     b.hard = (int)std::max<int64_t>(1, std::min<int64_t>(max_adc, 64));
     b.work = b.hard;
-    const double readout = 6.0 * (double)p.n_samples * std::max(n_out, 1);
-    const double other = 80.0 * (double)(p.n_rf + p.n_snapshots) + 30.0 * (double)p.n_shape_substeps;
+    // rough per-spin costs in vector instructions: a sample on the vector
+    // path or (cheaper) on the matrix cores, a pulse or snapshot, a shaped
+    // pulse applied from its cached propagator, a sub-step stepped
+    const double per_sample = p.matrix_only ? 3.0 : 6.0;
+    double pulses = (double)(p.n_rf + p.n_snapshots), substeps = 0.0;
+    for (const Op& op : p.ops)
+        if (op.kind == OP_SHAPE) {
+            if (op.u.shape.mode == SHAPE_APPLY) pulses += 1.0;
+            else substeps += op.n;
+        }
+    const double readout = per_sample * (double)p.n_samples * std::max(n_out, 1);
+    const double other = 80.0 * pulses + 30.0 * substeps;
     if (other > 0) b.work = (int)std::max<int64_t>(1, std::min<int64_t>(b.hard, (int64_t)(readout / other)));
+    b.other_share = readout + other > 0 ? other / (readout + other) : 0.0;
     return b;
+}
+
+int64_t device_slots(const Ctx* ctx, int S, const Program& p) {
+    int32_t slots = 0;
+    for (const Slice& sl : p.slices) slots = std::max(slots, sl.n_cache_slots);
+    const bool mo = S == 1 && p.matrix_only;
+    const size_t dyn = step_dyn_lds_bytes(ctx->cfg.precision, S, (int32_t)(p.rows.size() / 9), slots, mo);
+    return (int64_t)std::max(ctx->n_cu, 1) * step_workgroups_per_cu(ctx->cfg.precision, S, mo, dyn);
 }
 
 // Readout replicas for a launch of n_tiles workgroup tiles: none when the
@@ -244,6 +263,25 @@ int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32
     const int64_t shared = std::min<int64_t>((want + n_tiles - 1) / n_tiles, bound.work);
     const int64_t rule = std::max<int64_t>(1, std::min<int64_t>(bound.hard, std::max(own, shared)));
     return (int)(mode == REPLICAS_DOUBLE ? std::min<int64_t>(bound.hard, 2 * rule) : rule);
+}
+
+ReplicaSplit replica_split(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32_t mode, int64_t slots) {
+    ReplicaSplit r;
+    r.replicas = replicas_for_load(ctx, n_tiles, bound, mode);
+    if (r.replicas > 1 || n_tiles <= std::max(ctx->n_cu, 1) || slots <= 0) return r;
+    if ((ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) || mode == REPLICAS_NONE) return r;
+    // More tiles than CUs: the tiles that fill whole rounds of the device's
+    // workgroup slots run whole, and the rest, which would leave the last
+    // round part-empty, are split over the slots they leave free (at most 8
+    // replicas each).
+    const int64_t whole = n_tiles / slots * slots, rest = n_tiles - whole;
+    if (rest == 0) return r;
+    int64_t R = std::min<int64_t>({(int64_t)bound.hard, slots / rest, 8});
+    if (mode == REPLICAS_DOUBLE) R = std::min<int64_t>(bound.hard, 2 * R);
+    if (R < 2) return r;
+    r.replicas = (int)R;
+    r.n_whole = whole;
+    return r;
 }
 
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
@@ -291,7 +329,10 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->state_bytes = prog.slices.size() > 1
                          ? (size_t)(state_reals_per_spin(prog.n_state_slots) * obj->n_spins * real_bytes)
                          : 0;
-    r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out), r->replica_mode);
+    const ReplicaSplit rs = replica_split(ctx, r->n_blocks, replica_bound(r->prog, r->n_out), r->replica_mode,
+                                          device_slots(ctx, r->S, r->prog));
+    r->n_replicas = rs.replicas;
+    r->n_whole = rs.n_whole;
     return PS_OK;
 }
 
@@ -326,6 +367,7 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
     a.snaps = r.snaps;
     a.n_replicas = r.n_replicas;
     a.n_tiles = r.n_blocks;
+    a.n_whole = r.n_whole;
     for (int d = 0; d < 3; ++d) a.mx_mu[d] = prog.matrix_mu[d];
     a.mx_tau = prog.matrix_tau;
     const Op* ops_dev = reinterpret_cast<const Op*>(b.ops);

@@ -160,6 +160,8 @@ static ps_status tune_request(Ctx* ctx, const ps_object* obj, const ps_sequence*
     std::string err;
     if ((st = compile_sequence(&probe, &pp, &err)) != PS_OK) return fail(st, err);
     plan_slices(&pp, int64_t(1) << 40);        // one slice: the readouts a tile's replicas can share
+    if (ctx->cfg.precision != 64 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT)) mark_matrix_readouts(&pp);
+    assign_shape_slots(&pp, kShapeSlots);
     if (res) res->probe_events = probe.n_events;
 
     // candidates: every spins-per-lane value of the precision with the
@@ -172,9 +174,10 @@ static ps_status tune_request(Ctx* ctx, const ps_object* obj, const ps_sequence*
         if (base_rep == REPLICAS_NONE || obj->n_spins == 0) continue;
         const int64_t tiles = (obj->n_spins + spins_per_block_of(S) - 1) / spins_per_block_of(S);
         const ReplicaBound b = replica_bound(pp, std::max(n_coils, 1));
-        const int rule = replicas_for_load(ctx, tiles, b, REPLICAS_RULE);
+        const int64_t slots = device_slots(ctx, S, pp);
+        const int rule = replica_split(ctx, tiles, b, REPLICAS_RULE, slots).replicas;
         if (rule > 1) cands.push_back(Tiling{S, REPLICAS_NONE, true});
-        if (rule > 1 && replicas_for_load(ctx, tiles, b, REPLICAS_DOUBLE) > rule)
+        if (rule > 1 && replica_split(ctx, tiles, b, REPLICAS_DOUBLE, slots).replicas > rule)
             cands.push_back(Tiling{S, REPLICAS_DOUBLE, true});
     }
     if ((int)cands.size() > PS_TUNE_MAX_CANDIDATES) cands.resize(PS_TUNE_MAX_CANDIDATES);
