@@ -328,6 +328,33 @@ ps_status ps_tile_for(ps_ctx* handle, int64_t n_spins, const ps_sequence* seq, i
     return PS_OK;
 }
 
+ps_status ps_readout_path(ps_ctx* handle, const ps_sequence* seq, int32_t spins_per_lane, int64_t* n_readouts,
+                          int64_t* n_matrix, int32_t* matrix_only) {
+    clear_error();
+    if (!handle || !seq) return fail(PS_E_INVALID_ARG, "ctx or seq is NULL");
+    if (spins_per_lane != 1 && spins_per_lane != 2 && spins_per_lane != 4 && spins_per_lane != 8)
+        return fail(PS_E_INVALID_ARG, "spins_per_lane must be 1, 2, 4 or 8");
+    Ctx* ctx = reinterpret_cast<Ctx*>(handle);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Program p;
+    std::string err;
+    const ps_status st = compile_sequence(seq, &p, &err);
+    if (st != PS_OK) return fail(st, err);
+    plan_slices(&p, int64_t(1) << 40);
+    const bool fp32 = ctx->cfg.precision != 64;
+    if (fp32 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT)) mark_matrix_readouts(&p);
+    int64_t n = 0, m = 0;
+    for (const Op& op : p.ops) {
+        if (op.kind != OP_ADC && op.kind != OP_ADCT) continue;
+        ++n;
+        if (fp32 && spins_per_lane == 1 && (op.flags & OPF_MATRIX)) ++m;
+    }
+    if (n_readouts) *n_readouts = n;
+    if (n_matrix) *n_matrix = m;
+    if (matrix_only) *matrix_only = fp32 && spins_per_lane == 1 && p.matrix_only ? 1 : 0;
+    return PS_OK;
+}
+
 ps_status ps_tune_save(ps_ctx* handle, const char* path) {
     clear_error();
     if (!handle || !path) return fail(PS_E_INVALID_ARG, "ctx or path is NULL");
