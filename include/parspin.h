@@ -472,7 +472,9 @@ ps_status ps_server_stats(ps_ctx *ctx, ps_server_stats_t *out);
  * context (what a request gets when the tiling table has no entry for its
  * class): spins held per lane -- the configured value, else 2 once the
  * object gives every SIMD two waves at 2 spins per lane, else 1 -- and
- * spins per workgroup (4 waves of 64 lanes). */
+ * spins per workgroup (4 waves of 64 lanes).  A request whose FP32 readouts
+ * take the matrix cores (PS_CFG_NO_MATRIX_READOUT) gets 1 whatever its
+ * size; this call, which sees no sequence, gives the size rule. */
 ps_status ps_tile(ps_ctx *ctx, int64_t n_spins, int32_t *spins_per_lane, int64_t *spins_per_block);
 
 /* ---- tiling autotuner -------------------------------------------------

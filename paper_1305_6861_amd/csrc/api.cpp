@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -81,8 +82,29 @@ void HostBuf::release() {
     bytes = 0;
 }
 
-int threshold_spins_per_lane(const Ctx* ctx, int64_t n_spins) {
+// Whether the FP32 matrix-core readout would sum a run of this sequence's
+// readouts: some per-sample step (moment and dwell per sample) shared by two
+// readouts of at least kMatrixMinSamples untabulated samples (the compiler's
+// rule, see mark_matrix_readouts, without compiling the sequence).
+static bool repeated_matrix_readouts(const ps_sequence* seq) {
+    if (!seq || !seq->events) return false;
+    std::vector<std::array<double, 4>> steps;
+    for (int64_t i = 0; i < seq->n_events; ++i) {
+        const ps_event& e = seq->events[i];
+        if (e.n_adc < kMatrixMinSamples || (e.flags & PS_EV_TRAJECTORY)) continue;
+        const double n = (double)e.n_adc;
+        steps.push_back({e.dt / n, e.m[0] / n, e.m[1] / n, e.m[2] / n});
+    }
+    std::sort(steps.begin(), steps.end());
+    return std::adjacent_find(steps.begin(), steps.end()) != steps.end();
+}
+
+int threshold_spins_per_lane(const Ctx* ctx, int64_t n_spins, const ps_sequence* seq) {
     if (ctx->cfg.spins_per_lane > 0) return ctx->cfg.spins_per_lane;
+    // FP32 readouts that take the matrix cores run fastest at one spin per
+    // lane (the matrix-only kernel), whatever the object's size
+    if (ctx->cfg.precision != 64 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT) && repeated_matrix_readouts(seq))
+        return 1;
     // Keep at least ~2 waves per SIMD (2 x 1024 SIMDs) while giving each lane
     // as many spins as possible: more spins per lane amortise the per-sample
     // lane-sum + butterfly reduction.  Readouts run 8 spins per lane from

@@ -119,8 +119,9 @@ struct Ctx {
 constexpr size_t kNoAllocStagingBytes = size_t(8) << 20;
 
 // The fixed threshold rule: 2 spins per lane once the object fills the
-// device twice over at that size, else 1 (or the configured value).
-int threshold_spins_per_lane(const Ctx* ctx, int64_t n_spins);
+// device twice over at that size, else 1 (or the configured value); 1 for
+// an FP32 sequence (when given) whose readouts take the matrix cores.
+int threshold_spins_per_lane(const Ctx* ctx, int64_t n_spins, const ps_sequence* seq = nullptr);
 // Tuner class of a request (seq must be valid; n_coils 0 = one homogeneous coil).
 TuneKey tune_key(const Ctx* ctx, int64_t n_spins, const ps_sequence* seq, int n_coils);
 // The tiling a request gets: the configured spins per lane if set, else the

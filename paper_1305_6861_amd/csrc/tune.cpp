@@ -78,7 +78,7 @@ Tiling choose_tiling(const Ctx* ctx, int64_t n_spins, const ps_sequence* seq, in
         if (rep == REPLICAS_NONE) t.replicas = REPLICAS_NONE;
         return t;
     }
-    return Tiling{threshold_spins_per_lane(ctx, n_spins), rep, false};
+    return Tiling{threshold_spins_per_lane(ctx, n_spins, seq), rep, false};
 }
 
 // Spin-steps a probe may hold: a few ms of the device at the readout rate.
@@ -151,7 +151,7 @@ static ps_status tune_request(Ctx* ctx, const ps_object* obj, const ps_sequence*
     }
     const int n_coils = rx ? rx->n_coils : 0;
     const TuneKey key = tune_key(ctx, obj->n_spins, seq, n_coils);
-    const int rule_S = threshold_spins_per_lane(ctx, obj->n_spins);
+    const int rule_S = threshold_spins_per_lane(ctx, obj->n_spins, seq);
     const int32_t base_rep = (ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) ? REPLICAS_NONE : REPLICAS_RULE;
 
     ps_sequence probe = *seq;

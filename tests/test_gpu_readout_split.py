@@ -63,17 +63,24 @@ def test_tail_split_of_a_large_object(ps):
     """More tiles than the device holds workgroups at once: the tiles of the
     whole rounds run whole and only the rest (which would leave the last
     round part-empty) are split into replicas.  1,000 tiles at one spin per
-    lane (256,000 spins) with 12 readouts of 160 samples, in FP32 and FP64;
-    bitwise equal to the unsplit launch and within the oracle bars."""
+    lane (256,000 spins) with 12 readouts of 160 samples, in FP32 and FP64,
+    in one launch and in five time slices; bitwise equal to the unsplit
+    launch and within the oracle bars."""
     from workloads.phantom import random_spins
     from tests.test_gpu_matrix_readout import cartesian
     obj = random_spins(256000, seed=77, dw_sigma_hz=30.0)
     seq = cartesian(160, 12)
     ref = oracle.simulate(obj, seq)
     for prec, tol in ((32, 1e-5), (64, 1e-12)):
-        res = {}
-        for split in (True, False):
-            with ps.Context(readout_split=split, spins_per_lane=1, precision=prec) as ctx:
-                res[split] = ctx.simulate(obj, seq).cpu().numpy()
-        np.testing.assert_array_equal(res[True], res[False])
-        within(res[True], ref, tol, f"tail split 1000 tiles fp{prec}")
+        # whole, and in five time slices of 400 samples: the split tiles'
+        # replicas then start from the anchors that replica 0 of the
+        # previous slice wrote to the other anchor buffer
+        rows = 1000
+        for part in (0, rows * 2 * (prec // 8) * 400):
+            res = {}
+            for split in (True, False):
+                with ps.Context(readout_split=split, spins_per_lane=1, precision=prec,
+                                max_partial_bytes=part) as ctx:
+                    res[split] = ctx.simulate(obj, seq).cpu().numpy()
+            np.testing.assert_array_equal(res[True], res[False])
+            within(res[True], ref, tol, f"tail split 1000 tiles fp{prec} partial={part}")
