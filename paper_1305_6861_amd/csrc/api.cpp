@@ -260,9 +260,17 @@ ReplicaBound replica_bound(const Program& p, int n_out) {
     const double readout = per_sample * (double)p.n_samples * std::max(n_out, 1);
     const double other = 80.0 * pulses + 30.0 * substeps;
     if (other > 0) b.work = (int)std::max<int64_t>(1, std::min<int64_t>(b.hard, (int64_t)(readout / other)));
+    b.other_share = readout + other > 0 ? other / (readout + other) : 0.0;
     return b;
 }
 
+int64_t device_slots(const Ctx* ctx, int S, const Program& p) {
+    int32_t slots = 0;
+    for (const Slice& sl : p.slices) slots = std::max(slots, sl.n_cache_slots);
+    const bool mo = S == 1 && p.matrix_only;
+    const size_t dyn = step_dyn_lds_bytes(ctx->cfg.precision, S, (int32_t)(p.rows.size() / 9), slots, mo);
+    return (int64_t)std::max(ctx->n_cu, 1) * step_workgroups_per_cu(ctx->cfg.precision, S, mo, dyn);
+}
 
 // Readout replicas for a launch of n_tiles workgroup tiles: none when the
 // tiles alone give every CU a workgroup.  Otherwise replicas that each get
@@ -279,6 +287,24 @@ int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32
     return (int)(mode == REPLICAS_DOUBLE ? std::min<int64_t>(bound.hard, 2 * rule) : rule);
 }
 
+ReplicaSplit replica_split(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32_t mode, int64_t slots) {
+    ReplicaSplit r;
+    r.replicas = replicas_for_load(ctx, n_tiles, bound, mode);
+    if (r.replicas > 1 || n_tiles <= std::max(ctx->n_cu, 1) || slots <= 0) return r;
+    if ((ctx->cfg.flags & PS_CFG_NO_READOUT_SPLIT) || mode == REPLICAS_NONE) return r;
+    // More tiles than CUs: the tiles that fill whole rounds of the device's
+    // workgroup slots run whole, and the rest, which would leave the last
+    // round part-empty, are split over the slots they leave free (at most 8
+    // replicas each).
+    const int64_t whole = n_tiles / slots * slots, rest = n_tiles - whole;
+    if (rest == 0) return r;
+    int64_t R = std::min<int64_t>({(int64_t)bound.hard, slots / rest, 8});
+    if (mode == REPLICAS_DOUBLE) R = std::min<int64_t>(bound.hard, 2 * R);
+    if (R < 2) return r;
+    r.replicas = (int)R;
+    r.n_whole = whole;
+    return r;
+}
 
 ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, const ps_receive* rx,
                       double* signal, int64_t n_samples, void* snaps, int64_t n_snapshots, const Tiling* force,
@@ -325,7 +351,10 @@ ps_status plan_single(Ctx* ctx, const ps_object* obj, const ps_sequence* seq, co
     r->state_bytes = prog.slices.size() > 1
                          ? (size_t)(state_reals_per_spin(prog.n_state_slots) * obj->n_spins * real_bytes)
                          : 0;
-    r->n_replicas = replicas_for_load(ctx, r->n_blocks, replica_bound(r->prog, r->n_out), r->replica_mode);
+    const ReplicaSplit rs = replica_split(ctx, r->n_blocks, replica_bound(r->prog, r->n_out), r->replica_mode,
+                                          device_slots(ctx, r->S, r->prog));
+    r->n_replicas = rs.replicas;
+    r->n_whole = rs.n_whole;
     return PS_OK;
 }
 
@@ -360,6 +389,7 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
     a.snaps = r.snaps;
     a.n_replicas = r.n_replicas;
     a.n_tiles = r.n_blocks;
+    a.n_whole = r.n_whole;
     for (int d = 0; d < 3; ++d) a.mx_mu[d] = prog.matrix_mu[d];
     a.mx_tau = prog.matrix_tau;
     const Op* ops_dev = reinterpret_cast<const Op*>(b.ops);

@@ -1585,12 +1585,23 @@ struct StepOccupancy {
     static constexpr int kWavesPerEU = MO ? 3 : !std::is_same<real, float>::value ? 1 : S <= 2 ? 2 : 1;
 };
 
-// Workgroup b runs tile b % n_tiles as readout replica b / n_tiles.
+// Workgroup b < n_whole runs tile b whole; later workgroups run the tiles
+// from n_whole on, b' = b - n_whole being tile n_whole + b' % (n_tiles -
+// n_whole) as readout replica b' / (n_tiles - n_whole).  The whole tiles
+// come first, so the split ones fill the end of the launch.
 template <typename real, int S, bool MO = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, MO>::kWavesPerEU)))
 void step_kernel(StepArgs a) {
     const int64_t b = blockIdx.x;
-    step_body<real, S, MO>(a, b % a.n_tiles, (int)(b / a.n_tiles), a.n_replicas);
+    int64_t tile = b;
+    int rep = 0, n_rep = 1;
+    if (b >= a.n_whole) {
+        const int64_t bs = b - a.n_whole, nt = a.n_tiles - a.n_whole;
+        tile = a.n_whole + bs % nt;
+        rep = (int)(bs / nt);
+        n_rep = a.n_replicas;
+    }
+    step_body<real, S, MO>(a, tile, rep, n_rep);
 }
 
 // Persistent form: workgroups take (request, tile, readout replica) items
@@ -1761,6 +1772,23 @@ size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_row
     }
 }
 
+int step_workgroups_per_cu(int precision, int spins_per_lane, bool matrix_only, size_t dyn_lds) {
+    int n = 0;
+    hipError_t e;
+    if (precision != 64 && spins_per_lane == 1 && matrix_only)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 1, true>, kBlock, dyn_lds);
+    else if (precision == 64)
+        e = spins_per_lane == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, 1>, kBlock, dyn_lds)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, 2>, kBlock, dyn_lds);
+    else switch (spins_per_lane) {
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 1>, kBlock, dyn_lds); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 2>, kBlock, dyn_lds); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 4>, kBlock, dyn_lds); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 8>, kBlock, dyn_lds); break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
 int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, bool matrix_only) {
     // FP32: keep a workgroup's LDS within half of a CU's 160 KiB so that two
     // workgroups (8 waves, the register-bound occupancy at S = 2) stay
@@ -1795,8 +1823,10 @@ static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t
     StepArgs b = a;
     b.n_tiles = n_blocks;
     if (b.n_replicas < 1) b.n_replicas = 1;
-    hipLaunchKernelGGL((step_kernel<real, S, MO>), dim3((unsigned)(n_blocks * b.n_replicas)), dim3(kBlock), dyn, st,
-                       b);
+    if (b.n_whole < 0 || b.n_whole > n_blocks) return hipErrorInvalidValue;
+    if (b.n_whole == n_blocks) b.n_replicas = 1;
+    const int64_t grid = b.n_whole + (n_blocks - b.n_whole) * b.n_replicas;
+    hipLaunchKernelGGL((step_kernel<real, S, MO>), dim3((unsigned)grid), dim3(kBlock), dyn, st, b);
     return hipGetLastError();
 }
 

@@ -34,8 +34,10 @@ struct StepArgs {
     int64_t coil_stride;     // reals between coils' sample blocks inside a row
     void* snaps;             // device, n_snapshots * 3 * n_spins reals (OP_SNAP targets)
     const double* traj;      // device, trajectory rows (K + k_s, txy + t_s), 4 doubles each
-    int32_t n_replicas;      // readout replicas per tile (>= 1)
+    int32_t n_replicas;      // readout replicas per tile (>= 1) from tile n_whole on
     int64_t n_tiles;         // workgroup tiles of the object (set by launch_step)
+    int64_t n_whole;         // launch_step: tiles 0 .. n_whole - 1 run whole (one replica);
+                             // the batched kernel splits every tile (n_whole = 0)
     double mx_mu[3];         // matrix-only kernel: the per-sample step (mu, tau) that every
     double mx_tau;           // readout of the program shares
 };
@@ -64,8 +66,9 @@ int64_t spins_per_block_of(int spins_per_lane);
 // Partial-sum rows one workgroup writes (one per wave group).
 int64_t rows_per_block_of(int spins_per_lane);
 
-// Launches n_blocks * a.n_replicas workgroups: every tile of the object
-// once per readout replica (replicas split the slice's readouts).
+// Launches a.n_whole + (n_blocks - a.n_whole) * a.n_replicas workgroups:
+// the first n_whole tiles whole, every later tile once per readout replica
+// (replicas split the slice's readouts).
 // matrix_only (a program whose readouts are all marked OPF_MATRIX, none
 // tabulated, and share one per-sample step, given in a.mx_mu / a.mx_tau)
 // selects, at FP32 and one spin per lane, a kernel built without the vector
@@ -78,6 +81,9 @@ hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int
 // matrix-only kernel, see launch_step) and propagator slots.
 size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
                           bool matrix_only = false);
+// Step workgroups resident per CU (occupancy of the kernel the arguments
+// select, with dyn_lds bytes of dynamic LDS).
+int step_workgroups_per_cu(int precision, int spins_per_lane, bool matrix_only, size_t dyn_lds);
 // Propagator slots (at most kShapeSlots) that fit a step workgroup's LDS
 // budget next to n_shape_rows shaped-pulse rows.
 int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, bool matrix_only = false);

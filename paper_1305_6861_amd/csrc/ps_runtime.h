@@ -154,16 +154,31 @@ ps_status validate_receive(const ps_receive* rx, const ps_object* obj);
 struct ReplicaBound {
     int hard = 1;
     int work = 1;
+    double other_share = 0.0;   // estimated share of a tile's work outside its readouts
 };
 ReplicaBound replica_bound(const Program& p, int n_out);
 int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32_t mode = REPLICAS_RULE);
+// A single request's launch: tiles 0 .. n_whole - 1 whole, the rest in
+// `replicas` readout replicas each (replicas_for_load's count with
+// n_whole = 0 when that is above one; else the tiles past the last whole
+// round of slots, the workgroups the device holds at once, split over the
+// slots that round leaves free).
+struct ReplicaSplit {
+    int replicas = 1;
+    int64_t n_whole = 0;
+};
+ReplicaSplit replica_split(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32_t mode, int64_t slots);
+// Workgroups of the step kernel that runs p at S spins per lane resident on
+// the whole device at once.
+int64_t device_slots(const Ctx* ctx, int S, const Program& p);
 
 // One request compiled for a context: program, tiling and buffer sizes.
 struct Single {
     Program prog;
     int S = 1, n_coils = 0, n_out = 1;
     int32_t replica_mode = REPLICAS_RULE;
-    int n_replicas = 1;            // readout replicas per tile
+    int n_replicas = 1;            // readout replicas per tile from tile n_whole on
+    int64_t n_whole = 0;           // tiles that run whole (see ReplicaSplit)
     int64_t n_blocks = 0, n_rows = 0, coil_stride = 0, row_stride = 0;
     bool any_snaps = false;
     ps_object obj{};

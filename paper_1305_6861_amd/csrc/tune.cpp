@@ -174,9 +174,10 @@ static ps_status tune_request(Ctx* ctx, const ps_object* obj, const ps_sequence*
         if (base_rep == REPLICAS_NONE || obj->n_spins == 0) continue;
         const int64_t tiles = (obj->n_spins + spins_per_block_of(S) - 1) / spins_per_block_of(S);
         const ReplicaBound b = replica_bound(pp, std::max(n_coils, 1));
-        const int rule = replicas_for_load(ctx, tiles, b, REPLICAS_RULE);
+        const int64_t slots = device_slots(ctx, S, pp);
+        const int rule = replica_split(ctx, tiles, b, REPLICAS_RULE, slots).replicas;
         if (rule > 1) cands.push_back(Tiling{S, REPLICAS_NONE, true});
-        if (rule > 1 && replicas_for_load(ctx, tiles, b, REPLICAS_DOUBLE) > rule)
+        if (rule > 1 && replica_split(ctx, tiles, b, REPLICAS_DOUBLE, slots).replicas > rule)
             cands.push_back(Tiling{S, REPLICAS_DOUBLE, true});
     }
     if ((int)cands.size() > PS_TUNE_MAX_CANDIDATES) cands.resize(PS_TUNE_MAX_CANDIDATES);

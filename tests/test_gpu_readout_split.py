@@ -59,19 +59,22 @@ def test_split_with_coils_snapshots_and_slices(ps):
     np.testing.assert_array_equal(res[True][1], res[False][1])
 
 
-def test_large_object_whole_and_sliced(ps):
-    """An object of more tiles than CUs (1,000 tiles at one spin per lane,
-    256,000 spins) takes no readout replicas, so the split and unsplit
-    contexts give the same bits; 12 readouts of 160 samples, FP32 and FP64,
-    in one launch and in five time slices (the anchors alternate between
-    the slice state's two buffers), within the oracle bars."""
+def test_tail_split_of_a_large_object(ps):
+    """More tiles than the device holds workgroups at once: the tiles of the
+    whole rounds run whole and only the rest (which would leave the last
+    round part-empty) are split into replicas.  1,000 tiles at one spin per
+    lane (256,000 spins) with 12 readouts of 160 samples, in FP32 and FP64,
+    in one launch and in five time slices; bitwise equal to the unsplit
+    launch and within the oracle bars."""
     from workloads.phantom import random_spins
     from tests.test_gpu_matrix_readout import cartesian
     obj = random_spins(256000, seed=77, dw_sigma_hz=30.0)
     seq = cartesian(160, 12)
     ref = oracle.simulate(obj, seq)
     for prec, tol in ((32, 1e-5), (64, 1e-12)):
-        # whole, and in five time slices of 400 samples
+        # whole, and in five time slices of 400 samples: the split tiles'
+        # replicas then start from the anchors that replica 0 of the
+        # previous slice wrote to the other anchor buffer
         rows = 1000
         for part in (0, rows * 2 * (prec // 8) * 400):
             res = {}
