@@ -430,6 +430,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--spins-per-lane", type=int, default=0,
                     help="0 = the autotuner's choice (or the threshold rule with --no-tune)")
+    ap.add_argument("--no-readout-split", action="store_true",
+                    help="no readout replicas (PS_CFG_NO_READOUT_SPLIT); with --spins-per-lane, pins the "
+                         "tuner's 'none' choice for a profiled run")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner: tiles from the threshold rule")
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "c5", "kt"], default="c3",
@@ -491,7 +494,7 @@ def main():
     dev = ps.to_device(obj)
     cache = not args.no_shape_cache
     ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache,
-                     precision=args.precision)
+                     precision=args.precision, readout_split=not args.no_readout_split)
     fp64 = args.precision == 64
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
     packed = ps.pack_sequence(seq)

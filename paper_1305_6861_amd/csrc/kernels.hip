@@ -755,16 +755,25 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
         s_md[(tb * kWaves + wave) * 64 + lane] =
             make_float4(acc0[0] + acc1[0], acc0[1] + acc1[1], acc0[2] + acc1[2], acc0[3] + acc1[3]);
         __syncthreads();
-        // thread (wave w, lane l): element w of lane l, added over the waves
-        // in wave order; it is component w & 1 of sample
-        // 16 (2 (l >> 4) + (w >> 1)) + (l & 15)
-        const float* md = reinterpret_cast<const float*>(s_md + tb * kWaves * 64);
-        float v = md[lane * 4 + wave];
+        // waves 0 and 1, lane l: elements (2 h, 2 h + 1) of lane l with
+        // h = wave, i.e. (re, im) of sample 16 (2 (l >> 4) + h) + (l & 15),
+        // added over the waves in wave order and stored as one pair, so that
+        // 16 consecutive lanes write 128 contiguous bytes
+        if (wave < 2) {
+            const float2* md = reinterpret_cast<const float2*>(s_md + tb * kWaves * 64);
+            float2 v = md[lane * 2 + wave];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) v += md[(w * 64 + lane) * 4 + wave];
-        const int t = 32 * (lane >> 4) + 16 * (wave >> 1) + (lane & 15);
-        const int smp = tile * kMatrixTile + t;
-        if (smp < n) out[2 * (int64_t)smp + (wave & 1)] = v;
+            for (int w = 1; w < kWaves; ++w) {
+                const float2 u = md[(w * 64 + lane) * 2 + wave];
+                v.x += u.x;
+                v.y += u.y;
+            }
+            const int smp = tile * kMatrixTile + 32 * (lane >> 4) + 16 * wave + (lane & 15);
+            if (smp < n) {
+                out[2 * (int64_t)smp] = v.x;
+                out[2 * (int64_t)smp + 1] = v.y;
+            }
+        }
     }
 }
 
