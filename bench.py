@@ -563,7 +563,7 @@ def main():
     # which kernel and units sum the readouts: FP32 readouts at one spin per
     # lane run on the matrix cores (dense FP32 matrix peak = FP32 vector
     # peak on MI355X, 157.3 TFLOP/s)
-    path = ctx.readout_path(packed, spl)
+    path = ctx.readout_path(obj.n_spins, packed, spl, args.coils)
     kernel = "step_kernel<%s,%d%s>" % ("double" if fp64 else "float", spl, ",matrix-only" if path["matrix_only"] else "")
     roof = {"bound": "mfma" if path["matrix"] > 0 else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,

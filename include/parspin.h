@@ -525,15 +525,19 @@ ps_status ps_tune(ps_ctx *ctx, const ps_object *obj, const ps_sequence *seq, con
  * tiling table (*tuned = 1) or the threshold rule.  Any output may be NULL. */
 ps_status ps_tile_for(ps_ctx *ctx, int64_t n_spins, const ps_sequence *seq, int32_t n_coils,
                       int32_t *spins_per_lane, int32_t *replicas, int32_t *tuned);
-/* How the readouts of this sequence are summed at spins_per_lane (1, 2, 4
- * or 8) on this context: *n_readouts ADC intervals (after cutting at 8,192
- * samples), *n_matrix of them on the matrix cores, and *matrix_only = 1 when
- * that is all of them with one per-sample step, so that the kernel built
- * without the vector readout runs the request (see
- * PS_CFG_NO_MATRIX_READOUT).  Any output may be NULL.  Measurement support,
- * not part of the simulation. */
-ps_status ps_readout_path(ps_ctx *ctx, const ps_sequence *seq, int32_t spins_per_lane, int64_t *n_readouts,
-                          int64_t *n_matrix, int32_t *matrix_only);
+/* How the readouts of a request (n_spins spins, this sequence, n_coils coils
+ * with 0 for one homogeneous coil) are summed at spins_per_lane (1, 2, 4 or
+ * 8) on this context, planned as ps_simulate_rx plans it: *n_readouts ADC
+ * intervals (after time slicing and cutting at 8,192 samples), *n_matrix of
+ * them on the matrix cores, *matrix_only = 1 when that is all of them with
+ * one per-sample step, so that the kernel built without the vector readout
+ * runs the request (see PS_CFG_NO_MATRIX_READOUT), and *n_slices time
+ * slices.  Any output may be NULL.  PS_E_INVALID_ARG for an invalid
+ * sequence, n_spins < 0 or n_coils < 0.  Host only
+ * (no device work); measurement support, not part of the simulation. */
+ps_status ps_readout_path(ps_ctx *ctx, int64_t n_spins, const ps_sequence *seq, int32_t n_coils,
+                          int32_t spins_per_lane, int64_t *n_readouts, int64_t *n_matrix, int32_t *matrix_only,
+                          int64_t *n_slices);
 /* Write the tiling table to a text file, headed by the device model, its
  * compute-unit count and a hash of this library's sources. */
 ps_status ps_tune_save(ps_ctx *ctx, const char *path);

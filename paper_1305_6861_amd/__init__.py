@@ -211,15 +211,18 @@ class Context:
         return {"spins_per_lane": int(spl.value), "replicas": _b.REPLICA_MODES[int(rep.value)],
                 "tuned": bool(tuned.value)}
 
-    def readout_path(self, seq, spins_per_lane: int) -> dict:
-        """How the sequence's readouts are summed at this spins-per-lane
-        (ps_readout_path): readouts in all, on the matrix cores, and whether
-        the matrix-only kernel runs the request."""
+    def readout_path(self, n_spins: int, seq, spins_per_lane: int, n_coils: int = 0) -> dict:
+        """How a request's readouts are summed at this spins-per-lane, planned
+        as a simulate call plans it (ps_readout_path): readouts in all, on the
+        matrix cores, whether the matrix-only kernel runs the request, and
+        its time slices."""
         ps = pack_sequence(seq)
-        n, m, mo = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
-        _b.check(_b.lib.ps_readout_path(self._h, ctypes.byref(ps.struct), int(spins_per_lane), ctypes.byref(n),
-                                        ctypes.byref(m), ctypes.byref(mo)))
-        return {"readouts": int(n.value), "matrix": int(m.value), "matrix_only": bool(mo.value)}
+        n, m, mo, sl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _b.check(_b.lib.ps_readout_path(self._h, int(n_spins), ctypes.byref(ps.struct), int(n_coils),
+                                        int(spins_per_lane), ctypes.byref(n), ctypes.byref(m), ctypes.byref(mo),
+                                        ctypes.byref(sl)))
+        return {"readouts": int(n.value), "matrix": int(m.value), "matrix_only": bool(mo.value),
+                "slices": int(sl.value)}
 
     def tune(self, obj, seq, coils=None, force: bool = False) -> dict:
         """Time the candidate tilings of the request's class on the device and

@@ -166,9 +166,9 @@ SIGNATURES = {
     "ps_plan_destroy": (None, [ctypes.c_void_p]),
     "ps_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_object), ctypes.POINTER(ps_sequence),
                                ctypes.POINTER(ps_receive), ctypes.c_uint32, ctypes.POINTER(ps_tune_result)]),
-    "ps_readout_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ps_sequence), ctypes.c_int32,
-                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.POINTER(ctypes.c_int32)]),
+    "ps_readout_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ps_sequence), ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "ps_tile_for": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ps_sequence), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]),

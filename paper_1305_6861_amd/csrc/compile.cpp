@@ -260,26 +260,38 @@ void plan_slices(Program* p, int64_t max_samples) {
         cur.op_begin = (int64_t)ops.size();
         cur.sample_begin = sample;
     };
+    // samples [done, done + take) of readout op0 as one or more ops
+    auto emit = [&](const Op& op0, int64_t done, int64_t take) {
+        // runs of a Cartesian readout: near-equal lengths of at most kAdcRun
+        const int64_t runs = op0.kind == OP_ADC ? (take + kAdcRun - 1) / kAdcRun : 1;
+        for (int64_t r = 0; r < runs; ++r) {
+            const int64_t b = take * r / runs, e = take * (r + 1) / runs;
+            Op op = op0;
+            if (op0.kind == OP_ADCT) {
+                op.u.tab.row = op0.u.tab.row + (uint64_t)(done + b);
+            } else {
+                for (int d = 0; d < 3; ++d) op.k[d] = op0.k[d] + (double)(done + b) * op0.u.adc.mu[d];
+                op.txy = op0.txy + (double)(done + b) * op0.u.adc.tau;
+            }
+            op.n = (uint32_t)(e - b);
+            op.aux = (uint32_t)(sample - cur.sample_begin);
+            ops.push_back(op);
+            sample += e - b;
+        }
+    };
     for (const Op& op0 : p->ops) {
         if (op0.kind != OP_ADC && op0.kind != OP_ADCT) { ops.push_back(op0); continue; }
-        int64_t done = 0;
         const int64_t n = op0.n;
+        const int64_t used = sample - cur.sample_begin;
+        // a readout that fits a slice of its own starts one rather than
+        // being cut at the slice boundary
+        if (n <= max_samples && used + n > max_samples && used > 0) close_slice();
+        int64_t done = 0;
         while (done < n) {
             int64_t room = max_samples - (sample - cur.sample_begin);
             if (room <= 0) { close_slice(); room = max_samples; }
-            int64_t take = std::min<int64_t>(room, n - done);
-            if (op0.kind == OP_ADC) take = std::min<int64_t>(take, kAdcRun);
-            Op op = op0;
-            if (op0.kind == OP_ADCT) {
-                op.u.tab.row = op0.u.tab.row + (uint64_t)done;
-            } else {
-                for (int d = 0; d < 3; ++d) op.k[d] = op0.k[d] + (double)done * op0.u.adc.mu[d];
-                op.txy = op0.txy + (double)done * op0.u.adc.tau;
-            }
-            op.n = (uint32_t)take;
-            op.aux = (uint32_t)(sample - cur.sample_begin);
-            ops.push_back(op);
-            sample += take;
+            const int64_t take = std::min<int64_t>(room, n - done);
+            emit(op0, done, take);
             done += take;
         }
     }

@@ -46,13 +46,16 @@ void rf_delta(double alpha, double phi, double d[9]);
 // without, the flag is only counted.
 ps_status compile_sequence(const ps_sequence* seq, Program* out, std::string* err, bool snapshots = false);
 
-// Cut the program into time slices of at most max_samples samples each
-// (ADC operations longer than that are split exactly), setting every ADC
-// op's offset inside its slice.  max_samples >= 1.  A Cartesian readout is
-// also cut into runs of at most kAdcRun samples: each run starts from its
-// own FP64 phase, which bounds the FP32 recurrence a readout accumulates
-// (its anchor advances one multiply per wave group's 32 G samples, and the
-// rounding of that factor adds up linearly along the run).
+// Cut the program into time slices of at most max_samples samples each,
+// setting every ADC op's offset inside its slice.  max_samples >= 1.  A
+// readout that does not fit the rest of a slice starts the next one when it
+// fits a slice of its own (readouts stay whole, so each keeps its readout
+// path); only readouts longer than max_samples are split, exactly.  A
+// Cartesian readout is also cut into runs of near-equal length, at most
+// kAdcRun samples: each run starts from its own FP64 phase, which bounds
+// the FP32 recurrence a readout accumulates (its anchor advances one
+// multiply per wave group's 32 G samples, and the rounding of that factor
+// adds up linearly along the run).
 constexpr int64_t kAdcRun = 8192;
 void plan_slices(Program* p, int64_t max_samples);
 

@@ -328,21 +328,24 @@ ps_status ps_tile_for(ps_ctx* handle, int64_t n_spins, const ps_sequence* seq, i
     return PS_OK;
 }
 
-ps_status ps_readout_path(ps_ctx* handle, const ps_sequence* seq, int32_t spins_per_lane, int64_t* n_readouts,
-                          int64_t* n_matrix, int32_t* matrix_only) {
+ps_status ps_readout_path(ps_ctx* handle, int64_t n_spins, const ps_sequence* seq, int32_t n_coils,
+                          int32_t spins_per_lane, int64_t* n_readouts, int64_t* n_matrix, int32_t* matrix_only,
+                          int64_t* n_slices) {
     clear_error();
     if (!handle || !seq) return fail(PS_E_INVALID_ARG, "ctx or seq is NULL");
+    if (n_spins < 0) return fail(PS_E_INVALID_ARG, "n_spins < 0");
+    if (n_coils < 0) return fail(PS_E_INVALID_ARG, "n_coils < 0");
     if (spins_per_lane != 1 && spins_per_lane != 2 && spins_per_lane != 4 && spins_per_lane != 8)
         return fail(PS_E_INVALID_ARG, "spins_per_lane must be 1, 2, 4 or 8");
     Ctx* ctx = reinterpret_cast<Ctx*>(handle);
     std::lock_guard<std::mutex> lk(ctx->mu);
+    // the plan ps_simulate_rx makes for the request at this tiling
+    const int64_t spb = spins_per_block_of(spins_per_lane);
+    const int64_t n_rows = (n_spins + spb - 1) / spb * rows_per_block_of(spins_per_lane);
     Program p;
-    std::string err;
-    const ps_status st = compile_sequence(seq, &p, &err);
-    if (st != PS_OK) return fail(st, err);
-    plan_slices(&p, int64_t(1) << 40);
+    const ps_status st = prepare(ctx, seq, n_rows, spins_per_lane, &p, n_coils);
+    if (st != PS_OK) return st;
     const bool fp32 = ctx->cfg.precision != 64;
-    if (fp32 && !(ctx->cfg.flags & PS_CFG_NO_MATRIX_READOUT)) mark_matrix_readouts(&p);
     int64_t n = 0, m = 0;
     for (const Op& op : p.ops) {
         if (op.kind != OP_ADC && op.kind != OP_ADCT) continue;
@@ -352,6 +355,7 @@ ps_status ps_readout_path(ps_ctx* handle, const ps_sequence* seq, int32_t spins_
     if (n_readouts) *n_readouts = n;
     if (n_matrix) *n_matrix = m;
     if (matrix_only) *matrix_only = fp32 && spins_per_lane == 1 && p.matrix_only ? 1 : 0;
+    if (n_slices) *n_slices = (int64_t)p.slices.size();
     return PS_OK;
 }
 
