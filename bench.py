@@ -50,12 +50,18 @@ def bench_c4(args):
     devs = [ps.to_device(o) for o, _ in reqs]
     packs = [ps.pack_sequence(s) for _, s in reqs]
     spin_steps = float(sum(o.n_spins * s.n_steps_per_spin for o, s in reqs))
-    rule_ctx = ps.Context()                 # tilings of the threshold rule
-    ctx = ps.Context()
+    rule_ctx = ps.Context(**CTX_KW)         # tilings of the threshold rule
+    ctx = ps.Context(**CTX_KW)
     tuned = 0
+    classes = []
     if not args.no_tune:                    # one tuner run per request class
         t_tune = time.perf_counter()
-        tuned = sum(0 if ctx.tune(d, p)["from_table"] else 1 for d, p in zip(devs, packs))
+        for d, p in zip(devs, packs):
+            r = ctx.tune(d, p)
+            if not r["from_table"]:
+                classes.append({"n_spins": int(d["x"].shape[0]), "spins_per_lane": r["spins_per_lane"],
+                                "replicas": r["replicas"], "best_ms": r["best_ms"], "rule_ms": r["rule_ms"]})
+        tuned = len(classes)
         t_tune = time.perf_counter() - t_tune
     outs = [torch.empty(2 * s.n_samples, dtype=torch.float64, device="cuda") for _, s in reqs]
 
@@ -85,11 +91,11 @@ def bench_c4(args):
            "data": "synthetic",
            "config": {"workload": "c4: 64 requests, 2-D N^2 (N log-uniform 16..256), GRE or SE, "
                                   "U{32..256} phase encodes x N samples, per-request seeds",
-                      "spin_steps": spin_steps},
+                      "spin_steps": spin_steps, "matrix_readout": CTX_KW.get("matrix_readout", True)},
            "one_per_launch_ms": res["one_per_launch"] * 1e3,
            "speedup_vs_one_per_launch": res["one_per_launch"] / res["batched"],
            "tiling": {"source": "autotuner" if not args.no_tune else "threshold rule",
-                      "classes_tuned": tuned, "tuning_s": t_tune if not args.no_tune else 0.0,
+                      "classes_tuned": tuned, "classes": classes, "tuning_s": t_tune if not args.no_tune else 0.0,
                       "threshold_rule_batched_ms": res["rule_batched"] * 1e3,
                       "threshold_rule_one_per_launch_ms": res["rule_one_per_launch"] * 1e3},
            "roofline": None, "cpu_baseline": None}
@@ -120,7 +126,7 @@ def bench_kt(args):
     dev = ps.to_device(obj)
     packed = ps.pack_sequence(seq)
     n_samples, n_steps = packed.count()
-    ctx = ps.Context()
+    ctx = ps.Context(**CTX_KW)
 
     def timed(fn):
         for _ in range(args.warmup):
@@ -192,7 +198,7 @@ def c5_replay(n_requests: int, serve_graphs: bool = True, rate_hz: float = 50.0,
         return done, time.perf_counter() - t0
 
     # served
-    ctx = ps.Context(serve_graphs=serve_graphs)
+    ctx = ps.Context(serve_graphs=serve_graphs, **CTX_KW)
     def s_submit(i, t):
         return (t, ctx.submit(devs[i], packs[i]))
     kernel_s, queue_s = [], []
@@ -211,7 +217,7 @@ def c5_replay(n_requests: int, serve_graphs: bool = True, rate_hz: float = 50.0,
     ctx.close()
     # FIFO one launch per request: a worker thread runs requests in arrival order
     import queue, threading
-    ctx2 = ps.Context()
+    ctx2 = ps.Context(**CTX_KW)
     q = queue.Queue()
     lat_f = np.zeros(len(reqs))
     stream = torch.cuda.Stream()
@@ -247,7 +253,7 @@ def c5_replay(n_requests: int, serve_graphs: bool = True, rate_hz: float = 50.0,
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"c5: Poisson stream of {len(reqs)} requests at {rate_hz:g}/s, "
                                   f"{int(is3d.sum())} of them 3-D 2x64^3 sinc GRE, the rest c4-type",
-                      "spin_steps": spin_steps},
+                      "spin_steps": spin_steps, "matrix_readout": CTX_KW.get("matrix_readout", True)},
            "served": {"wall_s": wall_s, "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
                       "p50_2d_ms": pct(lat_s[~is3d], 50), "p99_2d_ms": pct(lat_s[~is3d], 99),
                       "p50_3d_ms": pct(lat_s[is3d], 50) if is3d.any() else None,
@@ -261,6 +267,9 @@ def c5_replay(n_requests: int, serve_graphs: bool = True, rate_hz: float = 50.0,
            "roofline": None, "cpu_baseline": None}
     return rec
 
+
+# keyword arguments of every context the run creates (--no-matrix-readout)
+CTX_KW = {}
 
 WORKLOADS = {
     "c2": ("c2: 2-D 256x256 grid, 4 jittered isochromats/voxel (262,144 spins), "
@@ -456,6 +465,8 @@ def main():
                     help="time replays of a compiled plan (HIP graph: no host compile or upload per step)")
     ap.add_argument("--coils", type=int, default=0,
                     help="receive with this many loop coils on a ring around the object (0: one homogeneous coil)")
+    ap.add_argument("--no-matrix-readout", action="store_true",
+                    help="sum every readout with the vector recurrence (PS_CFG_NO_MATRIX_READOUT), for comparison")
     ap.add_argument("--no-shape-cache", action="store_true",
                     help="step recurring shaped pulses sub-step by sub-step (default: propagator cache)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -466,6 +477,8 @@ def main():
     ap.add_argument("--valu-calibration", action="store_true",
                     help="instead of the workload, measure the attainable vector FMA rate (FP32 and FP64)")
     args = ap.parse_args()
+    if args.no_matrix_readout:
+        CTX_KW["matrix_readout"] = False
     if args.copy_calibration:
         copy_calibration()
         return
@@ -493,7 +506,7 @@ def main():
     obj, seq = load_workload(args.workload)
     dev = ps.to_device(obj)
     cache = not args.no_shape_cache
-    ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache,
+    ctx = ps.Context(kernel_timing=True, spins_per_lane=args.spins_per_lane, shape_cache=cache, **CTX_KW,
                      precision=args.precision, readout_split=not args.no_readout_split)
     fp64 = args.precision == 64
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
@@ -564,7 +577,10 @@ def main():
     # lane run on the matrix cores (dense FP32 matrix peak = FP32 vector
     # peak on MI355X, 157.3 TFLOP/s)
     path = ctx.readout_path(obj.n_spins, packed, spl, args.coils)
-    kernel = "step_kernel<%s,%d%s>" % ("double" if fp64 else "float", spl, ",matrix-only" if path["matrix_only"] else "")
+    variant = ""
+    if not fp64 and spl == 1:
+        variant = ",matrix-only" if path["matrix_only"] else ",vector-only" if path["matrix"] == 0 else ""
+    kernel = "step_kernel<%s,%d%s>" % ("double" if fp64 else "float", spl, variant)
     roof = {"bound": "mfma" if path["matrix"] > 0 else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": (traffic_from_profiles(args.workload, spl) if args.coils == 0 and not fp64 else None),
@@ -598,6 +614,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "n_spins": obj.n_spins, "n_steps_per_spin": n_steps,
                       "n_samples": n_samples, "spins_per_lane": spl, "tiling": tiling,
+                      "matrix_readout": CTX_KW.get("matrix_readout", True),
                       "precision": "fp64 throughout" if fp64 else "fp32 stepping, fp64 phases and cross-block sums",
                       "shape_cache": cache,
                       "receive_coils": args.coils or "one homogeneous coil",

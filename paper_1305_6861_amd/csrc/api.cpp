@@ -140,7 +140,8 @@ ps_status validate_object(const ps_object* obj) {
 
 int shape_cache_slots(const Ctx* ctx, int S, const Program& prog) {
     if (ctx->cfg.flags & PS_CFG_NO_SHAPE_CACHE) return 0;
-    return shape_cache_slots_fitting(ctx->cfg.precision, S, (int32_t)(prog.rows.size() / 9), prog.matrix_only);
+    return shape_cache_slots_fitting(ctx->cfg.precision, S, (int32_t)(prog.rows.size() / 9),
+                                     step_variant(ctx->cfg.precision, S, prog.matrix_only, prog.any_matrix));
 }
 
 // Compile + slice a request for a given number of partial-sum rows, spins
@@ -267,9 +268,9 @@ ReplicaBound replica_bound(const Program& p, int n_out) {
 int64_t device_slots(const Ctx* ctx, int S, const Program& p) {
     int32_t slots = 0;
     for (const Slice& sl : p.slices) slots = std::max(slots, sl.n_cache_slots);
-    const bool mo = S == 1 && p.matrix_only;
-    const size_t dyn = step_dyn_lds_bytes(ctx->cfg.precision, S, (int32_t)(p.rows.size() / 9), slots, mo);
-    return (int64_t)std::max(ctx->n_cu, 1) * step_workgroups_per_cu(ctx->cfg.precision, S, mo, dyn);
+    const int v = step_variant(ctx->cfg.precision, S, p.matrix_only, p.any_matrix);
+    const size_t dyn = step_dyn_lds_bytes(ctx->cfg.precision, S, (int32_t)(p.rows.size() / 9), slots, v);
+    return (int64_t)std::max(ctx->n_cu, 1) * step_workgroups_per_cu(ctx->cfg.precision, S, v, dyn);
 }
 
 // Readout replicas for a launch of n_tiles workgroup tiles: none when the
@@ -409,7 +410,8 @@ ps_status enqueue_single(const Ctx* ctx, const Single& r, const SingleBuffers& b
             if (!t0 || !t1 || !t2) return fail(PS_E_DEVICE, "timing event creation failed");
             hipEventRecord(t0, stream);
         }
-        if ((e = launch_step(a, precision, r.S, r.n_blocks, stream, prog.matrix_only)) != hipSuccess)
+        if ((e = launch_step(a, precision, r.S, r.n_blocks, stream,
+                             step_variant(precision, r.S, prog.matrix_only, prog.any_matrix))) != hipSuccess)
             return hip_fail(e, "step kernel launch");
         if (timing_ctx) hipEventRecord(t1, stream);
         for (int c = 0; c < r.n_out && sl.n_samples > 0; ++c) {

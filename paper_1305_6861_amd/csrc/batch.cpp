@@ -186,12 +186,15 @@ ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::
     rounds.assign(max_rounds, RoundImage());
     for (size_t k = 0; k < max_rounds; ++k) {
         RoundImage& R = rounds[k];
-        // one launch per kernel: spins per lane, and at one spin per lane
-        // whether the request's readouts all take the matrix cores
-        std::map<std::pair<int, bool>, std::vector<size_t>> by_S;
+        // one launch per kernel: spins per lane, and the kernel variant
+        // (step_variant) at one spin per lane
+        std::map<std::pair<int, int>, std::vector<size_t>> by_S;
         for (size_t i = 0; i < plans.size(); ++i)
-            if (k < n_slices_this_call[i] && plans[i]->obj.n_spins > 0)
-                by_S[{plans[i]->S, plans[i]->S == 1 && plans[i]->prog.matrix_only}].push_back(i);
+            if (k < n_slices_this_call[i] && plans[i]->obj.n_spins > 0) {
+                const Program& g = plans[i]->prog;
+                by_S[{plans[i]->S, step_variant(ctx->cfg.precision, plans[i]->S, g.matrix_only, g.any_matrix)}]
+                    .push_back(i);
+            }
         for (auto& kv : by_S) {
             // Longest tiles first: workgroups take items in record order, so
             // the requests whose tiles take longest start first and short
@@ -203,7 +206,7 @@ ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::
                              [&](size_t a, size_t b) { return cost[a] > cost[b]; });
             RoundImage::Class c;
             c.S = kv.first.first;
-            c.matrix_only = kv.first.second;
+            c.variant = kv.first.second;
             c.n_req = (int32_t)kv.second.size();
             c.items_off = reserve_bytes(sizeof(BatchItem) * kv.second.size());
             c.counter_off = reserve_bytes(sizeof(unsigned long long));
@@ -222,7 +225,7 @@ ps_status build_rounds(const Ctx* ctx, std::vector<ReqPlan*>& plans, const std::
                 it.n_items = p->n_blocks * R;
                 total += it.n_items;
                 dyn = std::max(dyn, step_dyn_lds_bytes(ctx->cfg.precision, c.S, it.args.n_shape_rows,
-                                                       it.args.n_cache_slots, c.matrix_only));
+                                                       it.args.n_cache_slots, c.variant));
                 std::memcpy(img.data() + c.items_off + q * sizeof(BatchItem), &it, sizeof(it));
             }
             c.total = total;
@@ -270,7 +273,7 @@ ps_status round_nodes(const Ctx* ctx, const RoundImage& R, unsigned char* dev, s
     for (const RoundImage::Class& c : R.classes) {
         const hipError_t e = batch_step_nodes(reinterpret_cast<const BatchItem*>(dev + c.items_off), c.n_req,
                                               c.total, reinterpret_cast<unsigned long long*>(dev + c.counter_off),
-                                              c.dyn_lds, ctx->cfg.precision, c.S, ctx->n_cu, nodes, c.matrix_only);
+                                              c.dyn_lds, ctx->cfg.precision, c.S, ctx->n_cu, nodes, c.variant);
         if (e != hipSuccess) return hip_fail(e, "batch step node");
     }
     if (R.n_fin > 0) {

@@ -53,9 +53,9 @@ ps_status upload_tables_contiguous(std::vector<ReqPlan*>& plans, void* dev, Host
 // per spins-per-lane class its request records and queue counter (zero),
 // then the round's finalize records.
 struct RoundImage {
-    struct Class {                      // one spins-per-lane class
+    struct Class {                      // one kernel: spins per lane and variant
         int S;
-        bool matrix_only;               // its requests' programs all are (Program::matrix_only)
+        int variant;                    // step-kernel variant of its requests (step_variant)
         size_t items_off;               // offset of its BatchItem array in the image
         size_t counter_off;             // offset of its queue counter
         int32_t n_req;

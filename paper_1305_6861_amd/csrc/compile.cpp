@@ -394,6 +394,8 @@ void mark_matrix_readouts(Program* p) {
         const bool next = a + 1 < adc.size() && same_step((*ops)[adc[a + 1]], op);
         if (prev || next) op.flags |= OPF_MATRIX;
     }
+    p->any_matrix = false;
+    for (size_t a : adc) p->any_matrix = p->any_matrix || ((*ops)[a].flags & OPF_MATRIX);
     p->matrix_only = true;
     const Op* first = nullptr;
     for (const Op& op : *ops) {

@@ -28,6 +28,7 @@ struct Program {
     int64_t n_rf = 0, n_shape_substeps = 0, n_adc_ops = 0;
     int64_t n_snapshots = 0;           // events flagged PS_EV_SNAPSHOT
     int32_t n_state_slots = 0;         // propagator slots kept in the slice state between slices
+    bool any_matrix = false;           // some readout marked OPF_MATRIX
     bool matrix_only = false;          // every readout marked OPF_MATRIX, none tabulated (OP_ADCT),
     double matrix_mu[3] = {0, 0, 0};   // and all with this per-sample step (mu, tau)
     double matrix_tau = 0;
@@ -76,8 +77,9 @@ void narrow_rotations(std::vector<Op>* ops);
 // per-sample step (mu, tau) equals that of the readout before or after them:
 // the matrix-core path builds per-spin tables for a step once and keeps them
 // while the step stays the same, so it pays off for runs of such readouts.
-// Sets p->matrix_only (and matrix_mu / matrix_tau) when that covers every
-// readout, none is tabulated and all share one step.
+// Sets p->any_matrix when it flags one, and p->matrix_only (and matrix_mu /
+// matrix_tau) when that covers every readout, none is tabulated and all
+// share one step.
 void mark_matrix_readouts(Program* p);
 
 }  // namespace ps

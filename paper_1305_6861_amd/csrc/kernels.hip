@@ -512,19 +512,19 @@ __device__ __forceinline__ void step_delta(double c, double tau, double r2, real
 }
 
 // LDS of a step workgroup outside the dynamic part (s_ops, s_x below).
-template <typename real, int S>
+template <typename real, int S, int VAR = STEP_GENERAL>
 struct MatrixReadout {
-    static constexpr bool on = std::is_same<real, float>::value && S == 1;
+    static constexpr bool on = std::is_same<real, float>::value && S == 1 && VAR != STEP_VECTOR_ONLY;
     static constexpr int LW = on ? kWaves : 1;   // LDS extents (1 when off)
 };
 
-template <typename real, int S>
+template <typename real, int S, int VAR = STEP_GENERAL>
 constexpr size_t static_lds_bytes() {
     constexpr int G = ReadoutShare<S>::G;
     constexpr int NF = StepFactors<real, S>::NF;
     // the matrix-core arrays exist only where that readout does (the
     // compiler drops the placeholders of the other kernels)
-    constexpr size_t matrix = MatrixReadout<real, S>::on
+    constexpr size_t matrix = MatrixReadout<real, S, VAR>::on
                                   ? sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64
                                   : 0;
     return sizeof(Op) * kOpChunk + sizeof(real) * 2 * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 64 * 2 +
@@ -779,14 +779,17 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
 
 // One workgroup tile of one request: spins [blk * 256 S, (blk + 1) * 256 S)
 // through the slice's operations, partial sums into the tile's rows.
-// MO: the matrix-only kernel (FP32, S = 1) of programs whose readouts are all
-// marked OPF_MATRIX, none tabulated, all with the step (a.mx_mu, a.mx_tau):
-// it is built without the vector and trajectory readouts and builds the
-// tables once, before the operations, so that they are loop-invariant and
-// keep their registers (tables rebuilt inside the loop make the register
-// allocator move them at every readout).
-template <typename real, int S, bool MO = false>
+// VAR: the kernel variant (StepVariant).  The matrix-only kernel (MO: FP32,
+// S = 1) runs programs whose readouts are all marked OPF_MATRIX, none
+// tabulated, all with the step (a.mx_mu, a.mx_tau): it is built without the
+// vector and trajectory readouts and builds the tables once, before the
+// operations, so that they are loop-invariant and keep their registers
+// (tables rebuilt inside the loop make the register allocator move them at
+// every readout).  The vector-only kernel (FP32, S = 1) is built without
+// the matrix-core readout and sums every readout with the vector path.
+template <typename real, int S, int VAR = STEP_GENERAL>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, const int rep, const int n_rep) {
+    constexpr bool MO = VAR == STEP_MATRIX_ONLY;
     constexpr int G = ReadoutShare<S>::G;
     constexpr int R = G * S;                 // spins per lane inside readouts
     using SF = StepFactors<real, S>;
@@ -805,9 +808,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     __shared__ real s_red[G > 1 ? kWaves : 1][64];   // chunk sums of waves sharing a chunk
     // matrix-core readout: each wave's A-operand tile, and the waves'
     // 16 x 16 results of a tile, in two buffers used by alternate tiles
-    constexpr bool kMatrix = MatrixReadout<real, S>::on;
+    constexpr bool kMatrix = MatrixReadout<real, S, VAR>::on;
     static_assert(!MO || kMatrix, "the matrix-only kernel is FP32 at one spin per lane");
-    constexpr int LW = MatrixReadout<real, S>::LW;
+    constexpr int LW = MatrixReadout<real, S, VAR>::LW;
     constexpr int LR = kMatrix ? kMatrixARows * 32 : 1;
     __shared__ __align__(16) float s_ta[LW][LR];
     __shared__ __align__(16) float4 s_md[2][LW][64];
@@ -1589,17 +1592,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
 // transcendental operations) and three in the matrix-only kernel (its
 // spills are on cold paths: the prologue, the table build and the
 // shaped-pulse fill); else whatever the code needs.
-template <typename real, int S, bool MO = false>
+template <typename real, int S, int VAR = STEP_GENERAL>
 struct StepOccupancy {
-    static constexpr int kWavesPerEU = MO ? 3 : !std::is_same<real, float>::value ? 1 : S <= 2 ? 2 : 1;
+    static constexpr int kWavesPerEU = !std::is_same<real, float>::value ? 1
+                                       : S == 1 && VAR != STEP_GENERAL ? 3
+                                       : S <= 2 ? 2 : 1;
 };
 
 // Workgroup b < n_whole runs tile b whole; later workgroups run the tiles
 // from n_whole on, b' = b - n_whole being tile n_whole + b' % (n_tiles -
 // n_whole) as readout replica b' / (n_tiles - n_whole).  The whole tiles
 // come first, so the split ones fill the end of the launch.
-template <typename real, int S, bool MO = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, MO>::kWavesPerEU)))
+template <typename real, int S, int VAR = STEP_GENERAL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, VAR>::kWavesPerEU)))
 void step_kernel(StepArgs a) {
     const int64_t b = blockIdx.x;
     int64_t tile = b;
@@ -1610,7 +1615,7 @@ void step_kernel(StepArgs a) {
         rep = (int)(bs / nt);
         n_rep = a.n_replicas;
     }
-    step_body<real, S, MO>(a, tile, rep, n_rep);
+    step_body<real, S, VAR>(a, tile, rep, n_rep);
 }
 
 // Persistent form: workgroups take (request, tile, readout replica) items
@@ -1619,8 +1624,8 @@ void step_kernel(StepArgs a) {
 // request's items being its tiles times its replicas, replica-major).  Every
 // item writes only its own rows and samples, so which workgroup runs it
 // never changes a result.
-template <typename real, int S, bool MO = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, MO>::kWavesPerEU)))
+template <typename real, int S, int VAR = STEP_GENERAL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepOccupancy<real, S, VAR>::kWavesPerEU)))
 void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_t total,
                        unsigned long long* counter) {
     __shared__ unsigned long long s_item;
@@ -1637,7 +1642,7 @@ void batch_step_kernel(const BatchItem* __restrict__ reqs, int32_t n_req, int64_
         }
         const StepArgs a = reqs[lo].args;
         const int64_t local = item - reqs[lo].item_begin;   // replica-major over the tiles
-        step_body<real, S, MO>(a, local % a.n_tiles, (int)(local / a.n_tiles), a.n_replicas);
+        step_body<real, S, VAR>(a, local % a.n_tiles, (int)(local / a.n_tiles), a.n_replicas);
     }
 }
 
@@ -1754,9 +1759,9 @@ __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <typename real, int S, bool MO = false>
+template <typename real, int S, int VAR = STEP_GENERAL>
 static size_t dyn_lds_t(int32_t n_shape_rows, int32_t n_cache_slots) {
-    return (MO ? 0 : (size_t)n_shape_rows * 9 * sizeof(double)) +
+    return (VAR == STEP_MATRIX_ONLY ? 0 : (size_t)n_shape_rows * 9 * sizeof(double)) +
            (size_t)n_cache_slots * kShapeCacheReals * S * kBlock * sizeof(real);
 }
 
@@ -1767,38 +1772,59 @@ constexpr size_t matrix_only_static_lds_bytes() {
     return sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64;
 }
 
-size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
-                          bool matrix_only) {
-    if (precision != 64 && spins_per_lane == 1 && matrix_only)
-        return dyn_lds_t<float, 1, true>(n_shape_rows, n_cache_slots);
-    if (precision == 64) return spins_per_lane == 1 ? dyn_lds_t<double, 1>(n_shape_rows, n_cache_slots)
-                                                    : dyn_lds_t<double, 2>(n_shape_rows, n_cache_slots);
+// Calls f(real_tag, S_tag, V_tag) for the kernel instance the arguments
+// select; returns false for a combination that has none.
+template <typename F>
+static bool dispatch_step(int precision, int spins_per_lane, int variant, F&& f) {
+    using std::integral_constant;
+    if (precision == 64) {
+        switch (spins_per_lane) {
+            case 1: f(double(), integral_constant<int, 1>(), integral_constant<int, STEP_GENERAL>()); return true;
+            case 2: f(double(), integral_constant<int, 2>(), integral_constant<int, STEP_GENERAL>()); return true;
+            default: return false;
+        }
+    }
     switch (spins_per_lane) {
-        case 1: return dyn_lds_t<float, 1>(n_shape_rows, n_cache_slots);
-        case 2: return dyn_lds_t<float, 2>(n_shape_rows, n_cache_slots);
-        case 4: return dyn_lds_t<float, 4>(n_shape_rows, n_cache_slots);
-        default: return dyn_lds_t<float, 8>(n_shape_rows, n_cache_slots);
+        case 1:
+            if (variant == STEP_MATRIX_ONLY)
+                f(float(), integral_constant<int, 1>(), integral_constant<int, STEP_MATRIX_ONLY>());
+            else if (variant == STEP_VECTOR_ONLY)
+                f(float(), integral_constant<int, 1>(), integral_constant<int, STEP_VECTOR_ONLY>());
+            else
+                f(float(), integral_constant<int, 1>(), integral_constant<int, STEP_GENERAL>());
+            return true;
+        case 2: f(float(), integral_constant<int, 2>(), integral_constant<int, STEP_GENERAL>()); return true;
+        case 4: f(float(), integral_constant<int, 4>(), integral_constant<int, STEP_GENERAL>()); return true;
+        case 8: f(float(), integral_constant<int, 8>(), integral_constant<int, STEP_GENERAL>()); return true;
+        default: return false;
     }
 }
 
-int step_workgroups_per_cu(int precision, int spins_per_lane, bool matrix_only, size_t dyn_lds) {
+size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
+                          int variant) {
+    size_t out = 0;
+    // (an unsupported spins_per_lane sizes as S = 8, the largest)
+    if (!dispatch_step(precision, precision == 64 ? std::min(spins_per_lane, 2) : spins_per_lane, variant,
+                       [&](auto r, auto sc, auto vc) {
+                           out = dyn_lds_t<decltype(r), decltype(sc)::value, decltype(vc)::value>(n_shape_rows,
+                                                                                                 n_cache_slots);
+                       }))
+        out = dyn_lds_t<float, 8>(n_shape_rows, n_cache_slots);
+    return out;
+}
+
+int step_workgroups_per_cu(int precision, int spins_per_lane, int variant, size_t dyn_lds) {
     int n = 0;
-    hipError_t e;
-    if (precision != 64 && spins_per_lane == 1 && matrix_only)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 1, true>, kBlock, dyn_lds);
-    else if (precision == 64)
-        e = spins_per_lane == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, 1>, kBlock, dyn_lds)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, 2>, kBlock, dyn_lds);
-    else switch (spins_per_lane) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 1>, kBlock, dyn_lds); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 2>, kBlock, dyn_lds); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 4>, kBlock, dyn_lds); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, 8>, kBlock, dyn_lds); break;
-    }
+    hipError_t e = hipErrorInvalidValue;
+    dispatch_step(precision, precision == 64 ? std::min(spins_per_lane, 2) : spins_per_lane, variant,
+                  [&](auto r, auto sc, auto vc) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, step_kernel<decltype(r), decltype(sc)::value, decltype(vc)::value>, kBlock, dyn_lds);
+    });
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, bool matrix_only) {
+int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, int variant) {
     // FP32: keep a workgroup's LDS within half of a CU's 160 KiB so that two
     // workgroups (8 waves, the register-bound occupancy at S = 2) stay
     // resident per CU.  At S = 1 registers allow three; slots that push a
@@ -1809,69 +1835,56 @@ int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape
     // The matrix-only kernel reads its shaped-pulse rows from memory: with one
     // slot (12 KiB) it stays within a third of the CU's LDS, the three
     // workgroups per CU its registers allow.
-    size_t fixed;
-    const bool mo = precision != 64 && spins_per_lane == 1 && matrix_only;
-    if (mo) fixed = matrix_only_static_lds_bytes();
-    else if (precision == 64) fixed = spins_per_lane == 1 ? static_lds_bytes<double, 1>() : static_lds_bytes<double, 2>();
-    else switch (spins_per_lane) {
-        case 1: fixed = static_lds_bytes<float, 1>(); break;
-        case 2: fixed = static_lds_bytes<float, 2>(); break;
-        case 4: fixed = static_lds_bytes<float, 4>(); break;
-        default: fixed = static_lds_bytes<float, 8>(); break;
-    }
+    size_t fixed = static_lds_bytes<float, 8>();
+    if (precision != 64 && spins_per_lane == 1 && variant == STEP_MATRIX_ONLY)
+        fixed = matrix_only_static_lds_bytes();
+    else
+        dispatch_step(precision, spins_per_lane, variant, [&](auto r, auto sc, auto vc) {
+            fixed = static_lds_bytes<decltype(r), decltype(sc)::value, decltype(vc)::value>();
+        });
     int n = 0;
     while (n < kShapeSlots &&
-           fixed + step_dyn_lds_bytes(precision, spins_per_lane, n_shape_rows, n + 1, mo) <= kBudget)
+           fixed + step_dyn_lds_bytes(precision, spins_per_lane, n_shape_rows, n + 1, variant) <= kBudget)
         ++n;
     return n;
 }
 
-template <typename real, int S, bool MO = false>
+template <typename real, int S, int VAR = STEP_GENERAL>
 static hipError_t launch_step_t(const StepArgs& a, int64_t n_blocks, hipStream_t st) {
-    const size_t dyn = dyn_lds_t<real, S, MO>(a.n_shape_rows, a.n_cache_slots);
+    const size_t dyn = dyn_lds_t<real, S, VAR>(a.n_shape_rows, a.n_cache_slots);
     StepArgs b = a;
     b.n_tiles = n_blocks;
     if (b.n_replicas < 1) b.n_replicas = 1;
     if (b.n_whole < 0 || b.n_whole > n_blocks) return hipErrorInvalidValue;
     if (b.n_whole == n_blocks) b.n_replicas = 1;
     const int64_t grid = b.n_whole + (n_blocks - b.n_whole) * b.n_replicas;
-    hipLaunchKernelGGL((step_kernel<real, S, MO>), dim3((unsigned)grid), dim3(kBlock), dyn, st, b);
+    hipLaunchKernelGGL((step_kernel<real, S, VAR>), dim3((unsigned)grid), dim3(kBlock), dyn, st, b);
     return hipGetLastError();
 }
 
-template <typename real, int S, bool MO = false>
+template <typename real, int S, int VAR = STEP_GENERAL>
 static hipError_t launch_batch_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                                  size_t dyn, int n_cu, hipStream_t st) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S, MO>, kBlock, dyn) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S, VAR>, kBlock, dyn) !=
             hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t grid = std::min<int64_t>(total, (int64_t)per_cu * n_cu);
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((batch_step_kernel<real, S, MO>), dim3((unsigned)grid), dim3(kBlock), dyn, st, reqs, n_req,
+    hipLaunchKernelGGL((batch_step_kernel<real, S, VAR>), dim3((unsigned)grid), dim3(kBlock), dyn, st, reqs, n_req,
                        total, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                              size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st,
-                             bool matrix_only) {
-    if (precision != 64 && spins_per_lane == 1 && matrix_only)
-        return launch_batch_t<float, 1, true>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-    if (precision == 64) {
-        switch (spins_per_lane) {
-            case 1: return launch_batch_t<double, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-            case 2: return launch_batch_t<double, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (spins_per_lane) {
-        case 1: return launch_batch_t<float, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-        case 2: return launch_batch_t<float, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-        case 4: return launch_batch_t<float, 4>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-        case 8: return launch_batch_t<float, 8>(reqs, n_req, total, counter, dyn_lds, n_cu, st);
-        default: return hipErrorInvalidValue;
-    }
+                             int variant) {
+    hipError_t e = hipErrorInvalidValue;
+    dispatch_step(precision, spins_per_lane, variant, [&](auto r, auto sc, auto vc) {
+        e = launch_batch_t<decltype(r), decltype(sc)::value, decltype(vc)::value>(reqs, n_req, total, counter,
+                                                                                   dyn_lds, n_cu, st);
+    });
+    return e;
 }
 
 hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
@@ -1908,17 +1921,17 @@ hipError_t KernelNode::launch(hipStream_t st) {
     return hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, p.sharedMemBytes, st);
 }
 
-template <typename real, int S, bool MO = false>
+template <typename real, int S, int VAR = STEP_GENERAL>
 static hipError_t batch_node_t(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                                size_t dyn, int n_cu, std::vector<KernelNode>* out) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S, MO>, kBlock, dyn) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<real, S, VAR>, kBlock, dyn) !=
             hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t grid = std::min<int64_t>(total, (int64_t)per_cu * n_cu);
     if (grid <= 0) return hipSuccess;
     KernelNode k;
-    k.func = reinterpret_cast<const void*>(&batch_step_kernel<real, S, MO>);
+    k.func = reinterpret_cast<const void*>(&batch_step_kernel<real, S, VAR>);
     k.grid = dim3((unsigned)grid);
     k.block = dim3(kBlock);
     k.shmem = dyn;
@@ -1930,23 +1943,13 @@ static hipError_t batch_node_t(const BatchItem* reqs, int32_t n_req, int64_t tot
 
 hipError_t batch_step_nodes(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out,
-                            bool matrix_only) {
-    if (precision != 64 && spins_per_lane == 1 && matrix_only)
-        return batch_node_t<float, 1, true>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-    if (precision == 64) {
-        switch (spins_per_lane) {
-            case 1: return batch_node_t<double, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-            case 2: return batch_node_t<double, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (spins_per_lane) {
-        case 1: return batch_node_t<float, 1>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-        case 2: return batch_node_t<float, 2>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-        case 4: return batch_node_t<float, 4>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-        case 8: return batch_node_t<float, 8>(reqs, n_req, total, counter, dyn_lds, n_cu, out);
-        default: return hipErrorInvalidValue;
-    }
+                            int variant) {
+    hipError_t e = hipErrorInvalidValue;
+    dispatch_step(precision, spins_per_lane, variant, [&](auto r, auto sc, auto vc) {
+        e = batch_node_t<decltype(r), decltype(sc)::value, decltype(vc)::value>(reqs, n_req, total, counter, dyn_lds,
+                                                                                 n_cu, out);
+    });
+    return e;
 }
 
 hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
@@ -2129,23 +2132,13 @@ hipError_t noalloc_scratch(int device, void** ptr) {
 }
 
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
-                       hipStream_t st, bool matrix_only) {
+                       hipStream_t st, int variant) {
     if (n_blocks <= 0) return hipSuccess;
-    if (precision != 64 && spins_per_lane == 1 && matrix_only) return launch_step_t<float, 1, true>(a, n_blocks, st);
-    if (precision == 64) {
-        switch (spins_per_lane) {
-            case 1: return launch_step_t<double, 1>(a, n_blocks, st);
-            case 2: return launch_step_t<double, 2>(a, n_blocks, st);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (spins_per_lane) {
-        case 1: return launch_step_t<float, 1>(a, n_blocks, st);
-        case 2: return launch_step_t<float, 2>(a, n_blocks, st);
-        case 4: return launch_step_t<float, 4>(a, n_blocks, st);
-        case 8: return launch_step_t<float, 8>(a, n_blocks, st);
-        default: return hipErrorInvalidValue;
-    }
+    hipError_t e = hipErrorInvalidValue;
+    dispatch_step(precision, spins_per_lane, variant, [&](auto r, auto sc, auto vc) {
+        e = launch_step_t<decltype(r), decltype(sc)::value, decltype(vc)::value>(a, n_blocks, st);
+    });
+    return e;
 }
 
 int64_t row_group_size() { return kRowGroup; }

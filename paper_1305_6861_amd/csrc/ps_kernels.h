@@ -66,27 +66,43 @@ int64_t spins_per_block_of(int spins_per_lane);
 // Partial-sum rows one workgroup writes (one per wave group).
 int64_t rows_per_block_of(int spins_per_lane);
 
+// Step-kernel variants at FP32 and one spin per lane (elsewhere there is
+// only the general kernel):
+//   STEP_GENERAL      both readout paths; the matrix-core tables are built
+//                     when a readout needs them (two waves per SIMD);
+//   STEP_MATRIX_ONLY  a program whose readouts are all marked OPF_MATRIX,
+//                     none tabulated, and share one per-sample step (given
+//                     in StepArgs::mx_mu / mx_tau): built without the vector
+//                     and trajectory readouts, it builds the tables once,
+//                     before its operations, so they stay in the same
+//                     registers throughout (three waves per SIMD);
+//   STEP_VECTOR_ONLY  a program with no OPF_MATRIX readout: built without
+//                     the matrix-core readout, so its registers allow three
+//                     waves per SIMD.
+enum StepVariant : int { STEP_GENERAL = 0, STEP_MATRIX_ONLY = 1, STEP_VECTOR_ONLY = 2 };
+// The variant that runs a program (Program::matrix_only, ::any_matrix).
+inline int step_variant(int precision, int spins_per_lane, bool matrix_only, bool any_matrix) {
+    if (precision == 64 || spins_per_lane != 1) return STEP_GENERAL;
+    return matrix_only ? STEP_MATRIX_ONLY : any_matrix ? STEP_GENERAL : STEP_VECTOR_ONLY;
+}
+
 // Launches a.n_whole + (n_blocks - a.n_whole) * a.n_replicas workgroups:
 // the first n_whole tiles whole, every later tile once per readout replica
-// (replicas split the slice's readouts).
-// matrix_only (a program whose readouts are all marked OPF_MATRIX, none
-// tabulated, and share one per-sample step, given in a.mx_mu / a.mx_tau)
-// selects, at FP32 and one spin per lane, a kernel built without the vector
-// and trajectory readouts that builds the matrix-core tables once, before
-// its operations, so they stay in the same registers throughout; elsewhere
-// it is ignored.
+// (replicas split the slice's readouts), with the kernel variant given
+// (step_variant; ignored where only the general kernel exists).
 hipError_t launch_step(const StepArgs& a, int precision, int spins_per_lane, int64_t n_blocks,
-                       hipStream_t st, bool matrix_only = false);
+                       hipStream_t st, int variant = STEP_GENERAL);
 // Dynamic LDS of a step workgroup: shaped-pulse rows (not in the
-// matrix-only kernel, see launch_step) and propagator slots.
+// matrix-only kernel, which reads them through the scalar cache) and
+// propagator slots.
 size_t step_dyn_lds_bytes(int precision, int spins_per_lane, int32_t n_shape_rows, int32_t n_cache_slots,
-                          bool matrix_only = false);
+                          int variant = STEP_GENERAL);
 // Step workgroups resident per CU (occupancy of the kernel the arguments
 // select, with dyn_lds bytes of dynamic LDS).
-int step_workgroups_per_cu(int precision, int spins_per_lane, bool matrix_only, size_t dyn_lds);
+int step_workgroups_per_cu(int precision, int spins_per_lane, int variant, size_t dyn_lds);
 // Propagator slots (at most kShapeSlots) that fit a step workgroup's LDS
 // budget next to n_shape_rows shaped-pulse rows.
-int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, bool matrix_only = false);
+int shape_cache_slots_fitting(int precision, int spins_per_lane, int32_t n_shape_rows, int variant = STEP_GENERAL);
 // Finalize pass 1: each thread sums kFinVals consecutive values, so partial
 // rows and the coil blocks inside them are padded to a multiple of kFinVals
 // values; finalize_tiles(n) workgroups of 256 threads cover n values.
@@ -104,7 +120,7 @@ hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t st);
 // step_dyn_lds_bytes.
 hipError_t launch_batch_step(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                              size_t dyn_lds, int precision, int spins_per_lane, int n_cu, hipStream_t st,
-                             bool matrix_only = false);
+                             int variant = STEP_GENERAL);
 hipError_t launch_batch_finalize(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
                                  hipStream_t st);
 
@@ -128,7 +144,7 @@ struct KernelNode {
 // nodes appended to *out (none when there is nothing to run).
 hipError_t batch_step_nodes(const BatchItem* reqs, int32_t n_req, int64_t total, unsigned long long* counter,
                             size_t dyn_lds, int precision, int spins_per_lane, int n_cu, std::vector<KernelNode>* out,
-                            bool matrix_only = false);
+                            int variant = STEP_GENERAL);
 hipError_t batch_finalize_nodes(const FinDesc* d, int32_t n, int64_t tiles1, int64_t tiles2, int precision,
                                 std::vector<KernelNode>* out);
 int64_t row_group_size();
