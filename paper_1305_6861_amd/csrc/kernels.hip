@@ -696,9 +696,16 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
     for (int tile = 0; tile < n_tiles; ++tile) {
         if (tile % kMatrixReanchor == 0) {
             // value at sample s0 from the anchors, as in the vector path
-            const double s0 = (double)tile * kMatrixTile;
-            const double t = uniform(op.txy) + s0 * tau;
-            const double k[3] = {op.k[0] + s0 * mu[0], op.k[1] + s0 * mu[1], op.k[2] + s0 * mu[2]};
+            // (at s0 = 0 the moment and time are the operation's own, exactly)
+            double t = uniform(op.txy);
+            double k[3] = {uniform(op.k[0]), uniform(op.k[1]), uniform(op.k[2])};
+            if (tile > 0) {
+                const double s0 = (double)(tile * kMatrixTile);
+                t += s0 * tau;
+                k[0] += s0 * mu[0];
+                k[1] += s0 * mu[1];
+                k[2] += s0 * mu[2];
+            }
             const float e2 = e2_of<float, 1, C>(sp, 0, t, dc);
             float co, sn;
             Math<float>::cis(phase_rev(k, t, sp.x[0], sp.y[0], sp.z[0], sp.dw[0]), co, sn);
