@@ -415,19 +415,21 @@ __device__ __forceinline__ double phase_rev(const double* k, double t, float x, 
 // formed for (the matrix-only kernel, one spin per lane): a sequence that
 // repeats its timing (every repetition of a Cartesian scan) forms them once.
 // A kept factor is the one the same computation gives, so results do not
-// change.
+// change.  The keys are the times' bit patterns, compared on the scalar unit
+// (it has no FP64 compare).
 template <bool On> struct DecayCache {};
 template <> struct DecayCache<true> {
-    double t1_time = -1.0, t2_time = -1.0;   // wave-uniform keys (times are >= 0)
-    float d1 = 0.0f, e2 = 0.0f;              // 1 - exp(-t1_time / T1), exp(-t2_time / T2)
+    uint64_t t1_key = ~0ull, t2_key = ~0ull;  // bit patterns of wave-uniform times (a NaN: no time yet)
+    float d1 = 0.0f, e2 = 0.0f;              // 1 - exp(-t1 / T1), exp(-t2 / T2) for those times
 };
 
 template <typename real, int S, bool C>
 __device__ __forceinline__ real one_minus_e1(const Spins<real, S>& sp, int s, double t, DecayCache<C>* dc) {
     if constexpr (C) {
-        if (t != dc->t1_time) {
+        const uint64_t key = (uint64_t)__double_as_longlong(t);
+        if (key != dc->t1_key) {
             dc->d1 = Math<real>::one_minus_expneg(t, sp.r1[s]);
-            dc->t1_time = t;
+            dc->t1_key = key;
         }
         return dc->d1;
     } else {
@@ -438,9 +440,10 @@ __device__ __forceinline__ real one_minus_e1(const Spins<real, S>& sp, int s, do
 template <typename real, int S, bool C>
 __device__ __forceinline__ real e2_of(const Spins<real, S>& sp, int s, double t, DecayCache<C>* dc) {
     if constexpr (C) {
-        if (t != dc->t2_time) {
+        const uint64_t key = (uint64_t)__double_as_longlong(t);
+        if (key != dc->t2_key) {
             dc->e2 = Math<real>::expneg(t, sp.r2[s]);
-            dc->t2_time = t;
+            dc->t2_key = key;
         }
         return dc->e2;
     } else {
@@ -739,20 +742,21 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
             s_a[(r0 + 1) * 32 + (col ^ (4 * ((r0 + 1) & 7)))] = im;
             s_a[(r0 + 2) * 32 + (col ^ (4 * ((r0 + 2) & 7)))] = nim;
         }
-        // all eight operand reads in flight before the first product, so
-        // that no LDS latency sits between the matrix-core instructions
+        // the eight operand reads (the compiler issues each just before its
+        // four products at this register budget; holding more in flight
+        // measured no faster), then one accumulation chain of 32 products
         float4 av[8];
         static_for<0, 8>([&](auto gc) {
             constexpr int g = decltype(gc)::value;
             av[g] = *reinterpret_cast<const float4*>(a_src + ((4 * g) ^ a_swz));
         });
-        floatx4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         static_for<0, 8>([&](auto gc) {
             constexpr int g = decltype(gc)::value;
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].x, mt.bq[4 * g + 0], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].y, mt.bq[4 * g + 1], acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].z, mt.bq[4 * g + 2], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].w, mt.bq[4 * g + 3], acc1, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].x, mt.bq[4 * g + 0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].y, mt.bq[4 * g + 1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].z, mt.bq[4 * g + 2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].w, mt.bq[4 * g + 3], acc, 0, 0, 0);
         });
         // lane l holds rows 4 (l >> 4) + r (r = 0 .. 3) of column l & 15;
         // two buffers for alternate tiles: a wave that writes buffer tb here
@@ -760,7 +764,7 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
         // earlier contents had reached after reading it
         const int tb = m_pass++ & 1;
         s_md[(tb * kWaves + wave) * 64 + lane] =
-            make_float4(acc0[0] + acc1[0], acc0[1] + acc1[1], acc0[2] + acc1[2], acc0[3] + acc1[3]);
+            make_float4(acc[0], acc[1], acc[2], acc[3]);
         __syncthreads();
         // waves 0 and 1, lane l: elements (2 h, 2 h + 1) of lane l with
         // h = wave, i.e. (re, im) of sample 16 (2 (l >> 4) + h) + (l & 15),
