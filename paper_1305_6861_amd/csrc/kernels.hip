@@ -645,8 +645,10 @@ __device__ __forceinline__ void matrix_tables(const Spins<float, 1>& sp, const d
     const int j = lane & 15;                 // B: sample inside the block
     const int c = (lane >> 4) & 1;           // contraction slot: component of the spin
     const int half = lane >> 5;
+    // the per-sample phase of the lane's own spin (FP64); the B operand takes
+    // the other spins' from their lanes
+    const double ph = phase_rev(mu, tau, sp.x[0], sp.y[0], sp.z[0], sp.dw[0]);
     {
-        const double ph = phase_rev(mu, tau, sp.x[0], sp.y[0], sp.z[0], sp.dw[0]);
         auto power = [&](double e, float& re, float& im) {   // z^e of the lane's own spin
             float co, sn;
             Math<float>::cis(ph * e, co, sn);
@@ -663,11 +665,9 @@ __device__ __forceinline__ void matrix_tables(const Spins<float, 1>& sp, const d
     static_for<0, 32>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const int src = q + 32 * half;
-        const float x = __shfl(sp.x[0], src), y = __shfl(sp.y[0], src), z = __shfl(sp.z[0], src),
-                    dw = __shfl(sp.dw[0], src);
-        const double r2 = __shfl(sp.r2[0], src);
+        const double ph_q = __shfl(ph, src), r2 = __shfl(sp.r2[0], src);
         float co, sn;
-        Math<float>::cis(phase_rev(mu, tau, x, y, z, dw) * (double)j, co, sn);
+        Math<float>::cis(ph_q * (double)j, co, sn);
         const float e = Math<float>::expneg(tau * (double)j, r2);
         mt.bq[q] = c == 0 ? e * co : -e * sn;           // component c of z^j
     });
