@@ -492,8 +492,11 @@ ps_status ps_tile(ps_ctx *ctx, int64_t n_spins, int32_t *spins_per_lane, int64_t
  * the rule gives replicas.  Each is timed on a probe -- the request's object
  * with the longest prefix of its sequence of about 6e10 spin-steps (at least
  * through its first readout; the whole sequence when shorter) -- by the
- * device time of its kernels: one warm-up and three timed runs, median.  The
- * threshold rule's tiling is kept unless a candidate is more than 3 % faster.
+ * device time of its kernels, in rounds over all candidates (one warm-up
+ * round, then five timed rounds; median of each candidate's five).  The
+ * threshold rule's tiling is kept unless a candidate is more than 3 % faster
+ * (15 % for another spins-per-lane value, which costs batched rounds a
+ * kernel class of their own).
  * The result of a request depends on its tiling (bitwise; within the FP32
  * tolerance across tilings), so a request run after its class was tuned may
  * differ in the last bits from one run before. */

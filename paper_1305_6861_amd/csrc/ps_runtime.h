@@ -162,7 +162,7 @@ int replicas_for_load(const Ctx* ctx, int64_t n_tiles, ReplicaBound bound, int32
 // `replicas` readout replicas each (replicas_for_load's count with
 // n_whole = 0 when that is above one; else the tiles past the last whole
 // round of slots, the workgroups the device holds at once, split over the
-// slots that round leaves free).
+// slots that round leaves free, when there are at most four whole rounds).
 struct ReplicaSplit {
     int replicas = 1;
     int64_t n_whole = 0;
