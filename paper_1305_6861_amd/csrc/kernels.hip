@@ -1717,13 +1717,30 @@ __global__ void finalize_rows_kernel(const real* __restrict__ partial, int64_t n
     sum_rows(partial, r0, r1, row_stride, j, n_vals, out + (int64_t)blockIdx.y * n_vals);
 }
 
+// Sum of the group sums of value j in group order; eight groups' loads in
+// flight before their adds (a thread per value leaves few workgroups, so
+// each must keep several loads outstanding).
+template <typename P>
+__device__ __forceinline__ double sum_groups(P mid, int64_t n_groups, int64_t n_vals, int64_t j) {
+    constexpr int kU = 8;
+    double s = 0.0;
+    int64_t g = 0;
+    for (; g + kU <= n_groups; g += kU) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = mid[(g + u) * n_vals + j];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) s += v[u];
+    }
+    for (; g < n_groups; ++g) s += mid[g * n_vals + j];
+    return s;
+}
+
 __global__ void finalize_groups_kernel(const double* __restrict__ mid, int64_t n_groups, int64_t n_vals,
                                        double* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_vals) return;
-    double s = 0.0;
-    for (int64_t g = 0; g < n_groups; ++g) s += mid[g * n_vals + j];
-    out[j] = s;
+    out[j] = sum_groups(mid, n_groups, n_vals, j);
 }
 
 // Batched finalize: pass 1 over (request, row group, value tile), pass 2
@@ -1756,10 +1773,7 @@ __global__ void batch_finalize_pass2(const FinDesc* __restrict__ d, int32_t n) {
     const FinDesc& f = d[find_desc(d, n, t, true)];
     const int64_t j = (t - f.tile_begin2) * 256 + threadIdx.x;
     if (f.n_groups <= 1 || j >= f.n_vals) return;
-    const auto mid = gmem(f.mid);
-    double s = 0.0;
-    for (int64_t g = 0; g < f.n_groups; ++g) s += mid[g * f.n_vals + j];
-    gmem(f.out)[j] = s;
+    gmem(f.out)[j] = sum_groups(gmem(f.mid), f.n_groups, f.n_vals, j);
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ out, int64_t n) {
