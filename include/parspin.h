@@ -495,8 +495,9 @@ ps_status ps_tile(ps_ctx *ctx, int64_t n_spins, int32_t *spins_per_lane, int64_t
  * device time of its kernels, in rounds over all candidates (one warm-up
  * round, then five timed rounds; median of each candidate's five).  The
  * threshold rule's tiling is kept unless a candidate is more than 3 % faster
- * (15 % for another spins-per-lane value, which costs batched rounds a
- * kernel class of their own).
+ * (for a request whose probe takes under 1 ms, 15 % for another
+ * spins-per-lane value: such requests share batched rounds, which run one
+ * kernel per spins-per-lane class).
  * The result of a request depends on its tiling (bitwise; within the FP32
  * tolerance across tilings), so a request run after its class was tuned may
  * differ in the last bits from one run before. */

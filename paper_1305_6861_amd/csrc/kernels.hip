@@ -51,8 +51,8 @@
 // spin's eight a_b = m z^(16 b) and stores them (Re, Im, -Im: the three
 // entries the real form of a complex product needs) in the wave's LDS tile,
 // from which the A operands are read four MFMAs at a time.  The waves'
-// 16 x 16 results are added in LDS in wave order, and one row per workgroup
-// is written, as in the vector path.
+// 16 x 16 results are added in LDS in wave order (two tiles of a readout per
+// barrier), and one row per workgroup is written, as in the vector path.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -528,7 +528,7 @@ constexpr size_t static_lds_bytes() {
     // the matrix-core arrays exist only where that readout does (the
     // compiler drops the placeholders of the other kernels)
     constexpr size_t matrix = MatrixReadout<real, S, VAR>::on
-                                  ? sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64
+                                  ? sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 4 * kWaves * 64
                                   : 0;
     return sizeof(Op) * kOpChunk + sizeof(real) * 2 * (G > 1 ? kWaves : 1) * (G > 1 ? S : 1) * 64 * 2 +
            sizeof(real) * S * NF * kBlock + sizeof(real) * (G > 1 ? kWaves : 1) * 64 + matrix;
@@ -678,7 +678,8 @@ __device__ __forceinline__ void matrix_tables(const Spins<float, 1>& sp, const d
 // each tile from an FP64 phase every kMatrixReanchor tiles and is stepped by
 // z^128 in between.  s_a is the wave's A-operand tile; out points at the
 // coil's first sample of this operation in the workgroup's row (2 reals per
-// sample).  Every wave of the workgroup takes part (one barrier per tile).
+// sample).  Every wave of the workgroup takes part (one barrier per tile,
+// or per pair of tiles inside the readout).
 constexpr int kMatrixReanchor = 8;
 
 template <bool C>
@@ -758,20 +759,44 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].z, mt.bq[4 * g + 2], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].w, mt.bq[4 * g + 3], acc, 0, 0, 0);
         });
-        // lane l holds rows 4 (l >> 4) + r (r = 0 .. 3) of column l & 15;
-        // two buffers for alternate tiles: a wave that writes buffer tb here
-        // has passed the previous tile's barrier, which every reader of tb's
-        // earlier contents had reached after reading it
-        const int tb = m_pass++ & 1;
-        s_md[(tb * kWaves + wave) * 64 + lane] =
-            make_float4(acc[0], acc[1], acc[2], acc[3]);
+        // lane l holds rows 4 (l >> 4) + r (r = 0 .. 3) of column l & 15,
+        // i.e. (re, im) of samples 32 (l >> 4) + (l & 15) and 16 more.  The
+        // results go to a ring of four slots; the first tile of a pair inside
+        // the readout waits for the second's barrier, after which wave 0
+        // sums the first and wave 1 the second.  Barriers come at least
+        // every two tiles, so a slot is written again only after a barrier
+        // that its readers reached once they had read it.
+        const int slot = m_pass % 4;
+        ++m_pass;
+        s_md[(slot * kWaves + wave) * 64 + lane] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        const bool first_of_pair = (tile & 1) == 0 && tile + 1 < n_tiles;
+        if (first_of_pair) continue;
         __syncthreads();
-        // waves 0 and 1, lane l: elements (2 h, 2 h + 1) of lane l with
-        // h = wave, i.e. (re, im) of sample 16 (2 (l >> 4) + h) + (l & 15),
-        // added over the waves in wave order and stored as one pair, so that
-        // 16 consecutive lanes write 128 contiguous bytes
-        if (wave < 2) {
-            const float2* md = reinterpret_cast<const float2*>(s_md + tb * kWaves * 64);
+        auto store_tile = [&](int sl, int t) {
+            const float4* md = s_md + sl * kWaves * 64;
+            float4 v = md[lane];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) {
+                const float4 u = md[w * 64 + lane];
+                v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+            }
+            const int smp = t * kMatrixTile + 32 * (lane >> 4) + (lane & 15);
+            if (smp < n) {
+                out[2 * (int64_t)smp] = v.x;
+                out[2 * (int64_t)smp + 1] = v.y;
+            }
+            if (smp + 16 < n) {
+                out[2 * (int64_t)(smp + 16)] = v.z;
+                out[2 * (int64_t)(smp + 16) + 1] = v.w;
+            }
+        };
+        if ((tile & 1) == 1) {
+            // a pair: the first tile in the previous slot
+            if (wave == 0) store_tile((slot + 3) % 4, tile - 1);
+            else if (wave == 1) store_tile(slot, tile);
+        } else if (wave < 2) {
+            // a single last tile: waves 0 and 1 each store one of its halves
+            const float2* md = reinterpret_cast<const float2*>(s_md + slot * kWaves * 64);
             float2 v = md[lane * 2 + wave];
 #pragma unroll
             for (int w = 1; w < kWaves; ++w) {
@@ -818,13 +843,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
     __shared__ __align__(16) real s_stepf[S][NF / V][kBlock][V];
     __shared__ real s_red[G > 1 ? kWaves : 1][64];   // chunk sums of waves sharing a chunk
     // matrix-core readout: each wave's A-operand tile, and the waves'
-    // 16 x 16 results of a tile, in two buffers used by alternate tiles
+    // 16 x 16 results of a tile, in a ring of four slots (see matrix_readout)
     constexpr bool kMatrix = MatrixReadout<real, S, VAR>::on;
     static_assert(!MO || kMatrix, "the matrix-only kernel is FP32 at one spin per lane");
     constexpr int LW = MatrixReadout<real, S, VAR>::LW;
     constexpr int LR = kMatrix ? kMatrixARows * 32 : 1;
     __shared__ __align__(16) float s_ta[LW][LR];
-    __shared__ __align__(16) float4 s_md[2][LW][64];
+    __shared__ __align__(16) float4 s_md[4][LW][64];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     // shaped-pulse deltas, FP64: staged in LDS, except in the matrix-only
     // kernel, which reads them (wave-uniform) through the scalar cache and
@@ -1794,7 +1819,7 @@ static size_t dyn_lds_t(int32_t n_shape_rows, int32_t n_cache_slots) {
 // (it reads its operations through the scalar cache, and the vector path's
 // arrays are not in it).
 constexpr size_t matrix_only_static_lds_bytes() {
-    return sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 2 * kWaves * 64;
+    return sizeof(float) * kWaves * kMatrixARows * 32 + sizeof(float4) * 4 * kWaves * 64;
 }
 
 // Calls f(real_tag, S_tag, V_tag) for the kernel instance the arguments

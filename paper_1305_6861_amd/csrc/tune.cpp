@@ -41,6 +41,9 @@ namespace ps {
 
 // Timed rounds over the candidates (after one warm-up round).
 constexpr int kTimedRounds = 5;
+// Probes shorter than this (ms) belong to requests small enough to share
+// batched rounds with others.
+constexpr double kShortProbeMs = 1.0;
 
 static int floor_log2(int64_t v) {
     int r = -1;
@@ -232,18 +235,19 @@ static ps_status tune_request(Ctx* ctx, const ps_object* obj, const ps_sequence*
     signal.release();
     if (st != PS_OK) return st;
 
-    // the rule's tiling is kept unless a candidate beats it by more than 3 %,
-    // or by more than 15 % for another spins-per-lane value: batched and
-    // served rounds launch one kernel per spins-per-lane class, so a class
-    // moved off the rule's value can cost a batch a launch of its own that
-    // the probe of one request does not see (c4: two classes moved, 12 %
-    // faster alone, made the batch 17 % slower)
+    // the rule's tiling is kept unless a candidate beats it by more than 3 %;
+    // a small request (probe under kShortProbeMs) needs 15 % to move to
+    // another spins-per-lane value: batched and served rounds run one
+    // kernel per spins-per-lane class, one after another, so a small class
+    // moved off the rule's value stops sharing a persistent kernel with the
+    // others, which the probe of one request does not see (c4: two classes
+    // moved, each 12-13 % faster alone, made the batch 17 % slower)
     size_t rule_c = 0;
     for (size_t c = 0; c < cands.size(); ++c)
         if (cands[c].S == rule_S && cands[c].replicas == base_rep) rule_c = c;
     size_t best = rule_c;
     for (size_t c = 0; c < cands.size(); ++c) {
-        const double need = cands[c].S == rule_S ? 0.97 : 0.85;
+        const double need = cands[c].S == rule_S || ms[rule_c] >= kShortProbeMs ? 0.97 : 0.85;
         if (ms[c] < need * ms[rule_c] && ms[c] < ms[best]) best = c;
     }
     TuneEntry ent;
