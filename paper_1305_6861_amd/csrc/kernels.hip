@@ -94,6 +94,15 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// A value of a partial-sum row: each is written once and read once, by the
+// finalize after the whole launch, so the store is nontemporal (a slice's
+// rows are far larger than the caches and would only displace what the
+// step kernel reads again).
+template <typename T, typename V>
+__device__ __forceinline__ void put_partial(__attribute__((address_space(1))) T* p, V v) {
+    __builtin_nontemporal_store((T)v, p);
+}
+
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 
@@ -782,12 +791,12 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
             }
             const int smp = t * kMatrixTile + 32 * (lane >> 4) + (lane & 15);
             if (smp < n) {
-                out[2 * (int64_t)smp] = v.x;
-                out[2 * (int64_t)smp + 1] = v.y;
+                put_partial(out + 2 * (int64_t)smp, v.x);
+                put_partial(out + 2 * (int64_t)smp + 1, v.y);
             }
             if (smp + 16 < n) {
-                out[2 * (int64_t)(smp + 16)] = v.z;
-                out[2 * (int64_t)(smp + 16) + 1] = v.w;
+                put_partial(out + 2 * (int64_t)(smp + 16), v.z);
+                put_partial(out + 2 * (int64_t)(smp + 16) + 1, v.w);
             }
         };
         if ((tile & 1) == 1) {
@@ -806,8 +815,8 @@ __device__ __forceinline__ void matrix_readout(const Spins<float, 1>& sp, const 
             }
             const int smp = tile * kMatrixTile + 32 * (lane >> 4) + 16 * wave + (lane & 15);
             if (smp < n) {
-                out[2 * (int64_t)smp] = v.x;
-                out[2 * (int64_t)smp + 1] = v.y;
+                put_partial(out + 2 * (int64_t)smp, v.x);
+                put_partial(out + 2 * (int64_t)smp + 1, v.y);
             }
         }
     }
@@ -1233,7 +1242,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                             }
                             const float v = reduce16(red16, lane);
                             if (j * kT + smp_lane < n)
-                                partial_c[2 * (int64_t)(aux + j * kT + smp_lane) + (lane & 1)] = v;
+                                put_partial(partial_c + 2 * (int64_t)(aux + j * kT + smp_lane) + (lane & 1), v);
                         }
                         continue;
                     }
@@ -1324,7 +1333,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                             }
                         }
                         if (wg == 0 && j * kT + smp_lane < n)
-                            partial_c[2 * (int64_t)(aux + j * kT + smp_lane) + (lane & 1)] = v;
+                            put_partial(partial_c + 2 * (int64_t)(aux + j * kT + smp_lane) + (lane & 1), v);
                     }
                 }
                 __syncthreads();                     // the staging area is free again
@@ -1581,7 +1590,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int64_t blk, 
                                 for (int k = 1; k < P; ++k) v += s_red[wave + k][lane];
                         }
                         if (sub == 0 && j * kT + smp_of_lane < n)
-                            partial_c[2 * (int64_t)(aux + j * kT + smp_of_lane) + (lane & 1)] = v;
+                            put_partial(partial_c + 2 * (int64_t)(aux + j * kT + smp_of_lane) + (lane & 1), v);
                     }
                 };
                 if (__builtin_expect(n_share == 1, 1)) {
@@ -1692,14 +1701,18 @@ constexpr int64_t kRowGroup = 64;
 // row_stride and every coil block to a multiple of kFinVals values, so the
 // loads are aligned and stay inside the rows (values past n_vals in the
 // padding are read but never stored).  Each value is still summed over the
-// rows in row order.
+// rows in row order.  The partial rows are read once, so the loads are
+// nontemporal, as are the step kernels' stores of them (put_partial).
 
 __device__ __forceinline__ void load_fin(const float* p, double (&v)[kFinVals]) {
-    const float4 q = *reinterpret_cast<const float4*>(p);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 q = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
     v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
 }
 __device__ __forceinline__ void load_fin(const double* p, double (&v)[kFinVals]) {
-    const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 a = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p) + 1);
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
